@@ -1,0 +1,236 @@
+"""CPU oracle for PG-SGD layout — TEST INFRASTRUCTURE ONLY.
+
+Plain single-threaded C (``oracle.c``, built with gcc into ``liboracle.so``)
+written from the paper: the layout loop of Alg. 1, the path stress of Eq. 1
+and the sampled path stress of Eq. 2 with its 95% confidence interval.  It
+shares no code with the GPU library.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product path never
+does.
+
+Every function states the passage it follows; see ``oracle.c`` for the
+readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# Compiled without FMA contraction or fast-math so each FP64 expression is
+# evaluated exactly as written.
+CFLAGS = ["-O2", "-fPIC", "-shared", "-std=gnu11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-pthread"]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.check_call(["gcc", *CFLAGS, "-o", _LIB_PATH, _SRC, "-lm"])
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    u32, u64, f64, f32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_float
+    sig = {
+        "or_philox4x32_10": ([P, P, P], None),
+        "or_zipf_table": ([f64, u32, P], None),
+        "or_zipf_draw": ([P, u32, u32], u32),
+        "or_schedule": ([u32, f64, f64, P], None),
+        "or_graph_new": ([u32, P, u32, P, P], P),
+        "or_graph_free": ([P], None),
+        "or_graph_pos": ([P], P),
+        "or_graph_path_nt": ([P], P),
+        "or_graph_d_max": ([P], ctypes.c_int64),
+        "or_endpoint_pos": ([P, u64, u32], ctypes.c_int64),
+        "or_sample_terms": ([P, u32, f64, u32, u64, u32, u32, u64, u64, P, P, P], None),
+        "or_layout": ([P, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
+        "or_layout_threaded": ([P, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P, u32, u64], u64),
+        "or_apply_terms_f64": ([P, f64, P, P, P, u64, P], u64),
+        "or_apply_terms_f32": ([P, f64, P, P, P, u64, P], u64),
+        "or_sampled_path_stress": ([P, P, u32, u64, u32, P, P], None),
+        "or_sps_expectation": ([P, P, P], None),
+        "or_path_stress_exact": ([P, P, P], None),
+        "or_init_coords": ([P, u64, u32, f32, P], None),
+        "or_stress_loss_grad": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+# ---------------------------------------------------------------------------
+# Counter-based random numbers (Philox4x32-10, Salmon et al. SC'11)
+# ---------------------------------------------------------------------------
+def philox(counter, key) -> np.ndarray:
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def zipf_table(theta: float = 0.99, window: int = 1000) -> np.ndarray:
+    C = np.zeros(window + 1, dtype=np.uint32)
+    _load().or_zipf_table(float(theta), int(window), _p(C))
+    return C
+
+
+def zipf_draw(C: np.ndarray, n: int, r: int) -> int:
+    C = np.ascontiguousarray(C, dtype=np.uint32)
+    return int(_load().or_zipf_draw(_p(C), int(n), int(r)))
+
+
+def schedule(n_iters: int, eta_max: float, eta_min: float = 0.01) -> np.ndarray:
+    eta = np.zeros(max(1, n_iters), dtype=np.float64)
+    _load().or_schedule(int(n_iters), float(eta_max), float(eta_min), _p(eta))
+    return eta[:n_iters]
+
+
+# ---------------------------------------------------------------------------
+# Graph + layout (Alg. 1)
+# ---------------------------------------------------------------------------
+class Graph:
+    """Oracle view of a variation graph: node lengths and path step lists."""
+
+    def __init__(self, node_len, path_off, step_node):
+        self.node_len = np.ascontiguousarray(node_len, dtype=np.uint32)
+        self.path_off = np.ascontiguousarray(path_off, dtype=np.uint64)
+        self.step_node = np.ascontiguousarray(step_node, dtype=np.uint32)
+        self.n_nodes = int(self.node_len.shape[0])
+        self.n_paths = int(self.path_off.shape[0]) - 1
+        self.S = int(self.path_off[-1])
+        self._h = _load().or_graph_new(self.n_nodes, _p(self.node_len), self.n_paths, _p(self.path_off),
+                                       _p(self.step_node))
+
+    @classmethod
+    def from_synth(cls, sg):
+        return cls(sg.node_len, sg.path_off, sg.step_node)
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _lib is not None:
+            _lib.or_graph_free(h)
+
+    @property
+    def pos(self) -> np.ndarray:
+        addr = _load().or_graph_pos(self._h)
+        return np.ctypeslib.as_array(ctypes.cast(addr, ctypes.POINTER(ctypes.c_int64)), shape=(max(1, self.S),))[
+            : self.S].copy()
+
+    @property
+    def path_nt(self) -> np.ndarray:
+        addr = _load().or_graph_path_nt(self._h)
+        return np.ctypeslib.as_array(ctypes.cast(addr, ctypes.POINTER(ctypes.c_int64)),
+                                     shape=(max(1, self.n_paths),))[: self.n_paths].copy()
+
+    @property
+    def d_max(self) -> int:
+        return int(_load().or_graph_d_max(self._h))
+
+    def endpoint_pos(self, s: int, e: int) -> int:
+        return int(_load().or_endpoint_pos(self._h, int(s), int(e)))
+
+
+DEFAULTS = dict(n_iters=30, terms_per_step=10, eta_max=0.0, eta_min=0.01, theta=0.99, window=1000, seed=24301,
+                graph_id=0)
+
+
+def sample_terms(g: Graph, iter: int, t_begin: int, count: int, n_iters=30, theta=0.99, window=1000, seed=24301,
+                 graph_id=0):
+    i = np.zeros(count, dtype=np.uint64)
+    j = np.zeros(count, dtype=np.uint64)
+    f = np.zeros(count, dtype=np.uint8)
+    _load().or_sample_terms(g._h, int(n_iters), float(theta), int(window), int(seed), int(graph_id), int(iter),
+                            int(t_begin), int(count), _p(i), _p(j), _p(f))
+    return i, j, f
+
+
+def layout(g: Graph, coords: np.ndarray, n_iters=30, terms_per_step=10, eta_max=0.0, eta_min=0.01, theta=0.99,
+           window=1000, seed=24301, graph_id=0, first_iter=0, last_iter=0, threads=1, term_limit=0) -> int:
+    """Runs Alg. 1 in place on float32 coords [2][n_nodes][2]; returns applied updates."""
+    assert coords.dtype == np.float32 and coords.flags.c_contiguous and coords.size == 4 * g.n_nodes
+    L = _load()
+    if threads <= 1 and term_limit == 0:
+        return int(L.or_layout(g._h, int(n_iters), int(terms_per_step), float(eta_max), float(eta_min),
+                               float(theta), int(window), int(seed), int(graph_id), int(first_iter),
+                               int(last_iter), _p(coords)))
+    return int(L.or_layout_threaded(g._h, int(n_iters), int(terms_per_step), float(eta_max), float(eta_min),
+                                    float(theta), int(window), int(seed), int(graph_id), int(first_iter),
+                                    int(last_iter), _p(coords), int(threads), int(term_limit)))
+
+
+def apply_terms_f64(g: Graph, eta: float, i, j, flags, coords64: np.ndarray) -> int:
+    assert coords64.dtype == np.float64 and coords64.flags.c_contiguous
+    i = np.ascontiguousarray(i, dtype=np.uint64)
+    j = np.ascontiguousarray(j, dtype=np.uint64)
+    flags = np.ascontiguousarray(flags, dtype=np.uint8)
+    return int(_load().or_apply_terms_f64(g._h, float(eta), _p(i), _p(j), _p(flags), len(i), _p(coords64)))
+
+
+def apply_terms_f32(g: Graph, eta: float, i, j, flags, coords: np.ndarray) -> int:
+    assert coords.dtype == np.float32 and coords.flags.c_contiguous
+    i = np.ascontiguousarray(i, dtype=np.uint64)
+    j = np.ascontiguousarray(j, dtype=np.uint64)
+    flags = np.ascontiguousarray(flags, dtype=np.uint8)
+    return int(_load().or_apply_terms_f32(g._h, float(eta), _p(i), _p(j), _p(flags), len(i), _p(coords)))
+
+
+# ---------------------------------------------------------------------------
+# Metrics (Eq. 1, Eq. 2)
+# ---------------------------------------------------------------------------
+def sampled_path_stress(g: Graph, coords: np.ndarray, m: int = 100, seed: int = 7, graph_id: int = 0) -> dict:
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    out = np.zeros(6, dtype=np.float64)
+    cnt = np.zeros(2, dtype=np.uint64)
+    _load().or_sampled_path_stress(g._h, _p(coords), int(m), int(seed), int(graph_id), _p(out), _p(cnt))
+    return dict(mean=out[0], ci_lo=out[1], ci_hi=out[2], stddev=out[3], sum=out[4], sumsq_dev=out[5],
+                n_valid=int(cnt[0]), n_skipped=int(cnt[1]))
+
+
+def sps_expectation(g: Graph, coords: np.ndarray):
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    out = np.zeros(2, dtype=np.float64)
+    _load().or_sps_expectation(g._h, _p(coords), _p(out))
+    return float(out[0]), float(out[1])
+
+
+def path_stress_exact(g: Graph, coords: np.ndarray):
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    out = np.zeros(2, dtype=np.float64)
+    _load().or_path_stress_exact(g._h, _p(coords), _p(out))
+    return float(out[0]), int(out[1])
+
+
+def init_coords(g: Graph, seed: int = 5, jitter: float = 10.0, graph_id: int = 0) -> np.ndarray:
+    coords = np.zeros(4 * g.n_nodes, dtype=np.float32)
+    _load().or_init_coords(g._h, int(seed), int(graph_id), float(jitter), _p(coords))
+    return coords
+
+
+def stress_loss_grad(g: Graph, coords: np.ndarray, n_pairs: int, seed: int = 11, step: int = 0, theta=0.99,
+                     window=1000, graph_id=0, want_grad=True):
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    out = np.zeros(2, dtype=np.float64)
+    grad = np.zeros(4 * g.n_nodes, dtype=np.float64) if want_grad else None
+    _load().or_stress_loss_grad(g._h, _p(coords), int(n_pairs), float(theta), int(window), int(seed),
+                                int(graph_id), int(step), _p(out), _p(grad))
+    return float(out[0]), int(out[1]), grad

@@ -1,0 +1,650 @@
+/*
+ * CPU oracle for PG-SGD pangenome graph layout — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded reference of what the GPU library computes,
+ * written from the paper ("Rapid GPU-Based Pangenome Graph Layout", SC24):
+ *   - the layout loop of Alg. 1 (Section "Path-Guided SGD Algorithm"),
+ *   - the path stress of Eq. 1 and the sampled path stress of Eq. 2 with its
+ *     95% confidence interval (Section "A Quantitative Metric for Pangenome
+ *     Layouts"),
+ * plus the sampling definition that makes the random choices of Alg. 1
+ * reproducible (a counter-based Philox4x32-10 draw per term).  Coordinates
+ * are stored in FP32 and every update is computed in FP64; a pure-FP64 batch
+ * update exists for the deterministic-batch check.
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load this library.  It shares no code, header or table generator with
+ * the GPU library; both implement the same published definitions.
+ *
+ * Readings of points the paper leaves open (each is stated where used):
+ *   R1  N_iters iterations t = 0..N-1 (Alg. 1 loop bounds).
+ *   R2  cooling when t >= floor(N/2), or by a fair coin shared by each
+ *       aligned group of 64 consecutive terms (warp merging, Section
+ *       "Warp Merging", made part of the definition).
+ *   R3  "p ∝ |p|, then a step of p" is drawn as one uniform global step.
+ *   R4  power-law partner: j = i ± z, z ~ Zipf(theta) truncated to the room
+ *       left in the path and to a window W (hop distance counted in steps).
+ *   R5  d_ref is the nucleotide distance between the chosen endpoints along
+ *       the path: endpoint e of step s sits at pos[s] + len*(e XOR reverse).
+ *   R6  the update is the clamped SGD step of Zheng et al. that the paper
+ *       follows for "move against the gradient": mu = min(eta/d^2, 1),
+ *       each point moves by mu*(mag-d)/2 along the pair direction.
+ *   R7  schedule eta_t = eta_max * exp(-lambda t), eta_max = d_max^2,
+ *       eta_min = 0.01, lambda = ln(eta_max/eta_min)/(N-1).
+ *   R8  terms whose two points coincide as coordinate slots, or whose d is 0,
+ *       are skipped (still counted as sampled terms).
+ *   R9  sampled path stress draws exactly m*|p| uniform pairs per path,
+ *       excludes pairs with d = 0 and pools all paths (Eq. 2).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies and xors with a
+ * Weyl-sequence key schedule.
+ * ------------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Stream ids placed in the top byte of counter word 3. */
+enum { STREAM_LAYOUT = 0, STREAM_SPS = 1, STREAM_PAIRS = 2, STREAM_INIT = 3 };
+
+static void draw(uint64_t seed, uint64_t index, uint32_t word2, uint32_t stream, uint32_t graph_id,
+                 uint32_t r[4]) {
+  uint32_t ctr[4] = {(uint32_t)index, (uint32_t)(index >> 32), word2, (stream << 24) | (graph_id & 0xFFFFFFu)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  or_philox4x32_10(ctr, key, r);
+}
+
+/* floor(a * b / 2^64) and floor(a * b / 2^32): range reduction without rejection. */
+static uint64_t mulhi64(uint64_t a, uint64_t b) { return (uint64_t)(((unsigned __int128)a * b) >> 64); }
+static uint32_t mulhi32(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+
+/* ---------------------------------------------------------------------------
+ * Zipf (power-law) hop distance, reading R4.  F[k] = sum_{z=1..k} z^-theta in
+ * FP64 in increasing z; C[k] = floor(F[k]/F[W] * (2^32-1)) with C[0] = 0.  A
+ * draw from 32 random bits r on [1, n] is the smallest k with C[k] > u where
+ * u = floor(r * C[n] / 2^32).
+ * ------------------------------------------------------------------------- */
+void or_zipf_table(double theta, uint32_t W, uint32_t *C) {
+  double *F = (double *)malloc(sizeof(double) * ((size_t)W + 1));
+  F[0] = 0.0;
+  for (uint32_t k = 1; k <= W; ++k) F[k] = F[k - 1] + pow((double)k, -theta);
+  C[0] = 0;
+  for (uint32_t k = 1; k <= W; ++k) C[k] = (uint32_t)floor(F[k] / F[W] * 4294967295.0);
+  free(F);
+}
+
+uint32_t or_zipf_draw(const uint32_t *C, uint32_t n, uint32_t r) {
+  uint32_t u = mulhi32(r, C[n]);
+  /* smallest k in [1, n] with C[k] > u; C[n] > u guarantees one exists */
+  uint32_t lo = 1, hi = n;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo) / 2;
+    if (C[mid] > u) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+/* ---------------------------------------------------------------------------
+ * Learning-rate schedule S of Alg. 1, reading R7.
+ * ------------------------------------------------------------------------- */
+void or_schedule(uint32_t n_iters, double eta_max, double eta_min, double *eta) {
+  if (n_iters == 0) return;
+  if (n_iters == 1) { eta[0] = eta_max; return; }
+  double lambda = log(eta_max / eta_min) / (double)(n_iters - 1);
+  for (uint32_t t = 0; t < n_iters; ++t) eta[t] = eta_max * exp(-lambda * (double)t);
+}
+
+/* ---------------------------------------------------------------------------
+ * Graph: only node lengths and path step lists enter the layout (Alg. 1 reads
+ * P and L; the lean structure stores node lengths, Section "CUDA Kernel for
+ * Pangenome Graph Layout").  pos[s] is the nucleotide offset of step s from
+ * the start of its path: the sum of the lengths of the earlier steps.
+ * ------------------------------------------------------------------------- */
+#define REV_BIT 0x80000000u
+
+typedef struct {
+  uint32_t n_nodes, n_paths;
+  const uint32_t *node_len;   /* borrowed */
+  const uint64_t *path_off;   /* borrowed */
+  const uint32_t *step_node;  /* borrowed */
+  uint64_t S;
+  int64_t *pos;               /* owned */
+  int64_t *path_nt;           /* owned */
+  int64_t d_max;
+} or_graph;
+
+or_graph *or_graph_new(uint32_t n_nodes, const uint32_t *node_len, uint32_t n_paths, const uint64_t *path_off,
+                       const uint32_t *step_node) {
+  or_graph *g = (or_graph *)calloc(1, sizeof(or_graph));
+  g->n_nodes = n_nodes; g->n_paths = n_paths;
+  g->node_len = node_len; g->path_off = path_off; g->step_node = step_node;
+  g->S = path_off[n_paths];
+  g->pos = (int64_t *)malloc(sizeof(int64_t) * (g->S ? g->S : 1));
+  g->path_nt = (int64_t *)malloc(sizeof(int64_t) * (n_paths ? n_paths : 1));
+  g->d_max = 0;
+  for (uint32_t p = 0; p < n_paths; ++p) {
+    int64_t acc = 0;
+    for (uint64_t s = path_off[p]; s < path_off[p + 1]; ++s) {
+      g->pos[s] = acc;
+      acc += node_len[step_node[s] & ~REV_BIT];
+    }
+    g->path_nt[p] = acc;
+    if (acc > g->d_max) g->d_max = acc;
+  }
+  return g;
+}
+
+void or_graph_free(or_graph *g) {
+  if (!g) return;
+  free(g->pos); free(g->path_nt); free(g);
+}
+
+const int64_t *or_graph_pos(const or_graph *g) { return g->pos; }
+const int64_t *or_graph_path_nt(const or_graph *g) { return g->path_nt; }
+int64_t or_graph_d_max(const or_graph *g) { return g->d_max; }
+
+static uint32_t step_node_id(const or_graph *g, uint64_t s) { return g->step_node[s] & ~REV_BIT; }
+static uint32_t step_rev(const or_graph *g, uint64_t s) { return g->step_node[s] >> 31; }
+
+/* Reading R5: path coordinate of endpoint e (0 start, 1 end) of step s. */
+int64_t or_endpoint_pos(const or_graph *g, uint64_t s, uint32_t e) {
+  int64_t len = g->node_len[step_node_id(g, s)];
+  return g->pos[s] + len * (int64_t)(e ^ step_rev(g, s));
+}
+
+/* Largest p with path_off[p] <= i (empty paths are never returned for i < S). */
+static uint32_t path_of_step(const or_graph *g, uint64_t i) {
+  uint32_t lo = 0, hi = g->n_paths - 1;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (g->path_off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+/* ---------------------------------------------------------------------------
+ * One term of Alg. 1: step selection (R3), cooling (R2), partner (R4),
+ * endpoint coins, and the skip conditions of R8.
+ * flags: bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t n_iters;
+  uint32_t zipf_window;
+  uint64_t seed;
+  uint32_t graph_id;
+  const uint32_t *zipf;  /* C[0..W] */
+} sampler;
+
+static void partner_power_law(const or_graph *g, const sampler *sp, uint64_t i, uint64_t start, uint64_t len,
+                              uint32_t r2, uint32_t r3, uint64_t *j, int *skip) {
+  uint64_t room_plus = start + len - 1 - i;
+  uint64_t room_minus = i - start;
+  uint32_t dir = (r3 >> 2) & 1u;         /* 0: towards the path end, 1: towards its start */
+  if (dir == 0 && room_plus == 0) dir = 1;
+  else if (dir == 1 && room_minus == 0) dir = 0;
+  uint64_t room = dir == 0 ? room_plus : room_minus;
+  if (room == 0) { *j = i; *skip = 1; return; }
+  uint32_t n = room < sp->zipf_window ? (uint32_t)room : sp->zipf_window;
+  uint32_t z = or_zipf_draw(sp->zipf, n, r2);
+  *j = dir == 0 ? i + z : i - z;
+  (void)g;
+}
+
+static void sample_term(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t t, uint32_t group_coin,
+                        uint64_t *i_out, uint64_t *j_out, uint32_t *flags) {
+  uint32_t r[4];
+  draw(sp->seed, t, iter, STREAM_LAYOUT, sp->graph_id, r);
+  uint64_t i = mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), g->S);
+  uint32_t p = path_of_step(g, i);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+  uint32_t cooling = (iter >= sp->n_iters / 2) || group_coin;
+  uint32_t e_i = r[3] & 1u, e_j = (r[3] >> 1) & 1u;
+  uint64_t j;
+  int skip = 0;
+  if (cooling) partner_power_law(g, sp, i, start, len, r[2], r[3], &j, &skip);
+  else j = start + mulhi32(r[2], (uint32_t)len);
+  if (!skip) {
+    uint64_t a = 2ull * step_node_id(g, i) + e_i, b = 2ull * step_node_id(g, j) + e_j;
+    int64_t d = or_endpoint_pos(g, i, e_i) - or_endpoint_pos(g, j, e_j);
+    if (a == b || d == 0) skip = 1;
+  }
+  *i_out = i; *j_out = j;
+  *flags = e_i | (e_j << 1) | (cooling << 2) | ((uint32_t)skip << 3);
+}
+
+/* The fair coin of R2 for the 64-term group containing t: bit 3 of word 3 of
+ * the group's first term. */
+static uint32_t group_coin_of(const sampler *sp, uint32_t iter, uint64_t t) {
+  uint32_t r[4];
+  draw(sp->seed, t - (t % 64), iter, STREAM_LAYOUT, sp->graph_id, r);
+  return (r[3] >> 3) & 1u;
+}
+
+static void make_sampler(sampler *sp, uint32_t n_iters, double theta, uint32_t W, uint64_t seed, uint32_t graph_id) {
+  sp->n_iters = n_iters; sp->zipf_window = W; sp->seed = seed; sp->graph_id = graph_id;
+  uint32_t *C = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)W + 1));
+  or_zipf_table(theta, W, C);
+  sp->zipf = C;
+}
+
+void or_sample_terms(const or_graph *g, uint32_t n_iters, double theta, uint32_t W, uint64_t seed, uint32_t graph_id,
+                     uint32_t iter, uint64_t t_begin, uint64_t count, uint64_t *i_out, uint64_t *j_out,
+                     uint8_t *flags_out) {
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  for (uint64_t k = 0; k < count; ++k) {
+    uint64_t t = t_begin + k;
+    uint32_t fl;
+    sample_term(g, &sp, iter, t, group_coin_of(&sp, iter, t), &i_out[k], &j_out[k], &fl);
+    flags_out[k] = (uint8_t)fl;
+  }
+  free((void *)sp.zipf);
+}
+
+/* ---------------------------------------------------------------------------
+ * The update of one term, reading R6.  Points a and b are coordinate slots
+ * 2*node+endpoint in the X and Y planes.  Returns 1 if applied.
+ * ------------------------------------------------------------------------- */
+static int update_f32(float *X, float *Y, uint64_t a, uint64_t b, int64_t d_int, double eta) {
+  double d = (double)d_int;
+  double dx = (double)X[a] - (double)X[b];
+  double dy = (double)Y[a] - (double)Y[b];
+  double mag = sqrt(dx * dx + dy * dy);
+  if (mag == 0.0) return 0;
+  double mu = eta / (d * d);
+  if (mu > 1.0) mu = 1.0;
+  double r = mu * (mag - d) / (2.0 * mag);
+  X[a] = (float)((double)X[a] - r * dx);
+  Y[a] = (float)((double)Y[a] - r * dy);
+  X[b] = (float)((double)X[b] + r * dx);
+  Y[b] = (float)((double)Y[b] + r * dy);
+  return 1;
+}
+
+static int update_f64(double *X, double *Y, uint64_t a, uint64_t b, int64_t d_int, double eta) {
+  double d = (double)d_int;
+  double dx = X[a] - X[b];
+  double dy = Y[a] - Y[b];
+  double mag = sqrt(dx * dx + dy * dy);
+  if (mag == 0.0) return 0;
+  double mu = eta / (d * d);
+  if (mu > 1.0) mu = 1.0;
+  double r = mu * (mag - d) / (2.0 * mag);
+  X[a] -= r * dx; Y[a] -= r * dy;
+  X[b] += r * dx; Y[b] += r * dy;
+  return 1;
+}
+
+static int64_t term_distance(const or_graph *g, uint64_t i, uint64_t j, uint32_t flags) {
+  int64_t d = or_endpoint_pos(g, i, flags & 1u) - or_endpoint_pos(g, j, (flags >> 1) & 1u);
+  return d < 0 ? -d : d;
+}
+
+/* Coordinates use the boundary layout [2][n_nodes][2]: the X plane, then the
+ * Y plane, endpoint e of node n at index 2n+e. */
+
+/* ---------------------------------------------------------------------------
+ * The layout loop of Alg. 1, one thread, terms in order.  Iterations
+ * [first, last) of an n_iters schedule; terms_per_step * S terms per
+ * iteration (Alg. 1 uses 10).  Returns the number of applied updates.
+ * ------------------------------------------------------------------------- */
+uint64_t or_layout(const or_graph *g, uint32_t n_iters, uint32_t terms_per_step, double eta_max, double eta_min,
+                   double theta, uint32_t W, uint64_t seed, uint32_t graph_id, uint32_t first, uint32_t last,
+                   float *coords) {
+  if (g->S == 0 || n_iters == 0) return 0;
+  if (eta_max <= 0.0) eta_max = (double)g->d_max * (double)g->d_max;
+  double *eta = (double *)malloc(sizeof(double) * n_iters);
+  or_schedule(n_iters, eta_max, eta_min, eta);
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  uint64_t T = (uint64_t)terms_per_step * g->S, applied = 0;
+  if (last == 0 || last > n_iters) last = n_iters;
+  for (uint32_t it = first; it < last; ++it) {
+    uint32_t coin = 0;
+    for (uint64_t t = 0; t < T; ++t) {
+      if (t % 64 == 0) coin = group_coin_of(&sp, it, t);
+      uint64_t i, j;
+      uint32_t fl;
+      sample_term(g, &sp, it, t, coin, &i, &j, &fl);
+      if (fl & 8u) continue;
+      uint64_t a = 2ull * step_node_id(g, i) + (fl & 1u), b = 2ull * step_node_id(g, j) + ((fl >> 1) & 1u);
+      applied += update_f32(X, Y, a, b, term_distance(g, i, j, fl), eta[it]);
+    }
+  }
+  free((void *)sp.zipf);
+  free(eta);
+  return applied;
+}
+
+/* Threaded Hogwild mode (Section "Data-level Parallelism"): T threads take
+ * contiguous term ranges and update without locks.  Loads and stores of a
+ * coordinate are relaxed atomics on its bit pattern so the races are
+ * well-defined; results are not deterministic. */
+typedef struct {
+  const or_graph *g; const sampler *sp; const double *eta; float *coords;
+  uint32_t first, last; uint64_t T, t0, t1; uint64_t applied;
+} hw_job;
+
+static float ld_relaxed(const float *p) {
+  uint32_t u = __atomic_load_n((const uint32_t *)p, __ATOMIC_RELAXED);
+  float f; memcpy(&f, &u, 4); return f;
+}
+static void st_relaxed(float *p, float f) {
+  uint32_t u; memcpy(&u, &f, 4);
+  __atomic_store_n((uint32_t *)p, u, __ATOMIC_RELAXED);
+}
+
+static void *hogwild_worker(void *arg) {
+  hw_job *jb = (hw_job *)arg;
+  const or_graph *g = jb->g;
+  float *X = jb->coords, *Y = jb->coords + 2ull * g->n_nodes;
+  for (uint32_t it = jb->first; it < jb->last; ++it) {
+    uint32_t coin = 0;
+    for (uint64_t t = jb->t0; t < jb->t1; ++t) {
+      if (t == jb->t0 || t % 64 == 0) coin = group_coin_of(jb->sp, it, t);
+      uint64_t i, j;
+      uint32_t fl;
+      sample_term(g, jb->sp, it, t, coin, &i, &j, &fl);
+      if (fl & 8u) continue;
+      uint64_t a = 2ull * step_node_id(g, i) + (fl & 1u), b = 2ull * step_node_id(g, j) + ((fl >> 1) & 1u);
+      double d = (double)term_distance(g, i, j, fl);
+      double xa = ld_relaxed(&X[a]), ya = ld_relaxed(&Y[a]), xb = ld_relaxed(&X[b]), yb = ld_relaxed(&Y[b]);
+      double dx = xa - xb, dy = ya - yb, mag = sqrt(dx * dx + dy * dy);
+      if (mag == 0.0) continue;
+      double mu = jb->eta[it] / (d * d);
+      if (mu > 1.0) mu = 1.0;
+      double r = mu * (mag - d) / (2.0 * mag);
+      st_relaxed(&X[a], (float)(xa - r * dx)); st_relaxed(&Y[a], (float)(ya - r * dy));
+      st_relaxed(&X[b], (float)(xb + r * dx)); st_relaxed(&Y[b], (float)(yb + r * dy));
+      jb->applied++;
+    }
+  }
+  return NULL;
+}
+
+/* Runs iterations [first,last) on n_threads threads.  With term_limit > 0 only
+ * the first term_limit terms of each iteration are processed (a bounded sample
+ * for timing).  Threads synchronise only between iterations. */
+uint64_t or_layout_threaded(const or_graph *g, uint32_t n_iters, uint32_t terms_per_step, double eta_max,
+                            double eta_min, double theta, uint32_t W, uint64_t seed, uint32_t graph_id,
+                            uint32_t first, uint32_t last, float *coords, uint32_t n_threads, uint64_t term_limit) {
+  if (g->S == 0 || n_iters == 0 || n_threads == 0) return 0;
+  if (eta_max <= 0.0) eta_max = (double)g->d_max * (double)g->d_max;
+  double *eta = (double *)malloc(sizeof(double) * n_iters);
+  or_schedule(n_iters, eta_max, eta_min, eta);
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  uint64_t T = (uint64_t)terms_per_step * g->S;
+  if (term_limit > 0 && term_limit < T) T = term_limit;
+  if (last == 0 || last > n_iters) last = n_iters;
+  hw_job *jobs = (hw_job *)calloc(n_threads, sizeof(hw_job));
+  pthread_t *th = (pthread_t *)calloc(n_threads, sizeof(pthread_t));
+  uint64_t applied = 0;
+  for (uint32_t it = first; it < last; ++it) {
+    for (uint32_t k = 0; k < n_threads; ++k) {
+      jobs[k] = (hw_job){g, &sp, eta, coords, it, it + 1, T, T * k / n_threads, T * (k + 1) / n_threads, 0};
+      pthread_create(&th[k], NULL, hogwild_worker, &jobs[k]);
+    }
+    for (uint32_t k = 0; k < n_threads; ++k) {
+      pthread_join(th[k], NULL);
+      applied += jobs[k].applied;
+    }
+  }
+  free(jobs); free(th); free((void *)sp.zipf); free(eta);
+  return applied;
+}
+
+/* Pure-FP64 application of a given batch of terms, in order (the
+ * deterministic-batch check).  coords64 uses the boundary layout in FP64. */
+uint64_t or_apply_terms_f64(const or_graph *g, double eta, const uint64_t *i, const uint64_t *j,
+                            const uint8_t *flags, uint64_t count, double *coords64) {
+  double *X = coords64, *Y = coords64 + 2ull * g->n_nodes;
+  uint64_t applied = 0;
+  for (uint64_t k = 0; k < count; ++k) {
+    if (flags[k] & 8u) continue;
+    uint64_t a = 2ull * step_node_id(g, i[k]) + (flags[k] & 1u);
+    uint64_t b = 2ull * step_node_id(g, j[k]) + ((flags[k] >> 1) & 1u);
+    applied += update_f64(X, Y, a, b, term_distance(g, i[k], j[k], flags[k]), eta);
+  }
+  return applied;
+}
+
+/* Same, with FP32 storage and FP64 math (what one oracle term does). */
+uint64_t or_apply_terms_f32(const or_graph *g, double eta, const uint64_t *i, const uint64_t *j,
+                            const uint8_t *flags, uint64_t count, float *coords) {
+  float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  uint64_t applied = 0;
+  for (uint64_t k = 0; k < count; ++k) {
+    if (flags[k] & 8u) continue;
+    uint64_t a = 2ull * step_node_id(g, i[k]) + (flags[k] & 1u);
+    uint64_t b = 2ull * step_node_id(g, j[k]) + ((flags[k] >> 1) & 1u);
+    applied += update_f32(X, Y, a, b, term_distance(g, i[k], j[k], flags[k]), eta);
+  }
+  return applied;
+}
+
+/* ---------------------------------------------------------------------------
+ * Sampled path stress, Eq. 2, with the two-pass CI95 (reading R9).  Pair q of
+ * path p, q in [m*off[p], m*off[p+1]), draws Philox stream 1 at counter q:
+ * i = start + floor(u64 * |p| / 2^64), j = start + floor(r2 * |p| / 2^32),
+ * e_i = bit 0, e_j = bit 1 of r3.  stress = ((mag - d)/d)^2 in FP64.
+ * out[0..5] = mean, ci_lo, ci_hi, stddev, sum (pass 1), sum of squared
+ * deviations (pass 2); counts[0..1] = n_valid, n_skipped (d == 0).
+ * ------------------------------------------------------------------------- */
+static void sps_pair(const or_graph *g, uint64_t seed, uint32_t graph_id, uint32_t p, uint64_t q,
+                     uint64_t *i, uint64_t *j, uint32_t *ei, uint32_t *ej) {
+  uint32_t r[4];
+  draw(seed, q, 0, STREAM_SPS, graph_id, r);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+  *i = start + mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), len);
+  *j = start + mulhi32(r[2], (uint32_t)len);
+  *ei = r[3] & 1u;
+  *ej = (r[3] >> 1) & 1u;
+}
+
+static double pair_stress(const or_graph *g, const float *coords, uint64_t i, uint64_t j, uint32_t ei, uint32_t ej,
+                          int *valid) {
+  int64_t dd = or_endpoint_pos(g, i, ei) - or_endpoint_pos(g, j, ej);
+  if (dd == 0) { *valid = 0; return 0.0; }
+  double d = (double)(dd < 0 ? -dd : dd);
+  const float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  uint64_t a = 2ull * step_node_id(g, i) + ei, b = 2ull * step_node_id(g, j) + ej;
+  double dx = (double)X[a] - (double)X[b], dy = (double)Y[a] - (double)Y[b];
+  double mag = sqrt(dx * dx + dy * dy);
+  double e = (mag - d) / d;
+  *valid = 1;
+  return e * e;
+}
+
+void or_sampled_path_stress(const or_graph *g, const float *coords, uint32_t m, uint64_t seed, uint32_t graph_id,
+                            double *out, uint64_t *counts) {
+  double sum = 0.0;
+  uint64_t n = 0, skipped = 0;
+  for (uint32_t p = 0; p < g->n_paths; ++p) {
+    for (uint64_t q = (uint64_t)m * g->path_off[p]; q < (uint64_t)m * g->path_off[p + 1]; ++q) {
+      uint64_t i, j; uint32_t ei, ej; int valid;
+      sps_pair(g, seed, graph_id, p, q, &i, &j, &ei, &ej);
+      double s = pair_stress(g, coords, i, j, ei, ej, &valid);
+      if (valid) { sum += s; ++n; } else { ++skipped; }
+    }
+  }
+  double mean = n ? sum / (double)n : 0.0;
+  double dev = 0.0;
+  for (uint32_t p = 0; p < g->n_paths; ++p) {
+    for (uint64_t q = (uint64_t)m * g->path_off[p]; q < (uint64_t)m * g->path_off[p + 1]; ++q) {
+      uint64_t i, j; uint32_t ei, ej; int valid;
+      sps_pair(g, seed, graph_id, p, q, &i, &j, &ei, &ej);
+      double s = pair_stress(g, coords, i, j, ei, ej, &valid);
+      if (valid) dev += (s - mean) * (s - mean);
+    }
+  }
+  double sd = n > 1 ? sqrt(dev / (double)(n - 1)) : 0.0;
+  double half = n ? 1.96 * sd / sqrt((double)n) : 0.0;
+  out[0] = mean; out[1] = mean - half; out[2] = mean + half; out[3] = sd; out[4] = sum; out[5] = dev;
+  counts[0] = n; counts[1] = skipped;
+}
+
+/* The exact expectation of one pass of the sampled estimator: every
+ * (i, j, e_i, e_j) of path p has probability 1/(4|p|^2) per pair and path p
+ * receives m|p| of the m*S pairs, so E[sum] / E[n] enumerates all of them
+ * weighted by 1/(4|p|).  out[0] = E[sum s]/E[n] (the ratio the pooled mean
+ * converges to), out[1] = E[n] / (m*S). */
+void or_sps_expectation(const or_graph *g, const float *coords, double *out) {
+  double num = 0.0, den = 0.0;
+  for (uint32_t p = 0; p < g->n_paths; ++p) {
+    uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+    if (len == 0) continue;
+    double w = 1.0 / (4.0 * (double)len);
+    for (uint64_t i = start; i < start + len; ++i)
+      for (uint64_t j = start; j < start + len; ++j)
+        for (uint32_t e = 0; e < 4; ++e) {
+          int valid;
+          double s = pair_stress(g, coords, i, j, e & 1u, e >> 1, &valid);
+          if (valid) { num += w * s; den += w; }
+        }
+  }
+  out[0] = den > 0 ? num / den : 0.0;
+  out[1] = g->S ? den / (double)g->S : 0.0;
+}
+
+/* Path stress, Eq. 1: the mean over all unordered step pairs i < j of the
+ * same path of the stress averaged over the four endpoint combinations
+ * (combinations with d = 0 are left out of that average; a pair whose four
+ * combinations all have d = 0 is left out).  out[0] = path stress, out[1] =
+ * number of pairs. */
+void or_path_stress_exact(const or_graph *g, const float *coords, double *out) {
+  double sum = 0.0;
+  uint64_t pairs = 0;
+  for (uint32_t p = 0; p < g->n_paths; ++p) {
+    for (uint64_t i = g->path_off[p]; i < g->path_off[p + 1]; ++i)
+      for (uint64_t j = i + 1; j < g->path_off[p + 1]; ++j) {
+        double acc = 0.0;
+        int nv = 0;
+        for (uint32_t e = 0; e < 4; ++e) {
+          int valid;
+          double s = pair_stress(g, coords, i, j, e & 1u, e >> 1, &valid);
+          if (valid) { acc += s; ++nv; }
+        }
+        if (nv) { sum += acc / nv; ++pairs; }
+      }
+  }
+  out[0] = pairs ? sum / (double)pairs : 0.0;
+  out[1] = (double)pairs;
+}
+
+/* ---------------------------------------------------------------------------
+ * Initial layout (the paper is silent; it is not part of any parity claim):
+ * node n starts on the x axis at the path coordinate of its first visit
+ * (paths scanned in order), X[2n] = pos, X[2n+1] = pos + len; never-visited
+ * nodes start at 0.  Y[2n+e] = jitter * (u - 1/2) with u = (r0 >> 8) / 2^24
+ * from Philox stream 3 at counter 2n+e.
+ * ------------------------------------------------------------------------- */
+void or_init_coords(const or_graph *g, uint64_t seed, uint32_t graph_id, float jitter, float *coords) {
+  float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  uint8_t *seen = (uint8_t *)calloc(g->n_nodes ? g->n_nodes : 1, 1);
+  for (uint32_t n = 0; n < g->n_nodes; ++n) { X[2ull * n] = 0.0f; X[2ull * n + 1] = 0.0f; }
+  for (uint64_t s = 0; s < g->S; ++s) {
+    uint32_t n = step_node_id(g, s);
+    if (seen[n]) continue;
+    seen[n] = 1;
+    X[2ull * n] = (float)g->pos[s];
+    X[2ull * n + 1] = (float)(g->pos[s] + (int64_t)g->node_len[n]);
+  }
+  free(seen);
+  for (uint64_t k = 0; k < 2ull * g->n_nodes; ++k) {
+    uint32_t r[4];
+    draw(seed, k, 0, STREAM_INIT, graph_id, r);
+    float u = (float)(r[0] >> 8) * (1.0f / 16777216.0f);
+    Y[k] = jitter * (u - 0.5f);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Differentiable form: the sampled stress as a loss over n_pairs power-law
+ * pairs (the cooling sampler, Philox stream 2, counter word 2 = optimiser
+ * step).  L = (1/n_valid) sum ((mag - d)/d)^2; dL/dv_a = (2/n_valid)
+ * (mag - d)/d^2 * (v_a - v_b)/mag and dL/dv_b = -dL/dv_a (zero when mag = 0).
+ * Pairs skipped by R8 do not count.  grad (FP64, boundary layout) is
+ * overwritten.  out[0] = L, out[1] = n_valid.
+ * ------------------------------------------------------------------------- */
+static int pair_power_law(const or_graph *g, const sampler *sp, uint32_t step, uint64_t q, uint64_t *a, uint64_t *b,
+                          double *d) {
+  uint32_t r[4];
+  draw(sp->seed, q, step, STREAM_PAIRS, sp->graph_id, r);
+  uint64_t i = mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), g->S);
+  uint32_t p = path_of_step(g, i);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start, j;
+  int skip = 0;
+  partner_power_law(g, sp, i, start, len, r[2], r[3], &j, &skip);
+  if (skip) return 0;
+  uint32_t ei = r[3] & 1u, ej = (r[3] >> 1) & 1u;
+  *a = 2ull * step_node_id(g, i) + ei;
+  *b = 2ull * step_node_id(g, j) + ej;
+  int64_t dd = or_endpoint_pos(g, i, ei) - or_endpoint_pos(g, j, ej);
+  if (*a == *b || dd == 0) return 0;
+  *d = (double)(dd < 0 ? -dd : dd);
+  return 1;
+}
+
+void or_stress_loss_grad(const or_graph *g, const float *coords, uint64_t n_pairs, double theta, uint32_t W,
+                         uint64_t seed, uint32_t graph_id, uint32_t step, double *out, double *grad) {
+  sampler sp;
+  make_sampler(&sp, 2, theta, W, seed, graph_id);
+  const float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  double sum = 0.0;
+  uint64_t n = 0;
+  for (uint64_t q = 0; q < n_pairs; ++q) {
+    uint64_t a, b; double d;
+    if (!pair_power_law(g, &sp, step, q, &a, &b, &d)) continue;
+    double dx = (double)X[a] - (double)X[b], dy = (double)Y[a] - (double)Y[b];
+    double mag = sqrt(dx * dx + dy * dy);
+    double e = (mag - d) / d;
+    sum += e * e;
+    ++n;
+  }
+  out[0] = n ? sum / (double)n : 0.0;
+  out[1] = (double)n;
+  if (grad) {
+    double *GX = grad, *GY = grad + 2ull * g->n_nodes;
+    memset(grad, 0, sizeof(double) * 4ull * g->n_nodes);
+    for (uint64_t q = 0; q < n_pairs && n > 0; ++q) {
+      uint64_t a, b; double d;
+      if (!pair_power_law(g, &sp, step, q, &a, &b, &d)) continue;
+      double dx = (double)X[a] - (double)X[b], dy = (double)Y[a] - (double)Y[b];
+      double mag = sqrt(dx * dx + dy * dy);
+      if (mag == 0.0) continue;
+      double c = 2.0 / (double)n * (mag - d) / (d * d) / mag;
+      GX[a] += c * dx; GY[a] += c * dy;
+      GX[b] -= c * dx; GY[b] -= c * dy;
+    }
+  }
+  free((void *)sp.zipf);
+}

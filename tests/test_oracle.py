@@ -1,0 +1,468 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each test checks the oracle against something other than itself: published
+known-answer values, closed forms, invariants of the method, exact rational
+arithmetic, or brute force on tiny inputs.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# T1: Philox4x32-10 against its published known-answer vectors
+# ---------------------------------------------------------------------------
+def _kat_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(x, 16) for x in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,expect", _kat_rows())
+def test_philox_known_answers(ctr, key, expect):
+    assert [int(x) for x in O.philox(ctr, key)] == expect
+
+
+def test_philox_bit_balance():
+    # every output bit of a good generator is set half the time
+    words = np.array([O.philox([k, 0, 3, 0], [24301, 0]) for k in range(4096)], dtype=np.uint64)
+    bits = np.unpackbits(words.astype(">u4").view(np.uint8)).reshape(-1, 128).mean(axis=0)
+    assert np.all(np.abs(bits - 0.5) < 5 * 0.5 / math.sqrt(4096))
+
+
+# ---------------------------------------------------------------------------
+# T3: Zipf table and sampler
+# ---------------------------------------------------------------------------
+def test_zipf_table_matches_generalized_harmonic_numbers():
+    theta, W = 0.99, 1000
+    C = O.zipf_table(theta, W).astype(np.float64)
+    # exactly-rounded partial sums (math.fsum) as the closed form F[k]/F[W]
+    terms = [k ** -theta for k in range(1, W + 1)]
+    FW = math.fsum(terms)
+    F = np.array([math.fsum(terms[:k]) for k in range(1, W + 1)])
+    assert C[0] == 0 and C[W] == 2 ** 32 - 1
+    assert np.all(np.diff(C) > 0), "table must be strictly increasing"
+    assert np.max(np.abs(C[1:] / C[W] - F / FW)) < 2 ** -31
+
+
+def test_zipf_table_theta1_exact_rational():
+    # theta = 1: F[k] is the harmonic number H_k; compare with exact Fractions
+    W = 60
+    C = O.zipf_table(1.0, W)
+    H = [Fraction(0)]
+    for k in range(1, W + 1):
+        H.append(H[-1] + Fraction(1, k))
+    for k in range(1, W + 1):
+        exact = math.floor(H[k] / H[W] * (2 ** 32 - 1))
+        assert abs(int(C[k]) - exact) <= 1
+
+
+def test_zipf_table_theta0_is_uniform():
+    W = 37
+    C = O.zipf_table(0.0, W)
+    for k in range(W + 1):
+        assert abs(int(C[k]) - (k * (2 ** 32 - 1)) // W) <= 1
+
+
+def test_zipf_draw_equals_linear_scan_and_stays_in_range():
+    C = O.zipf_table(0.99, 1000)
+    rng = np.random.default_rng(3)
+    for n in [1, 2, 3, 7, 64, 999, 1000]:
+        for r in rng.integers(0, 2 ** 32, size=300, dtype=np.uint64):
+            z = O.zipf_draw(C, n, int(r))
+            u = (int(r) * int(C[n])) >> 32
+            brute = next(k for k in range(1, n + 1) if C[k] > u)
+            assert z == brute and 1 <= z <= n
+    assert O.zipf_draw(C, 5, 0) == 1
+    assert O.zipf_draw(C, 5, 2 ** 32 - 1) == 5
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 1000])
+def test_zipf_draw_histogram_chi_square(n):
+    C = O.zipf_table(0.99, 1000)
+    # a fine uniform grid over the 32-bit input (deterministic, ~uniform)
+    N = 1 << 18
+    rs = (np.arange(N, dtype=np.uint64) * (2 ** 32 // N) + 12345) % (2 ** 32)
+    counts = np.zeros(n + 1)
+    for r in rs:
+        counts[O.zipf_draw(C, n, int(r))] += 1
+    pmf = np.diff(C[: n + 1].astype(np.float64)) / float(C[n])
+    expected = pmf * N
+    if n == 1:
+        assert counts[1] == N
+        return
+    chi2 = float(np.sum((counts[1:] - expected) ** 2 / expected))
+    # a grid is far more even than random sampling; bound by the chi-square 99.9% point
+    dof = n - 1
+    assert chi2 < dof + 4.5 * math.sqrt(2 * dof) + 10
+    # the table pmf is the truncated Zipf law z^-theta / H_{n,theta}
+    true = np.array([k ** -0.99 for k in range(1, n + 1)])
+    true /= true.sum()
+    assert np.max(np.abs(pmf - true)) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# T4: positions are node-length prefix sums; endpoint coordinates
+# ---------------------------------------------------------------------------
+def test_positions_are_prefix_sums(tiny_synth, tiny_oracle):
+    g, sg = tiny_oracle, tiny_synth
+    pos = g.pos
+    for p in range(g.n_paths):
+        acc = 0
+        for s in range(int(sg.path_off[p]), int(sg.path_off[p + 1])):
+            assert pos[s] == acc
+            acc += int(sg.node_len[int(sg.step_node[s]) & 0x7FFFFFFF])
+        assert g.path_nt[p] == acc
+    assert g.d_max == max(g.path_nt)
+
+
+def test_endpoint_positions_forward_and_reverse():
+    # node 0 (len 3) forward, node 1 (len 2) reverse, node 2 (len 4) forward
+    g = O.Graph(np.array([3, 2, 4], np.uint32), np.array([0, 3], np.uint64),
+                np.array([0, 1 | synth.REV_BIT, 2], np.uint32))
+    assert [g.endpoint_pos(0, 0), g.endpoint_pos(0, 1)] == [0, 3]
+    assert [g.endpoint_pos(1, 0), g.endpoint_pos(1, 1)] == [5, 3]   # reverse: start is met last
+    assert [g.endpoint_pos(2, 0), g.endpoint_pos(2, 1)] == [5, 9]
+    for s, L in [(0, 3), (1, 2), (2, 4)]:
+        assert abs(g.endpoint_pos(s, 0) - g.endpoint_pos(s, 1)) == L
+
+
+# ---------------------------------------------------------------------------
+# T5: schedule
+# ---------------------------------------------------------------------------
+def test_schedule_closed_form():
+    dmax = 8973
+    eta = O.schedule(30, float(dmax) ** 2, 0.01)
+    assert eta[0] == float(dmax) ** 2
+    assert abs(eta[-1] - 0.01) <= 1e-15
+    ratio = eta[1:] / eta[:-1]
+    assert np.allclose(ratio, ratio[0], rtol=1e-12, atol=0)
+    assert abs(ratio[0] - (0.01 / dmax ** 2) ** (1 / 29)) < 1e-12
+    assert list(O.schedule(1, 5.0, 0.01)) == [5.0]
+
+
+# ---------------------------------------------------------------------------
+# T2: sampling invariants and uniformity
+# ---------------------------------------------------------------------------
+def _path_of(path_off, s):
+    return np.searchsorted(path_off, s, side="right") - 1
+
+
+def test_sampling_invariants(tiny_synth, tiny_oracle):
+    g, sg = tiny_oracle, tiny_synth
+    for it in [0, 14, 15, 29]:
+        i, j, f = O.sample_terms(g, it, 0, 20000)
+        assert np.all(i < g.S) and np.all(j < g.S)
+        pi, pj = _path_of(sg.path_off, i), _path_of(sg.path_off, j)
+        assert np.all(pi == pj), "partner must lie on the same path"
+        cool = (f >> 2) & 1
+        if it >= 15:
+            assert np.all(cool == 1)
+        else:
+            assert 0.3 < cool.mean() < 0.7
+            # the coin is shared by each aligned group of 64 terms
+            assert np.all(cool.reshape(-1, 64)[:, :-1] == cool.reshape(-1, 64)[:, 1:]) if len(cool) % 64 == 0 \
+                else True
+        hop = np.abs(i.astype(np.int64) - j.astype(np.int64))
+        c = cool == 1
+        skip = ((f >> 3) & 1) == 1
+        assert np.all(hop[c & ~skip] >= 1) and np.all(hop[c] <= 1000)
+        # endpoint coins are fair
+        assert abs((f & 1).mean() - 0.5) < 0.02 and abs(((f >> 1) & 1).mean() - 0.5) < 0.02
+
+
+def test_sampling_group_coin_is_group_leader_bit(tiny_oracle):
+    g = tiny_oracle
+    i, j, f = O.sample_terms(g, 3, 64 * 10 + 5, 64 * 3)
+    for k in range(len(f)):
+        t = 64 * 10 + 5 + k
+        lead = O.philox([(t - t % 64) & 0xFFFFFFFF, t >> 32, 3, 0], [24301, 0])
+        assert ((f[k] >> 2) & 1) == ((lead[3] >> 3) & 1)
+
+
+def test_step_selection_uniform_chi_square(tiny_oracle):
+    g = tiny_oracle
+    N = 400_000
+    i, _, _ = O.sample_terms(g, 0, 0, N)
+    counts = np.bincount(i.astype(np.int64), minlength=g.S)
+    e = N / g.S
+    chi2 = float(np.sum((counts - e) ** 2 / e))
+    dof = g.S - 1
+    assert abs(chi2 - dof) < 5 * math.sqrt(2 * dof)
+
+
+def test_sampling_counter_carry_into_high_word(tiny_oracle):
+    # terms around t = 2^32 use counter words (t mod 2^32, t >> 32)
+    g = tiny_oracle
+    t0 = 2 ** 32 - 3
+    i, j, f = O.sample_terms(g, 7, t0, 6)
+    for k in range(6):
+        t = t0 + k
+        r = O.philox([t & 0xFFFFFFFF, t >> 32, 7, 0], [24301, 0])
+        u64 = int(r[0]) | (int(r[1]) << 32)
+        assert int(i[k]) == (u64 * g.S) >> 64
+
+
+def test_uniform_partner_is_uniform_within_path():
+    # one path of 5 steps: the uniform partner of any i covers all 5 steps evenly
+    g = O.Graph(np.full(5, 2, np.uint32), np.array([0, 5], np.uint64), np.arange(5, dtype=np.uint32))
+    i, j, f = O.sample_terms(g, 0, 0, 64 * 2000)
+    cool = ((f >> 2) & 1) == 1
+    cnt = np.bincount(j[~cool].astype(np.int64), minlength=5)
+    assert cnt.min() > 0.9 * cnt.mean() and cnt.max() < 1.1 * cnt.mean()
+
+
+def test_power_law_partner_boundaries():
+    # a single-step path is always skipped in cooling; at the path ends the hop turns inwards
+    g = O.Graph(np.array([4, 3, 3, 3], np.uint32), np.array([0, 1, 4], np.uint64), np.arange(4, dtype=np.uint32))
+    i, j, f = O.sample_terms(g, 20, 0, 20000)
+    cool_skip = ((f >> 3) & 1) == 1
+    assert np.all(cool_skip[i == 0]), "len-1 path must be skipped"
+    assert np.all(j[i == 1] > 1) and np.all(j[i == 3] < 3)
+    assert np.all((j[(i >= 1)] >= 1) & (j[(i >= 1)] <= 3))
+
+
+# ---------------------------------------------------------------------------
+# T6: one update against the closed form (two-node example) and the gradient
+# ---------------------------------------------------------------------------
+def _two_node():
+    # node A (len 3) then node B (len 2), one forward path: A.start at 0, B.end at 5 -> d = 5
+    return O.Graph(np.array([3, 2], np.uint32), np.array([0, 2], np.uint64), np.array([0, 1], np.uint32))
+
+
+def _coords_two_node(xa, xb):
+    c = np.zeros(8, np.float64)   # X plane [A.s, A.e, B.s, B.e], then Y plane
+    c[0], c[3] = xa, xb
+    return c
+
+
+@pytest.mark.parametrize("eta,expect", [(25.0, (2.5, 7.5)), (1000.0, (2.5, 7.5)), (5.0, (0.5, 9.5))])
+def test_two_node_update_closed_form(eta, expect):
+    g = _two_node()
+    c = _coords_two_node(0.0, 10.0)
+    i, j, fl = np.array([0], np.uint64), np.array([1], np.uint64), np.array([0 | (1 << 1)], np.uint8)
+    assert O.apply_terms_f64(g, eta, i, j, fl, c) == 1
+    assert c[0] == expect[0] and c[3] == expect[1]
+    assert c[4] == 0 and c[7] == 0
+    c32 = _coords_two_node(0.0, 10.0).astype(np.float32)
+    O.apply_terms_f32(g, eta, i, j, fl, c32)
+    assert c32[0] == expect[0] and c32[3] == expect[1]
+
+
+def test_update_is_quarter_eta_gradient_step_and_keeps_midpoint():
+    g = _two_node()
+    rng = np.random.default_rng(5)
+    i, j, fl = np.array([0], np.uint64), np.array([1], np.uint64), np.array([0 | (1 << 1)], np.uint8)
+    d = 5.0
+    for _ in range(20):
+        c = np.zeros(8)
+        c[[0, 3, 4, 7]] = rng.normal(scale=20, size=4)
+        va, vb = np.array([c[0], c[4]]), np.array([c[3], c[7]])
+        mag = np.linalg.norm(va - vb)
+        eta = float(rng.uniform(0.1, 20))          # mu = eta/d^2 < 1
+        mu = min(eta / d ** 2, 1.0)
+
+        def stress(a):
+            return ((np.linalg.norm(a - vb) - d) / d) ** 2
+
+        h = 1e-6
+        grad = np.array([(stress(va + h * e) - stress(va - h * e)) / (2 * h) for e in np.eye(2)])
+        O.apply_terms_f64(g, eta, i, j, fl, c)
+        na, nb = np.array([c[0], c[4]]), np.array([c[3], c[7]])
+        assert np.allclose(na, va - eta / 4 * grad, rtol=1e-6, atol=1e-6)
+        assert np.allclose((na + nb) / 2, (va + vb) / 2, atol=1e-9)
+        assert abs(np.linalg.norm(na - nb) - abs(mag - mu * (mag - d))) < 1e-9
+
+
+def test_update_skips_degenerate_terms():
+    # same slot (a == b) and zero distance are skipped at sampling; mag == 0 at update
+    g = _two_node()
+    c = np.zeros(8)
+    assert O.apply_terms_f64(g, 10.0, np.array([0], np.uint64), np.array([1], np.uint64),
+                             np.array([2], np.uint8), c) == 0   # coincident points: mag == 0
+    i, j, f = O.sample_terms(g, 0, 0, 4096)
+    a = i * 2 + (f & 1)
+    b = j * 2 + ((f >> 1) & 1)
+    pa = np.where((f & 1) == 1, np.array([3, 5])[i.astype(int)], np.array([0, 3])[i.astype(int)])
+    pb = np.where(((f >> 1) & 1) == 1, np.array([3, 5])[j.astype(int)], np.array([0, 3])[j.astype(int)])
+    should_skip = (a == b) | (pa == pb)
+    assert np.array_equal(((f >> 3) & 1) == 1, should_skip)
+
+
+# ---------------------------------------------------------------------------
+# T7: a single linear path converges to near-zero stress
+# ---------------------------------------------------------------------------
+def test_linear_path_converges():
+    sg = synth.linear_path(2000)
+    g = O.Graph.from_synth(sg)
+    c = O.init_coords(g)
+    O.layout(g, c)
+    assert O.sampled_path_stress(g, c)["mean"] < 1e-4
+    # from a scrambled start (initial stress ~4e3) the stress falls by more than 1e6
+    rng = np.random.default_rng(0)
+    c1 = O.init_coords(g)
+    c1[: 2 * g.n_nodes] = (rng.random(2 * g.n_nodes) * g.d_max).astype(np.float32)
+    s0 = O.sampled_path_stress(g, c1)["mean"]
+    c2 = c1.copy()
+    O.layout(g, c2)
+    assert O.sampled_path_stress(g, c2)["mean"] < s0 * 1e-6
+    c3 = c1.copy()
+    O.layout(g, c3, n_iters=60)
+    assert O.sampled_path_stress(g, c3)["mean"] < 1e-4
+
+
+def test_layout_reduces_stress_on_tiny(tiny_oracle):
+    g = tiny_oracle
+    c = O.init_coords(g)
+    s0 = O.sps_expectation(g, c)[0]
+    O.layout(g, c)
+    s1 = O.sps_expectation(g, c)[0]
+    assert s1 < 0.05 * s0
+
+
+def test_layout_split_run_equals_full_run(tiny_oracle):
+    g = tiny_oracle
+    c_full = O.init_coords(g)
+    O.layout(g, c_full)
+    c_split = O.init_coords(g)
+    O.layout(g, c_split, first_iter=0, last_iter=11)
+    O.layout(g, c_split, first_iter=11, last_iter=30)
+    assert np.array_equal(c_full, c_split)
+
+
+def test_threaded_mode_with_one_thread_equals_sequential(tiny_oracle):
+    g = tiny_oracle
+    a = O.init_coords(g)
+    b = a.copy()
+    O.layout(g, a, first_iter=0, last_iter=3)
+    O.layout(g, b, first_iter=0, last_iter=3, threads=1, term_limit=10 * g.S)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# T8: sampled path stress (Eq. 2) and path stress (Eq. 1)
+# ---------------------------------------------------------------------------
+def _scaled_line(g, lam):
+    # a single forward path drawn on a line scaled by lam: every pair has mag = lam * d
+    c = np.zeros(4 * g.n_nodes, np.float32)
+    pos = g.pos
+    for s in range(g.S):
+        n = s
+        c[2 * n] = lam * pos[s]
+        c[2 * n + 1] = lam * (pos[s] + int(g.node_len[n]))
+    return c
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.5, 2.0, 3.0])
+def test_stress_of_scaled_line_is_closed_form(lam):
+    sg = synth.linear_path(300, seed=4)
+    g = O.Graph.from_synth(sg)
+    c = _scaled_line(g, lam)
+    s = O.sampled_path_stress(g, c, m=20)
+    assert s["n_valid"] + s["n_skipped"] == 20 * g.S
+    assert abs(s["mean"] - (lam - 1) ** 2) < 1e-9
+    assert s["stddev"] < 1e-6
+    ps, pairs = O.path_stress_exact(g, c)
+    assert pairs == g.S * (g.S - 1) // 2
+    assert abs(ps - (lam - 1) ** 2) < 1e-9
+    assert abs(O.sps_expectation(g, c)[0] - (lam - 1) ** 2) < 1e-9
+
+
+def test_two_node_path_stress_by_hand():
+    # A (len 3) then B (len 2); layout: A.s=(0,0) A.e=(3,0) B.s=(3,4) B.e=(6,4)
+    g = _two_node()
+    c = np.zeros(8, np.float32)
+    c[0:4] = [0, 3, 3, 6]
+    c[4:8] = [0, 0, 4, 4]
+    # pair (A,B): combos (A.s,B.s): d=3, mag=5 -> (2/3)^2; (A.s,B.e): d=5, mag=sqrt(52);
+    # (A.e,B.s): d=0 -> excluded; (A.e,B.e): d=2, mag=5 -> (3/2)^2
+    v = [(2 / 3) ** 2, ((math.sqrt(52) - 5) / 5) ** 2, 1.5 ** 2]
+    ps, pairs = O.path_stress_exact(g, c)
+    assert pairs == 1 and abs(ps - sum(v) / 3) < 1e-6
+    # the SPS estimator's expectation: all (i, j, e_i, e_j) over 2 steps with equal weight;
+    # same-node pairs: (A.s,A.e) d=3 mag=3 -> 0, (B.s,B.e) d=2 mag=3 -> 1/4; same endpoints d=0
+    vals = [0, 0, 0.25, 0.25] + v + v
+    assert abs(O.sps_expectation(g, c)[0] - sum(vals) / len(vals)) < 1e-6
+
+
+def test_sps_matches_its_expectation_within_ci(tiny_oracle):
+    g = tiny_oracle
+    c = O.init_coords(g)
+    O.layout(g, c, first_iter=0, last_iter=20)
+    exp_mean, frac_valid = O.sps_expectation(g, c)
+    s = O.sampled_path_stress(g, c, m=100, seed=7)
+    n = s["n_valid"]
+    assert abs(s["mean"] - exp_mean) < 3.29 * s["stddev"] / math.sqrt(n)
+    assert abs(n / (100 * g.S) - frac_valid) < 5 * math.sqrt(frac_valid * (1 - frac_valid) / (100 * g.S)) + 1e-9
+    assert s["ci_lo"] < s["mean"] < s["ci_hi"]
+    assert abs((s["ci_hi"] - s["ci_lo"]) / 2 - 1.96 * s["stddev"] / math.sqrt(n)) < 1e-12
+    # a second seed gives a consistent value (the metric is stable across seeds)
+    s2 = O.sampled_path_stress(g, c, m=100, seed=8)
+    assert abs(s2["mean"] - s["mean"]) < 4.0 * s["stddev"] / math.sqrt(n)
+
+
+def test_sps_pair_count_is_m_times_path_length(tiny_oracle):
+    g = tiny_oracle
+    c = O.init_coords(g)
+    for m in [1, 3, 10]:
+        s = O.sampled_path_stress(g, c, m=m)
+        assert s["n_valid"] + s["n_skipped"] == m * g.S
+
+
+# ---------------------------------------------------------------------------
+# Differentiable form: loss and gradient
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.5, 2.0])
+def test_loss_of_scaled_line_is_closed_form(lam):
+    sg = synth.linear_path(500, seed=2)
+    g = O.Graph.from_synth(sg)
+    c = _scaled_line(g, lam)
+    L, n, grad = O.stress_loss_grad(g, c, 20000, seed=11)
+    assert n > 0.9 * 20000 and abs(L - (lam - 1) ** 2) < 1e-9
+
+
+def test_gradient_matches_finite_differences():
+    sg = synth.generate(60, 0.2, 3, 9)
+    g = O.Graph.from_synth(sg)
+    rng = np.random.default_rng(1)
+    c = (O.init_coords(g) + rng.normal(scale=3.0, size=4 * g.n_nodes)).astype(np.float32)
+    L, n, grad = O.stress_loss_grad(g, c, 3000, seed=11, step=2)
+    # the loss as a function of FP64 coordinates: perturb through float32-exact steps
+    idx = rng.choice(4 * g.n_nodes, size=40, replace=False)
+    for k in idx:
+        h = np.float32(2.0 ** (np.floor(np.log2(max(1.0, abs(float(c[k]))))) - 14))
+        cp, cm = c.copy(), c.copy()
+        cp[k] += h
+        cm[k] -= h
+        Lp = O.stress_loss_grad(g, cp, 3000, seed=11, step=2, want_grad=False)[0]
+        Lm = O.stress_loss_grad(g, cm, 3000, seed=11, step=2, want_grad=False)[0]
+        fd = (Lp - Lm) / (float(cp[k]) - float(cm[k]))
+        assert abs(fd - grad[k]) <= 1e-4 * max(abs(grad[k]), 1e-3 * np.abs(grad).max()), (k, fd, grad[k])
+
+
+def test_init_coords_follow_first_visits(tiny_synth, tiny_oracle):
+    g, sg = tiny_oracle, tiny_synth
+    c = O.init_coords(g, seed=5, jitter=10.0)
+    X, Y = c[: 2 * g.n_nodes], c[2 * g.n_nodes:]
+    pos = g.pos
+    seen = set()
+    for s in range(g.S):
+        n = int(int(sg.step_node[s]) & 0x7FFFFFFF)
+        if n in seen:
+            continue
+        seen.add(n)
+        assert X[2 * n] == np.float32(pos[s]) and X[2 * n + 1] == np.float32(pos[s] + int(sg.node_len[n]))
+    assert np.all(np.abs(Y) <= 5.0) and abs(float(Y.mean())) < 0.5
