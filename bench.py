@@ -1,0 +1,266 @@
+"""Benchmark: PG-SGD layout term updates/s and HBM GB/s on one MI355X.
+
+Workload: the chromosome-scale synthetic variation graph (5M-node backbone,
+node lengths 1+Geometric(0.05), 90 haplotype paths, ~4.1e8 path steps), 30
+iterations of 10 x S term updates each (Alg. 1).  One step = one full layout
+of that graph from its initial layout (init kernel + 30 layout launches); the
+inputs are resident in HBM before the timed region.  After the timed steps the
+sampled path stress (Eq. 2) of the final layout is measured on the GPU and
+compared with the oracle's stored value for the same graph when there is one.
+
+Prints ONE JSON line (rank 0).  Extra objects:
+  roofline      the dominant kernel (k_layout_iter): algorithmic bytes per
+                launch (64 B per term) / average launch duration from HIP events
+                on the launch stream, against the 8 TB/s HBM peak; traffic from
+                the committed rocprofv3 counter summary when it was taken on the
+                current kernel source, else null
+  cpu_baseline  the CPU oracle (threaded Hogwild mode) on a bounded sample of
+                the same workload on this host
+
+Options: --profile runs a short fixed sequence for rocprofv3 counter passes
+(two layout iterations plus a 1 GiB calibration copy) and prints nothing else.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_PER_TERM = 64  # 2 step records (16 B each) + 2 endpoints read (8 B each) + written (8 B each)
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
+PROFILE_COMMANDS = """rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline
+rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o fetch -- python3 bench.py --profile
+rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o write -- python3 bench.py --profile
+rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d gpurun_out/prof_tcc -o tcc -- python3 bench.py --profile
+python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv"""
+KERNEL_SOURCES = ["paper_2409_00876_amd/csrc/layout_kernels.hip", "paper_2409_00876_amd/csrc/device.h",
+                  "paper_2409_00876_amd/csrc/internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(terms_per_launch: int):
+    """Measured HBM traffic per launch from the committed counter summary, if it
+    was taken on the current kernel source and workload."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None, None
+    if rec.get("kernel_source_sha") != kernel_source_hash() or rec.get("terms_per_launch") != terms_per_launch:
+        return None, rec
+    return rec.get("traffic_bytes_per_launch"), rec
+
+
+def _read_counters(path):
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: str, command: str) -> None:
+    """Turns the rocprofv3 outputs of one --profile sequence into the committed
+    summaries: profiles/layout_iter_chromosome_counters.json (read by this
+    benchmark) and profiles/layout_iter_chromosome_counters.md."""
+    import csv
+    copy_bytes = 1 << 30
+
+    def per_kernel(rows, counter):
+        lay = [v for k, c, v in rows if c == counter and k.startswith("pgsgd::k_layout_iter")]
+        cp = [v for k, c, v in rows if c == counter and "copyBuffer" in k]
+        return lay, max(cp)  # the 1 GiB calibration copy is the largest copy
+
+    f_lay, f_copy = per_kernel(_read_counters(fetch_csv), "FETCH_SIZE")
+    w_lay, w_copy = per_kernel(_read_counters(write_csv), "WRITE_SIZE")
+    tcc = _read_counters(tcc_csv)
+    hits = [v for k, c, v in tcc if c == "TCC_HIT_sum" and k.startswith("pgsgd::k_layout_iter")]
+    miss = [v for k, c, v in tcc if c == "TCC_MISS_sum" and k.startswith("pgsgd::k_layout_iter")]
+    f_factor = copy_bytes / (f_copy * 1024)
+    w_factor = copy_bytes / (w_copy * 1024)
+    fetch_b = [v * 1024 * f_factor for v in f_lay]
+    write_b = [v * 1024 * w_factor for v in w_lay]
+    stats = None
+    for name in os.listdir(trace_dir):
+        if name.endswith("kernel_stats.csv"):
+            with open(os.path.join(trace_dir, name)) as f:
+                for r in csv.DictReader(f):
+                    if r["Name"].startswith("pgsgd::k_layout_iter"):
+                        stats = r
+    import synth
+    sg = synth.config_graph("chromosome")
+    T = 10 * sg.n_steps
+    avg_ns = float(stats["AverageNs"])
+    traffic = (sum(fetch_b) + sum(write_b)) / len(fetch_b)
+    rec = {"kernel": "k_layout_iter", "workload": "chromosome", "terms_per_launch": T,
+           "kernel_source_sha": kernel_source_hash(), "command": command,
+           "trace_avg_launch_ms": avg_ns / 1e6, "trace_calls": int(stats["Calls"]),
+           "fetch_calibration_factor": f_factor, "write_calibration_factor": w_factor,
+           "fetch_bytes_per_launch": sum(fetch_b) / len(fetch_b), "write_bytes_per_launch": sum(write_b) / len(write_b),
+           "traffic_bytes_per_launch": traffic, "traffic_bytes_per_term": traffic / T,
+           "traffic_gbs_at_trace_duration": traffic / (avg_ns * 1e-9) / 1e9,
+           "l2_hit_rate": sum(hits) / (sum(hits) + sum(miss)),
+           "l2_misses_per_term": sum(miss) / len(miss) / T}
+    out = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    md = out[:-5] + ".md"
+    with open(md, "w") as f:
+        f.write(f"# k_layout_iter, chromosome workload: rocprofv3 summary\n\n")
+        f.write(f"Commands (from the repository root, with TMPDIR=/tmp):\n\n```\n{command}\n```\n\n")
+        f.write("| quantity | value |\n|---|---|\n")
+        f.write(f"| kernel-trace calls / average duration | {rec['trace_calls']} / {rec['trace_avg_launch_ms']:.2f} ms |\n")
+        f.write(f"| terms per launch | {T:,} |\n")
+        f.write(f"| FETCH_SIZE calibration (1 GiB copy) | x{f_factor:.4f} |\n")
+        f.write(f"| WRITE_SIZE calibration (1 GiB copy) | x{w_factor:.4f} |\n")
+        f.write(f"| fetched bytes per launch (calibrated) | {rec['fetch_bytes_per_launch'] / 1e9:.1f} GB |\n")
+        f.write(f"| written bytes per launch (calibrated) | {rec['write_bytes_per_launch'] / 1e9:.1f} GB |\n")
+        f.write(f"| traffic per term | {rec['traffic_bytes_per_term']:.1f} B (algorithmic: 64 B) |\n")
+        f.write(f"| traffic rate at the traced duration | {rec['traffic_gbs_at_trace_duration']:.0f} GB/s "
+                f"({rec['traffic_gbs_at_trace_duration'] / HBM_PEAK_GBS:.1%} of 8 TB/s) |\n")
+        f.write(f"| L2 (TCC) hit rate | {rec['l2_hit_rate']:.1%} |\n")
+        f.write(f"| L2 misses per term | {rec['l2_misses_per_term']:.2f} |\n")
+        f.write(f"\nkernel source sha256[:16]: `{rec['kernel_source_sha']}`\n")
+    print(json.dumps(rec, indent=1))
+
+
+def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:
+    import oracle as O
+    og = O.Graph.from_synth(sg)
+    threads = min(16, len(os.sched_getaffinity(0)))
+    c = O.init_coords(og)
+    n0 = 2_000_000
+    t = time.time()
+    O.layout(og, c, first_iter=0, last_iter=1, threads=threads, term_limit=n0)
+    rate = n0 / max(time.time() - t, 1e-6)
+    n1 = int(min(max(rate * seconds_target, n0), 10 * og.S))
+    c = O.init_coords(og)
+    t = time.time()
+    O.layout(og, c, first_iter=0, last_iter=1, threads=threads, term_limit=n1)
+    dt = time.time() - t
+    return {"value": n1 / dt, "unit": "term updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n1} term updates of iteration 0 of the same graph, oracle Hogwild mode "
+                      f"({threads} threads), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chromosome", choices=["tiny", "mid", "chromosome"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--summarize", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "TCC_CSV"),
+                    help="write the committed counter summaries from rocprofv3 outputs (no GPU)")
+    a = ap.parse_args()
+    if a.summarize:
+        summarize_counters(*a.summarize, command=PROFILE_COMMANDS)
+        return
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU (the layout of one graph is not "
+                                   "sharded); run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+
+    dev = torch.device("cuda:0")
+    sg = synth.config_graph(a.workload)
+    g = P.Graph.from_synth(sg, device=0)
+    coords = g.new_coords()
+    params = P.LayoutParams()
+    T = params.terms_per_step * g.n_steps
+
+    if a.profile:
+        P.init_coords(g, coords)
+        P.layout(g, coords, first_iter=0, last_iter=1)
+        P.layout(g, coords, first_iter=15, last_iter=16)
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "done", "terms_per_launch": T, "copy_bytes": x.numel() * 4}))
+        return
+
+    # warm-up (not timed)
+    for _ in range(a.warmup):
+        P.init_coords(g, coords)
+        P.layout(g, coords, seed=params.seed + 1)
+    torch.cuda.synchronize()
+
+    iter_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        P.init_coords(g, coords)
+        iter_ms.append(P.layout_timed(g, coords, params))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    n_terms = a.steps * params.n_iters * T
+    value = n_terms / wall
+    all_ms = [float(x) for arr in iter_ms for x in arr]
+    avg_ms = sum(all_ms) / len(all_ms)
+    achieved = ALG_BYTES_PER_TERM * T / (avg_ms * 1e-3) / 1e9
+    traffic, counters = stored_traffic(T)
+
+    sps = P.path_stress(g, coords, pairs_per_step=10, seed=7)
+    oracle_sps = None
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_sps_{a.workload}_seed{params.seed}_t16.json")
+    for cand in (gold, gold.replace("_t16", "_t1")):
+        if os.path.exists(cand):
+            with open(cand) as f:
+                oracle_sps = json.load(f)
+            break
+
+    rec = {
+        "metric": "PG-SGD term updates/s + HBM GB/s at equal sampled path stress vs CPU oracle",
+        "value": value,
+        "unit": "term updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}-scale synthetic variation graph", "backbone": sg.stats["backbone"],
+                   "paths": g.n_paths, "nodes": g.n_nodes, "path_steps": g.n_steps, "d_max_nt": g.d_max,
+                   "iterations": params.n_iters, "terms_per_iteration": T, "zipf_theta": params.zipf_theta,
+                   "zipf_window": params.zipf_window, "coords": "fp32"},
+        "hbm_gbs_algorithmic": ALG_BYTES_PER_TERM * value / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_layout_iter", "avg_launch_ms": avg_ms,
+                     "bytes_per_term_algorithmic": ALG_BYTES_PER_TERM},
+        "sps": {"mean": sps["mean"], "ci_lo": sps["ci_lo"], "ci_hi": sps["ci_hi"], "pairs_per_step": 10,
+                "oracle_mean": oracle_sps["sps_mean"] if oracle_sps else None,
+                "ratio_to_oracle": sps["mean"] / oracle_sps["sps_mean"] if oracle_sps else None},
+    }
+    if traffic is not None:
+        rec["roofline"]["traffic_frac"] = traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if not a.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(sg)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

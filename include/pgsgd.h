@@ -1,0 +1,328 @@
+/*
+ * pgsgd.h — C ABI of the MI355X (gfx950) PG-SGD pangenome graph layout library.
+ *
+ * The library computes the path-guided SGD layout of a variation graph
+ * ("Rapid GPU-Based Pangenome Graph Layout", SC24, Alg. 1 in Section
+ * "Path-Guided SGD Algorithm") and its quality metric, the sampled path stress
+ * (Eq. 2 and its 95% confidence interval, Section "A Scalable Metric: Sampled
+ * Path Stress").  Only the paths and the node lengths of the graph enter the
+ * layout (Alg. 1 reads P and L; the lean structure of Section "CUDA Kernel for
+ * Pangenome Graph Layout" keeps node lengths only), so edges are not part of
+ * this interface.
+ *
+ * Conventions used by every entry point:
+ *   - Every call returns a pgsgd_status; nothing throws across the ABI.  On an
+ *     error, pgsgd_last_error() returns a message for the calling thread.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *     memory on the graph's device (for example torch tensor data_ptr()).
+ *   - Coordinates use the layout [2][n_nodes][2] in float32: the X plane, then
+ *     the Y plane; endpoint e (0 = start, 1 = end) of node n is element 2n+e of
+ *     a plane.  Coordinate buffers are owned by the caller, must be contiguous
+ *     and 16-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device work is
+ *     enqueued asynchronously on it unless a function says it synchronises.
+ *   - One graph handle must not be used from two streams at the same time.
+ *   - All argument validation happens on the host before any device work, so
+ *     every validation error is reported without touching the GPU.
+ *
+ * Random choices follow a counter-based definition (Philox4x32-10, Salmon et
+ * al., SC'11): draw = Philox(counter = (t mod 2^32, t >> 32, word2,
+ * stream << 24 | graph_id), key = (seed mod 2^32, seed >> 32)), with stream 0
+ * for layout terms (word2 = iteration), 1 for sampled-path-stress pairs
+ * (word2 = 0), 2 for differentiable-loss pairs (word2 = optimiser step) and 3
+ * for the initial layout jitter.  Results therefore do not depend on the launch
+ * configuration, and a run split into iteration ranges samples exactly the
+ * same terms as one full run.
+ */
+#ifndef PGSGD_H
+#define PGSGD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pgsgd_status;
+enum {
+  PGSGD_OK = 0,
+  PGSGD_ERR_INVALID_ARG = -1, /* null pointer, malformed graph, bad parameter */
+  PGSGD_ERR_RANGE = -2,       /* a size beyond what the library supports */
+  PGSGD_ERR_OOM = -3,         /* device or host allocation failed */
+  PGSGD_ERR_DEVICE = -4,      /* a HIP runtime error (no device, launch failure, ...) */
+  PGSGD_ERR_UNSUPPORTED = -5  /* a valid request this build does not implement */
+};
+
+/* Message of the last failing call on this thread ("" if none).  The pointer
+ * stays valid until the next call on this thread. */
+const char *pgsgd_last_error(void);
+const char *pgsgd_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Graph                                                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct pgsgd_graph pgsgd_graph;
+
+typedef struct {
+  uint64_t n_steps;       /* S = total path steps (sum over paths of |p|) */
+  uint32_t n_nodes;
+  uint32_t n_paths;
+  int64_t d_max;          /* longest path, in nucleotides */
+  uint64_t device_bytes;  /* device memory held by the handle */
+  int32_t device;
+  uint32_t max_path_steps;
+} pgsgd_graph_info;
+
+/*
+ * Copies a variation graph to the device.
+ *   n_nodes       number of nodes, < 2^31
+ *   node_len      host, n_nodes entries: nucleotide length of each node, >= 1
+ *   n_paths       number of paths, >= 1 and <= 2^20 (kernels stage the path
+ *                 offsets in LDS: a launch returns UNSUPPORTED when they do not
+ *                 fit the per-block LDS limit, about 3,500 paths on gfx950)
+ *   path_offsets  host, n_paths+1 entries: CSR offsets of each path's steps in
+ *                 step_node; [0] = 0, non-decreasing; S = path_offsets[n_paths]
+ *                 < 2^40 and every path has fewer than 2^32 steps.  Empty paths
+ *                 are allowed (they are never sampled).
+ *   step_node     host, S entries: node id of each step, bit 31 set for a
+ *                 reverse-strand visit
+ *   step_pos      host or NULL: nucleotide offset of each step from the start
+ *                 of its path.  NULL means "compute it": the sum of the lengths
+ *                 of the earlier steps of the path.  If given it must equal
+ *                 those sums (PGSGD_ERR_INVALID_ARG otherwise).
+ *   device        HIP device ordinal
+ *   out           receives the handle (NULL on error)
+ * The host arrays are copied; the caller may free them once the call returns.
+ * Errors: INVALID_ARG (null pointer, node id >= n_nodes, length 0, offsets not
+ * monotone, step_pos mismatch, n_paths = 0), RANGE (sizes above the limits,
+ * a path longer than 2^62 nt), OOM, DEVICE.  Synchronous.
+ */
+pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t *node_len, uint32_t n_paths,
+                                const uint64_t *path_offsets, const uint32_t *step_node, const int64_t *step_pos,
+                                int device, pgsgd_graph **out);
+/* Frees the handle and its device memory (synchronises the device first).  NULL-safe. */
+void pgsgd_graph_destroy(pgsgd_graph *g);
+/* Fills *out (host).  Errors: INVALID_ARG on NULL. */
+pgsgd_status pgsgd_graph_get_info(const pgsgd_graph *g, pgsgd_graph_info *out);
+
+/* ------------------------------------------------------------------------- */
+/* Layout parameters (Alg. 1 inputs: schedule S and N_iters)                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t n_iters;           /* N_iters (30); one kernel launch per iteration */
+  uint32_t terms_per_step;    /* term updates per iteration = terms_per_step * S (Alg. 1: 10) */
+  double eta_max;             /* first learning rate; <= 0 selects d_max^2 */
+  double eta_min;             /* last learning rate (0.01) */
+  double zipf_theta;          /* power-law exponent of the cooling partner (0.99) */
+  uint32_t zipf_window;       /* largest power-law hop, in steps (1000), 1..65535 */
+  uint32_t graph_id;          /* enters the random counter; < 2^24 */
+  uint64_t seed;              /* Philox key */
+  uint32_t first_iter;        /* run iterations [first_iter, last_iter) ... */
+  uint32_t last_iter;         /* ... ; last_iter = 0 means n_iters */
+  uint32_t max_inflight_waves;/* cap on concurrently running 64-term groups; 0 = automatic */
+  uint32_t flags;             /* reserved, must be 0 */
+} pgsgd_params;
+
+/* Fills the defaults listed above (seed 24301, graph_id 0). */
+void pgsgd_params_default(pgsgd_params *p);
+
+/*
+ * The learning rate of every iteration, as the float32 values the kernels use:
+ * eta_t = eta_max * exp(-lambda t), lambda = ln(eta_max/eta_min)/(N-1), in FP64
+ * then rounded (Alg. 1 input S; exponential annealing of Zheng et al., the
+ * update rule the paper follows).  d_max is used when eta_max <= 0.  eta_out:
+ * host, n_iters entries.  Host only.
+ */
+pgsgd_status pgsgd_schedule(const pgsgd_params *p, int64_t d_max, float *eta_out);
+
+/*
+ * The power-law (Zipf) cumulative table the cooling branch samples from
+ * (Alg. 1, "RandomSelect(p, Powerlaw)"): C[0] = 0 and, for k = 1..W,
+ * C[k] = floor(F[k]/F[W] * (2^32-1)) with F[k] = sum_{z=1..k} z^-theta summed
+ * in FP64 in increasing z.  C_out: host, W+1 entries.  Host only.
+ */
+pgsgd_status pgsgd_zipf_table(double theta, uint32_t W, uint32_t *C_out);
+
+/* ------------------------------------------------------------------------- */
+/* Layout                                                                     */
+/* ------------------------------------------------------------------------- */
+/*
+ * Initial layout: node n starts on the x axis at the path coordinate of its
+ * first visit (paths in order): X[2n] = pos, X[2n+1] = pos + len (0 for nodes
+ * never visited); Y[2n+e] = jitter * (u - 1/2), u = (r0 >> 8) / 2^24 from
+ * Philox stream 3 at counter 2n+e with this seed and graph_id.  coords: device,
+ * overwritten.  Async.
+ */
+pgsgd_status pgsgd_init_coords(pgsgd_graph *g, uint64_t seed, uint32_t graph_id, float jitter, float *coords,
+                               void *stream);
+
+/*
+ * Runs iterations [first_iter, last_iter) of the PG-SGD layout (Alg. 1) in
+ * place on coords (device).  Each iteration is one kernel launch covering
+ * terms_per_step * S term updates, run concurrently with unlocked updates
+ * (Hogwild, Section "Data-level Parallelism").  Term t of iteration it:
+ *   i  = floor(u64 * S / 2^64), u64 = r0 | r1 << 32 (a uniform global step:
+ *        "path with probability proportional to |p|, then a step of it");
+ *   cooling = (it >= floor(N/2)) or bit 3 of r3 of term t - (t mod 64)
+ *        (one coin per aligned group of 64 terms, as in warp merging);
+ *   cooling: j = i +/- z, direction bit 2 of r3 (flipped when there is no room
+ *        that way), z ~ Zipf(theta) on [1, min(W, room)] drawn from r2 with the
+ *        table of pgsgd_zipf_table; a single-step path is skipped;
+ *   otherwise: j = start(p) + floor(r2 * |p| / 2^32);
+ *   endpoints e_i = bit 0, e_j = bit 1 of r3; endpoint e of step s lies at path
+ *        coordinate pos[s] + len * (e XOR reverse[s]); d_ref = |difference|;
+ *   terms with the same coordinate slot, d_ref = 0 or coincident points are
+ *        skipped; otherwise mu = min(eta / d^2, 1) and both points move by
+ *        mu * (|v_i - v_j| - d) / 2 towards (or away from) each other.
+ * Async.  A graph with S = 0 returns OK without work.
+ * Errors: INVALID_ARG (NULL, flags != 0, zipf_window out of range, graph_id >=
+ * 2^24, first_iter > last_iter), RANGE (term count >= 2^48), DEVICE.
+ */
+pgsgd_status pgsgd_layout(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);
+
+/*
+ * pgsgd_layout with measurement: HIP events recorded on `stream` right before
+ * and after every iteration's kernel launch give that launch's duration in
+ * milliseconds, written to iter_ms (host, last_iter - first_iter entries).
+ * Synchronises the stream.  Same errors as pgsgd_layout, plus INVALID_ARG
+ * when iter_ms is NULL.
+ */
+pgsgd_status pgsgd_layout_timed(pgsgd_graph *g, const pgsgd_params *p, float *coords, float *iter_ms,
+                                void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Sampled path stress (Eq. 2)                                               */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double mean;       /* sampled path stress: mean of ((|v_i - v_j| - d)/d)^2 */
+  double ci_lo;      /* mean - 1.96 sigma / sqrt(n) */
+  double ci_hi;      /* mean + 1.96 sigma / sqrt(n) */
+  double stddev;     /* sigma from a second pass: sqrt(sum (s - mean)^2 / (n - 1)) */
+  double sum;        /* sum of the stress terms (pass 1) */
+  double sumsq_dev;  /* sum of squared deviations (pass 2) */
+  uint64_t n_valid;  /* pairs with d > 0 */
+  uint64_t n_skipped;/* pairs with d = 0 (left out of the mean) */
+} pgsgd_stress_result;
+
+/*
+ * Sampled path stress with its 95% confidence interval (Eq. 2; two passes, the
+ * second for sigma).  Path p receives exactly pairs_per_step * |p| pairs; pair
+ * q of path p (q in [m*off[p], m*off[p+1])) draws Philox stream 1 at counter
+ * q: i = start + floor(u64 * |p| / 2^64), j = start + floor(r2 * |p| / 2^32),
+ * e_i = bit 0, e_j = bit 1 of r3.  All paths are pooled.  Stress terms are
+ * computed in FP64 from the float32 coordinates.  coords: device; out: host.
+ * Synchronises the stream.  Errors: INVALID_ARG, DEVICE.
+ */
+pgsgd_status pgsgd_path_stress(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
+                               uint32_t graph_id, pgsgd_stress_result *out, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Differentiable form: sampled stress as a loss                             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Forward: L = (1/n_valid) sum_q ((|v_a - v_b| - d)/d)^2 over n_pairs pairs
+ * drawn with the cooling (power-law) sampler of pgsgd_layout from Philox stream
+ * 2, counter word 2 = step, with p->seed, p->graph_id, p->zipf_theta and
+ * p->zipf_window.  Skipped pairs (single-step path, same slot, d = 0) do not
+ * count.  Writes loss_dev[0] (device float32) and n_valid_dev[0] (device
+ * uint64).  Async.
+ */
+pgsgd_status pgsgd_stress_forward(pgsgd_graph *g, const pgsgd_params *p, const float *coords, uint64_t n_pairs,
+                                  uint32_t step, float *loss_dev, uint64_t *n_valid_dev, void *stream);
+/*
+ * Backward (adjoint of the forward with the same arguments): ADDS
+ * grad_out_dev[0] * dL/dcoords into grad_coords (device, [2][n_nodes][2]
+ * float32) with float32 atomics; dL/dv_a = (2/n_valid)(mag - d)/d^2 (v_a - v_b)/mag,
+ * dL/dv_b = -dL/dv_a, zero when mag = 0.  n_valid_dev is the forward's count.
+ * Async.
+ */
+pgsgd_status pgsgd_stress_backward(pgsgd_graph *g, const pgsgd_params *p, const float *coords, uint64_t n_pairs,
+                                   uint32_t step, const float *grad_out_dev, const uint64_t *n_valid_dev,
+                                   float *grad_coords, void *stream);
+/*
+ * One Adam step (Kingma and Ba, 2015) over n float32 parameters in place:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; x -= lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
+ * x, grad, m, v: device.  t >= 1.  Async.
+ */
+pgsgd_status pgsgd_adam_step(float *x, const float *grad, float *m, float *v, uint64_t n, float lr, float beta1,
+                             float beta2, float eps, uint32_t t, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Batched form: many graphs in one persistent, graph-captured launch per    */
+/* iteration                                                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t block_threads;   /* 64..1024, multiple of 64 */
+  uint32_t groups_per_item; /* consecutive 64-term groups a wave takes per work item, >= 1 */
+  uint32_t blocks_per_cu;   /* persistent blocks per compute unit, >= 1 */
+  uint32_t max_blocks;      /* cap on the grid (0 = none): bounds concurrent updates for small graphs */
+} pgsgd_tune;
+
+typedef struct pgsgd_batch pgsgd_batch;
+
+/*
+ * Prepares a batched layout of n graphs (all on the same device); work items
+ * are interleaved over the graphs in 32 phases so that concurrent updates are
+ * spread over all graphs in proportion to their size.  Graph k uses
+ * p->graph_id + k as its graph_id (so its terms equal those of a plain
+ * pgsgd_layout with that graph_id) and its own schedule from its own d_max
+ * when p->eta_max <= 0.  coords[k] is graph k's coordinate buffer (device).
+ * The n_iters launches are captured once in a HIP graph.  tune = NULL picks
+ * defaults.  The sampled terms do not depend on tune.  max_inflight_waves is
+ * ignored (the persistent grid sets the concurrency).
+ */
+pgsgd_status pgsgd_batch_create(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
+                                float *const *coords, const pgsgd_tune *tune, pgsgd_batch **out);
+/* Launches the captured iterations [first_iter, last_iter) on stream.  Async. */
+pgsgd_status pgsgd_batch_run(pgsgd_batch *b, void *stream);
+/* Frees the batch (synchronises the device first).  NULL-safe. */
+void pgsgd_batch_destroy(pgsgd_batch *b);
+/* One-shot: create, run, synchronise, destroy. */
+pgsgd_status pgsgd_layout_batched(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
+                                  float *const *coords, const pgsgd_tune *tune, void *stream);
+/*
+ * Times candidate tunings on one iteration of the batch (on scratch copies of
+ * the coordinates, which are left unchanged) and writes the fastest to *best.
+ * On entry best->max_blocks is a grid cap kept in every candidate (0 = none).
+ * ms_out (host, may be NULL) receives the best time.  Synchronous.
+ */
+pgsgd_status pgsgd_autotune_batched(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
+                                    float *const *coords, pgsgd_tune *best, float *ms_out, void *stream);
+
+/*
+ * Parity hook for the batched kernel: runs iteration iter of the batch in a
+ * recording mode that writes every sampled term of graph k (t in [0,
+ * terms_per_step * S_k)) to i_out[k], j_out[k], flags_out[k] (device arrays of
+ * that length, flags as in pgsgd_sample_terms) instead of updating
+ * coordinates.  Uses the same kernel, work mapping and tune as
+ * pgsgd_batch_run.  Synchronises the stream.
+ */
+pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p, uint32_t iter,
+                                      const pgsgd_tune *tune, uint64_t *const *i_out, uint64_t *const *j_out,
+                                      uint8_t *const *flags_out, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Parity hooks: the sampling and the update as separate kernels             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Writes the terms t in [t_begin, t_begin + count) of iteration iter, sampled
+ * exactly as pgsgd_layout samples them: i_out, j_out (device uint64) and
+ * flags_out (device uint8: bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped).
+ * Async.
+ */
+pgsgd_status pgsgd_sample_terms(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,
+                                uint64_t count, uint64_t *i_out, uint64_t *j_out, uint8_t *flags_out,
+                                void *stream);
+/*
+ * Applies count given terms (device arrays as written by pgsgd_sample_terms)
+ * with learning rate eta, one thread per term, with the update of
+ * pgsgd_layout.  Terms touching the same slot race.  Async.
+ */
+pgsgd_status pgsgd_apply_terms(pgsgd_graph *g, float eta, const uint64_t *i, const uint64_t *j,
+                               const uint8_t *flags, uint64_t count, float *coords, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGSGD_H */

@@ -1,0 +1,399 @@
+"""PG-SGD pangenome graph layout on MI355X (gfx950).
+
+A thin Python binding over ``libpgsgd.so``: it checks torch tensors (device,
+dtype, contiguity), passes their device pointers and the current HIP stream to
+the C ABI, and wraps the differentiable sampled stress as a
+``torch.autograd.Function``.  Every step of the computation runs in the
+library's HIP kernels; torch only supplies device memory and streams.
+
+Method: "Rapid GPU-Based Pangenome Graph Layout" (SC24), Alg. 1 (layout loop)
+and Eq. 2 (sampled path stress).
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from ._lib import (GraphInfo, Params, PgsgdError, StressResult, Tune, check, lib)  # noqa: F401
+
+__all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "schedule", "zipf_table",
+           "sample_terms", "apply_terms", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
+           "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
+
+
+def _stream(torch, device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _np_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _check_tensor(t, dtype, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+@dataclass
+class LayoutParams:
+    """Alg. 1 inputs; defaults follow the paper (30 iterations, 10 terms per step)."""
+    n_iters: int = 30
+    terms_per_step: int = 10
+    eta_max: float = 0.0        # <= 0: d_max^2
+    eta_min: float = 0.01
+    zipf_theta: float = 0.99
+    zipf_window: int = 1000
+    graph_id: int = 0
+    seed: int = 24301
+    first_iter: int = 0
+    last_iter: int = 0
+    max_inflight_waves: int = 0
+    flags: int = 0
+
+    def to_c(self) -> Params:
+        p = Params()
+        for f in Params._fields_:
+            setattr(p, f[0], getattr(self, f[0]))
+        return p
+
+
+def _params(params, kw) -> Params:
+    if params is None:
+        params = LayoutParams(**kw)
+    elif kw:
+        params = LayoutParams(**{**params.__dict__, **kw})
+    return params.to_c()
+
+
+class Graph:
+    """A variation graph resident on one GPU (node lengths and path steps)."""
+
+    def __init__(self, node_len, path_off, step_node, step_pos=None, device: int = 0):
+        node_len = np.ascontiguousarray(node_len, dtype=np.uint32)
+        path_off = np.ascontiguousarray(path_off, dtype=np.uint64)
+        step_node = np.ascontiguousarray(step_node, dtype=np.uint32)
+        pos = None if step_pos is None else np.ascontiguousarray(step_pos, dtype=np.int64)
+        h = ctypes.c_void_p()
+        check(lib().pgsgd_graph_create(len(node_len), _np_ptr(node_len), len(path_off) - 1, _np_ptr(path_off),
+                                       _np_ptr(step_node) if step_node.size else None,
+                                       _np_ptr(pos) if pos is not None else None, int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+        info = GraphInfo()
+        check(lib().pgsgd_graph_get_info(h, ctypes.byref(info)))
+        self.n_nodes = int(info.n_nodes)
+        self.n_paths = int(info.n_paths)
+        self.n_steps = int(info.n_steps)
+        self.d_max = int(info.d_max)
+        self.device_bytes = int(info.device_bytes)
+
+    @classmethod
+    def from_synth(cls, sg, device: int = 0):
+        return cls(sg.node_len, sg.path_off, sg.step_node, device=device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib().pgsgd_graph_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_coords(self):
+        import torch
+        return torch.empty(4 * self.n_nodes, dtype=torch.float32, device=f"cuda:{self.device}")
+
+
+def schedule(params: LayoutParams | None = None, d_max: int = 1, **kw) -> np.ndarray:
+    p = _params(params, kw)
+    out = np.zeros(max(1, p.n_iters), dtype=np.float32)
+    check(lib().pgsgd_schedule(ctypes.byref(p), int(d_max), _np_ptr(out)))
+    return out[: p.n_iters]
+
+
+def zipf_table(theta: float = 0.99, window: int = 1000) -> np.ndarray:
+    out = np.zeros(window + 1, dtype=np.uint32)
+    check(lib().pgsgd_zipf_table(float(theta), int(window), _np_ptr(out)))
+    return out
+
+
+def init_coords(g: Graph, coords, seed: int = 5, jitter: float = 10.0, graph_id: int = 0):
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    check(lib().pgsgd_init_coords(g.handle, int(seed), int(graph_id), float(jitter), ctypes.c_void_p(coords.data_ptr()),
+                                  _stream(torch, coords.device)))
+    return coords
+
+
+def layout(g: Graph, coords, params: LayoutParams | None = None, **kw):
+    """Runs Alg. 1 in place on coords (float32 [2][n_nodes][2] on the GPU), async on the current stream."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    p = _params(params, kw)
+    check(lib().pgsgd_layout(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()),
+                             _stream(torch, coords.device)))
+    return coords
+
+
+def layout_timed(g: Graph, coords, params: LayoutParams | None = None, **kw) -> np.ndarray:
+    """layout() that also returns each iteration's kernel duration in ms (HIP events
+    on the current stream around every launch); synchronises."""
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    p = _params(params, kw)
+    last = p.last_iter or p.n_iters
+    ms = np.zeros(max(1, last - p.first_iter), dtype=np.float32)
+    check(lib().pgsgd_layout_timed(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()), _np_ptr(ms),
+                                   _stream(torch, coords.device)))
+    return ms[: last - p.first_iter]
+
+
+def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, graph_id: int = 0) -> dict:
+    """Sampled path stress (Eq. 2) with CI95; synchronises the current stream."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    r = StressResult()
+    check(lib().pgsgd_path_stress(g.handle, ctypes.c_void_p(coords.data_ptr()), int(pairs_per_step), int(seed),
+                                  int(graph_id), ctypes.byref(r), _stream(torch, coords.device)))
+    return {f[0]: getattr(r, f[0]) for f in StressResult._fields_}
+
+
+def sample_terms(g: Graph, iter: int, t_begin: int, count: int, params: LayoutParams | None = None, **kw):
+    """The terms layout() samples: (i, j, flags) as device tensors (uint64 as int64, uint8)."""
+    import torch
+    p = _params(params, kw)
+    dev = f"cuda:{g.device}"
+    i = torch.empty(count, dtype=torch.int64, device=dev)
+    j = torch.empty(count, dtype=torch.int64, device=dev)
+    f = torch.empty(count, dtype=torch.uint8, device=dev)
+    check(lib().pgsgd_sample_terms(g.handle, ctypes.byref(p), int(iter), int(t_begin), int(count),
+                                   ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
+                                   ctypes.c_void_p(f.data_ptr()), _stream(torch, dev)))
+    return i, j, f
+
+
+def apply_terms(g: Graph, coords, eta: float, i, j, f):
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    _check_tensor(i, torch.int64, None, "i")
+    _check_tensor(j, torch.int64, i.numel(), "j")
+    _check_tensor(f, torch.uint8, i.numel(), "flags")
+    check(lib().pgsgd_apply_terms(g.handle, float(eta), ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
+                                  ctypes.c_void_p(f.data_ptr()), int(i.numel()), ctypes.c_void_p(coords.data_ptr()),
+                                  _stream(torch, coords.device)))
+    return coords
+
+
+# ---------------------------------------------------------------------------
+# Differentiable form
+# ---------------------------------------------------------------------------
+def stress_forward(g: Graph, coords, n_pairs: int, step: int = 0, params: LayoutParams | None = None, **kw):
+    """Returns (loss float32 device scalar, n_valid int64 device scalar)."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    p = _params(params, kw)
+    loss = torch.empty(1, dtype=torch.float32, device=coords.device)
+    nv = torch.empty(1, dtype=torch.int64, device=coords.device)
+    check(lib().pgsgd_stress_forward(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()), int(n_pairs),
+                                     int(step), ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(nv.data_ptr()),
+                                     _stream(torch, coords.device)))
+    return loss, nv
+
+
+def stress_backward(g: Graph, coords, n_pairs: int, step: int, grad_out, n_valid, grad_coords,
+                    params: LayoutParams | None = None, **kw):
+    """Adds grad_out * dL/dcoords into grad_coords."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    _check_tensor(grad_coords, torch.float32, 4 * g.n_nodes, "grad_coords")
+    _check_tensor(grad_out, torch.float32, 1, "grad_out")
+    _check_tensor(n_valid, torch.int64, 1, "n_valid")
+    p = _params(params, kw)
+    check(lib().pgsgd_stress_backward(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()), int(n_pairs),
+                                      int(step), ctypes.c_void_p(grad_out.data_ptr()),
+                                      ctypes.c_void_p(n_valid.data_ptr()), ctypes.c_void_p(grad_coords.data_ptr()),
+                                      _stream(torch, coords.device)))
+    return grad_coords
+
+
+class SampledPathStress(torch.autograd.Function):
+    """Sampled stress over power-law pairs as a differentiable loss.
+
+    ``SampledPathStress.apply(coords, graph, n_pairs, step, params)`` returns a
+    scalar loss.  The backward regenerates the same pairs from their Philox
+    counters (no pair buffer) and scatters the adjoint with float32 atomics.
+    """
+
+    @staticmethod
+    def forward(ctx, coords, graph, n_pairs, step, params=None):
+        loss, nv = stress_forward(graph, coords.detach(), n_pairs, step, params)
+        ctx.save_for_backward(coords.detach(), nv)
+        ctx.graph, ctx.n_pairs, ctx.step, ctx.params = graph, n_pairs, step, params
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        coords, nv = ctx.saved_tensors
+        grad = torch.zeros_like(coords)
+        go = grad_out.reshape(1).to(torch.float32).contiguous()
+        stress_backward(ctx.graph, coords, ctx.n_pairs, ctx.step, go, nv, grad, ctx.params)
+        return grad, None, None, None, None
+
+
+def adam_step(x, grad, m, v, t: int, lr: float = 1.0, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step in place on x (all float32 device tensors of the same size)."""
+    import torch
+    n = x.numel()
+    for name, tt in (("x", x), ("grad", grad), ("m", m), ("v", v)):
+        _check_tensor(tt, torch.float32, n, name)
+    check(lib().pgsgd_adam_step(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), n, float(lr),
+                                float(beta1), float(beta2), float(eps), int(t), _stream(torch, x.device)))
+    return x
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+def _tune_c(tune) -> Tune | None:
+    if tune is None:
+        return None
+    if isinstance(tune, Tune):
+        return tune
+    return Tune(int(tune["block_threads"]), int(tune["groups_per_item"]), int(tune["blocks_per_cu"]),
+                int(tune.get("max_blocks", 0)))
+
+
+def _graph_arrays(graphs, coords_list):
+    import torch
+    if len(graphs) != len(coords_list) or not graphs:
+        raise ValueError("need one coords tensor per graph")
+    for g, c in zip(graphs, coords_list):
+        _check_tensor(c, torch.float32, 4 * g.n_nodes, "coords")
+    gh = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+    ch = (ctypes.c_void_p * len(graphs))(*[c.data_ptr() for c in coords_list])
+    return gh, ch
+
+
+class Batch:
+    """Many graphs laid out together: one persistent launch per iteration, the
+    iterations captured in one HIP graph.  Graph k uses graph_id = params.graph_id + k."""
+
+    def __init__(self, graphs, coords_list, params: LayoutParams | None = None, tune=None, **kw):
+        gh, ch = _graph_arrays(graphs, coords_list)
+        p = _params(params, kw)
+        t = _tune_c(tune)
+        h = ctypes.c_void_p()
+        check(lib().pgsgd_batch_create(gh, len(graphs), ctypes.byref(p), ch,
+                                       ctypes.byref(t) if t is not None else None, ctypes.byref(h)))
+        self._h = h
+        self.graphs, self.coords = list(graphs), list(coords_list)
+        self.device = graphs[0].device
+
+    def run(self):
+        import torch
+        check(lib().pgsgd_batch_run(self._h, _stream(torch, f"cuda:{self.device}")))
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib().pgsgd_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def layout_batched(graphs, coords_list, params: LayoutParams | None = None, tune=None, **kw):
+    import torch
+    gh, ch = _graph_arrays(graphs, coords_list)
+    p = _params(params, kw)
+    t = _tune_c(tune)
+    check(lib().pgsgd_layout_batched(gh, len(graphs), ctypes.byref(p), ch,
+                                     ctypes.byref(t) if t is not None else None,
+                                     _stream(torch, f"cuda:{graphs[0].device}")))
+
+
+def batch_sample_terms(graphs, iter: int, params: LayoutParams | None = None, tune=None, **kw):
+    """The terms the batched kernel samples in iteration ``iter``, per graph: a
+    list of (i, j, flags) device tensors of length terms_per_step * S_k."""
+    p = _params(params, kw)
+    dev = f"cuda:{graphs[0].device}"
+    outs = []
+    for g in graphs:
+        T = p.terms_per_step * g.n_steps
+        outs.append((torch.empty(T, dtype=torch.int64, device=dev), torch.empty(T, dtype=torch.int64, device=dev),
+                     torch.empty(T, dtype=torch.uint8, device=dev)))
+    n = len(graphs)
+    gh = (ctypes.c_void_p * n)(*[g.handle.value for g in graphs])
+    ih = (ctypes.c_void_p * n)(*[o[0].data_ptr() for o in outs])
+    jh = (ctypes.c_void_p * n)(*[o[1].data_ptr() for o in outs])
+    fh = (ctypes.c_void_p * n)(*[o[2].data_ptr() for o in outs])
+    t = _tune_c(tune)
+    check(lib().pgsgd_batch_sample_terms(gh, n, ctypes.byref(p), int(iter), ctypes.byref(t) if t is not None else None,
+                                         ih, jh, fh, _stream(torch, dev)))
+    return outs
+
+
+def _tune_cache_path() -> str:
+    return os.environ.get("PGSGD_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "pgsgd_tune.json"))
+
+
+def autotune(graphs, coords_list, params: LayoutParams | None = None, use_cache: bool = True, max_blocks: int = 0,
+             **kw) -> dict:
+    """Picks block shape and work per wave for a batch by timing candidates
+    (native tuner); results are cached per workload signature in a JSON file
+    (PGSGD_TUNE_CACHE)."""
+    import torch
+    p = _params(params, kw)
+    sig = "|".join([torch.cuda.get_device_name(graphs[0].device), str(len(graphs)),
+                    str(sum(g.n_steps for g in graphs)), str(max(g.n_paths for g in graphs)),
+                    str(p.terms_per_step), str(p.zipf_window), str(max_blocks)])
+    path = _tune_cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if sig in cache:
+            return dict(cache[sig], cached=True)
+    gh, ch = _graph_arrays(graphs, coords_list)
+    best = Tune(0, 0, 0, int(max_blocks))
+    ms = ctypes.c_float()
+    check(lib().pgsgd_autotune_batched(gh, len(graphs), ctypes.byref(p), ch, ctypes.byref(best), ctypes.byref(ms),
+                                       _stream(torch, f"cuda:{graphs[0].device}")))
+    res = {"block_threads": best.block_threads, "groups_per_item": best.groups_per_item,
+           "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks, "ms": ms.value}
+    if use_cache:
+        cache[sig] = res
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return dict(res, cached=False)

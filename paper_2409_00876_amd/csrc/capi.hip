@@ -1,0 +1,1071 @@
+// Host runtime and C ABI of the PG-SGD layout library (see include/pgsgd.h).
+//
+// Responsibilities: graph validation (all on the host, before any device
+// work), packing of path steps into 16-byte records and their chunked upload
+// through pinned staging buffers, the learning-rate schedule and power-law
+// table, launch shapes, the two-pass sampled path stress, the differentiable
+// loss, and the batched form (HIP-graph capture and autotuning).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pgsgd.h"
+#include "device.h"
+#include "internal.h"
+
+using namespace pgsgd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pgsgd_status fail(pgsgd_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+pgsgd_status ok() {
+  g_last_error.clear();
+  return PGSGD_OK;
+}
+
+#define HIP_TRY(expr)                                                                                    \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess) {                                                                              \
+      (void)hipGetLastError();                                                                           \
+      return fail(e_ == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE, "%s failed: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                                      \
+    }                                                                                                    \
+  } while (0)
+
+constexpr uint64_t kMaxSteps = 1ull << 40;
+constexpr uint64_t kMaxTerms = 1ull << 48;
+constexpr int64_t kMaxPathNt = (int64_t)1 << 62;
+constexpr uint32_t kMaxPaths = 1u << 20;
+
+uint32_t pow2_floor(uint32_t v) {
+  uint32_t p = 1;
+  while ((p << 1) != 0 && (p << 1) <= v) p <<= 1;
+  return p;
+}
+
+// Power-law table of pgsgd_zipf_table plus its guide: guide[b] = smallest k in
+// [1, W] with C[k] > b * 2^(32-kGuideBits), guide[kGuideSize] = W.
+void build_zipf(double theta, uint32_t W, std::vector<uint32_t>& C, std::vector<uint16_t>& guide) {
+  std::vector<double> F(W + 1);
+  F[0] = 0.0;
+  for (uint32_t k = 1; k <= W; ++k) F[k] = F[k - 1] + std::pow((double)k, -theta);
+  C.assign(W + 1, 0);
+  for (uint32_t k = 1; k <= W; ++k) C[k] = (uint32_t)std::floor(F[k] / F[W] * 4294967295.0);
+  guide.assign(kGuideSize + 1, (uint16_t)W);
+  uint32_t k = 1;
+  for (uint32_t b = 0; b < kGuideSize; ++b) {
+    const uint64_t lo = (uint64_t)b << (32 - kGuideBits);
+    while (k < W && (uint64_t)C[k] <= lo) ++k;
+    guide[b] = (uint16_t)k;
+  }
+  guide[kGuideSize] = (uint16_t)W;
+}
+
+void build_schedule(uint32_t n_iters, double eta_max, double eta_min, std::vector<float>& eta) {
+  eta.assign(n_iters, 0.0f);
+  if (n_iters == 0) return;
+  if (n_iters == 1) {
+    eta[0] = (float)eta_max;
+    return;
+  }
+  const double lambda = std::log(eta_max / eta_min) / (double)(n_iters - 1);
+  for (uint32_t t = 0; t < n_iters; ++t) eta[t] = (float)(eta_max * std::exp(-lambda * (double)t));
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Graph handle
+// ---------------------------------------------------------------------------
+struct pgsgd_graph {
+  int device = 0;
+  uint32_t n_nodes = 0, n_paths = 0, path_top = 1, path_slots = 2, max_path_steps = 0;
+  uint64_t S = 0;
+  int64_t d_max = 0;
+  int n_cu = 256;
+  size_t lds_limit = 65536;
+  std::vector<uint64_t> h_path_off;
+  StepRec* d_rec = nullptr;
+  uint64_t* d_path_off = nullptr;
+  uint64_t* d_first = nullptr;
+  float2* d_work = nullptr;     // interleaved working copy of the coordinates
+  // power-law table cache
+  double zipf_theta = -1.0;
+  uint32_t zipf_W = 0;
+  uint32_t* d_zipf = nullptr;
+  uint16_t* d_guide = nullptr;
+  // reduction scratch
+  double* d_part_f = nullptr;
+  uint64_t* d_part_n = nullptr;
+  uint64_t* d_part_skip = nullptr;
+  double* d_out_f = nullptr;    // [4]
+  uint64_t* d_out_n = nullptr;  // [4]
+  double* d_mean = nullptr;
+  size_t device_bytes = 0;
+  int layout_blocks_per_cu = 0;  // occupancy of k_layout_iter, filled on first use
+
+  ~pgsgd_graph() {
+    DeviceGuard g(device);
+    (void)hipDeviceSynchronize();
+    for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
+                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean})
+      if (p) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <typename T>
+pgsgd_status dev_alloc(pgsgd_graph* g, T** p, size_t count) {
+  size_t bytes = sizeof(T) * (count ? count : 1);
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE, "hipMalloc(%zu bytes) failed: %s",
+                bytes, hipGetErrorString(e));
+  }
+  g->device_bytes += bytes;
+  return PGSGD_OK;
+}
+
+// Ensures the graph holds the power-law table for (theta, W) on the device.
+pgsgd_status ensure_zipf(pgsgd_graph* g, double theta, uint32_t W, hipStream_t s) {
+  if (g->d_zipf && g->zipf_theta == theta && g->zipf_W == W) return PGSGD_OK;
+  std::vector<uint32_t> C;
+  std::vector<uint16_t> guide;
+  build_zipf(theta, W, C, guide);
+  HIP_TRY(hipStreamSynchronize(s));  // earlier work on this stream may still read the old table
+  if (!g->d_zipf) {  // sized for the largest window (65535)
+    pgsgd_status st = dev_alloc(g, &g->d_zipf, 65536);
+    if (st) return st;
+  }
+  if (!g->d_guide) {
+    pgsgd_status st = dev_alloc(g, &g->d_guide, kGuideSize + 1);
+    if (st) return st;
+  }
+  HIP_TRY(hipMemcpy(g->d_zipf, C.data(), sizeof(uint32_t) * C.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->d_guide, guide.data(), sizeof(uint16_t) * guide.size(), hipMemcpyHostToDevice));
+  g->zipf_theta = theta;
+  g->zipf_W = W;
+  return PGSGD_OK;
+}
+
+pgsgd_status check_params(const pgsgd_params* p) {
+  if (!p) return fail(PGSGD_ERR_INVALID_ARG, "params is NULL");
+  if (p->flags != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags must be 0");
+  if (p->zipf_window < 1 || p->zipf_window > 65535)
+    return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", p->zipf_window);
+  if (!(p->zipf_theta >= 0.0) || !std::isfinite(p->zipf_theta))
+    return fail(PGSGD_ERR_INVALID_ARG, "zipf_theta must be finite and >= 0");
+  if (p->graph_id >= (1u << 24)) return fail(PGSGD_ERR_INVALID_ARG, "graph_id must be < 2^24");
+  if (p->terms_per_step == 0) return fail(PGSGD_ERR_INVALID_ARG, "terms_per_step must be >= 1");
+  if (!(p->eta_min > 0.0) || !std::isfinite(p->eta_min)) return fail(PGSGD_ERR_INVALID_ARG, "eta_min must be > 0");
+  if (!std::isfinite(p->eta_max)) return fail(PGSGD_ERR_INVALID_ARG, "eta_max must be finite");
+  const uint32_t last = p->last_iter == 0 ? p->n_iters : p->last_iter;
+  if (p->first_iter > last || last > p->n_iters)
+    return fail(PGSGD_ERR_INVALID_ARG, "iteration range [%u, %u) invalid for n_iters %u", p->first_iter, last,
+                p->n_iters);
+  return PGSGD_OK;
+}
+
+double eta_max_of(const pgsgd_params* p, int64_t d_max) {
+  if (p->eta_max > 0.0) return p->eta_max;
+  const double d = (double)(d_max > 0 ? d_max : 1);
+  return d * d;
+}
+
+LayoutLaunch make_layout_launch(const pgsgd_graph* g, const pgsgd_params* p) {
+  LayoutLaunch L{};
+  L.rec = g->d_rec;
+  L.work = g->d_work;
+  L.path_off = g->d_path_off;
+  L.zipf = g->d_zipf;
+  L.guide = g->d_guide;
+  L.n_nodes = g->n_nodes;
+  L.S = g->S;
+  L.n_terms = (uint64_t)p->terms_per_step * g->S;
+  L.n_groups = (L.n_terms + 63) / 64;
+  L.n_paths = g->n_paths;
+  L.path_slots = g->path_slots;
+  L.path_top = g->path_top;
+  L.W = p->zipf_window;
+  L.c3 = (kStreamLayout << 24) | p->graph_id;
+  L.k0 = (uint32_t)p->seed;
+  L.k1 = (uint32_t)(p->seed >> 32);
+  return L;
+}
+
+StressLaunch make_stress_launch(const pgsgd_graph* g, const float* coords, uint32_t stream, uint32_t graph_id,
+                                uint64_t seed) {
+  StressLaunch P{};
+  P.rec = g->d_rec;
+  P.coords = coords;
+  P.path_off = g->d_path_off;
+  P.zipf = g->d_zipf;
+  P.guide = g->d_guide;
+  P.n_nodes = g->n_nodes;
+  P.S = g->S;
+  P.n_paths = g->n_paths;
+  P.path_slots = g->path_slots;
+  P.path_top = g->path_top;
+  P.c3 = (stream << 24) | (graph_id & 0xFFFFFFu);
+  P.k0 = (uint32_t)seed;
+  P.k1 = (uint32_t)(seed >> 32);
+  return P;
+}
+
+pgsgd_status layout_blocks_per_cu(pgsgd_graph* g, size_t lds, int* out) {
+  if (g->layout_blocks_per_cu <= 0) {
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, layout_iter_kernel(), 256, lds));
+    g->layout_blocks_per_cu = nb > 0 ? nb : 1;
+  }
+  *out = g->layout_blocks_per_cu;
+  return PGSGD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pgsgd_last_error(void) { return g_last_error.c_str(); }
+const char* pgsgd_version(void) { return "pgsgd-gfx950 0.1.0"; }
+
+void pgsgd_params_default(pgsgd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n_iters = 30;
+  p->terms_per_step = 10;
+  p->eta_max = 0.0;
+  p->eta_min = 0.01;
+  p->zipf_theta = 0.99;
+  p->zipf_window = 1000;
+  p->graph_id = 0;
+  p->seed = 24301;
+  p->first_iter = 0;
+  p->last_iter = 0;
+  p->max_inflight_waves = 0;
+  p->flags = 0;
+}
+
+pgsgd_status pgsgd_schedule(const pgsgd_params* p, int64_t d_max, float* eta_out) {
+  if (!p || !eta_out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (!(p->eta_min > 0.0)) return fail(PGSGD_ERR_INVALID_ARG, "eta_min must be > 0");
+  std::vector<float> eta;
+  build_schedule(p->n_iters, eta_max_of(p, d_max), p->eta_min, eta);
+  std::copy(eta.begin(), eta.end(), eta_out);
+  return ok();
+}
+
+pgsgd_status pgsgd_zipf_table(double theta, uint32_t W, uint32_t* C_out) {
+  if (!C_out) return fail(PGSGD_ERR_INVALID_ARG, "C_out is NULL");
+  if (W < 1 || W > 65535) return fail(PGSGD_ERR_INVALID_ARG, "W %u outside [1, 65535]", W);
+  if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(PGSGD_ERR_INVALID_ARG, "theta must be finite, >= 0");
+  std::vector<uint32_t> C;
+  std::vector<uint16_t> guide;
+  build_zipf(theta, W, C, guide);
+  std::copy(C.begin(), C.end(), C_out);
+  return ok();
+}
+
+pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t* node_len, uint32_t n_paths,
+                                const uint64_t* path_off, const uint32_t* step_node, const int64_t* step_pos,
+                                int device, pgsgd_graph** out) {
+  if (!out) return fail(PGSGD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!node_len && n_nodes > 0) return fail(PGSGD_ERR_INVALID_ARG, "node_len is NULL");
+  if (!path_off) return fail(PGSGD_ERR_INVALID_ARG, "path_offsets is NULL");
+  if (n_paths == 0) return fail(PGSGD_ERR_INVALID_ARG, "n_paths must be >= 1");
+  if (n_paths > kMaxPaths) return fail(PGSGD_ERR_RANGE, "n_paths %u exceeds %u", n_paths, kMaxPaths);
+  if (n_nodes >= (1u << 31)) return fail(PGSGD_ERR_RANGE, "n_nodes must be < 2^31");
+  // ---- validation: host only, before any device work ----
+  for (uint32_t n = 0; n < n_nodes; ++n)
+    if (node_len[n] == 0) return fail(PGSGD_ERR_INVALID_ARG, "node %u has length 0", n);
+  if (path_off[0] != 0) return fail(PGSGD_ERR_INVALID_ARG, "path_offsets[0] must be 0");
+  uint64_t max_len = 0;
+  for (uint32_t p = 0; p < n_paths; ++p) {
+    if (path_off[p + 1] < path_off[p])
+      return fail(PGSGD_ERR_INVALID_ARG, "path_offsets not monotone at path %u", p);
+    max_len = std::max(max_len, path_off[p + 1] - path_off[p]);
+  }
+  const uint64_t S = path_off[n_paths];
+  if (S >= kMaxSteps) return fail(PGSGD_ERR_RANGE, "total steps %llu >= 2^40", (unsigned long long)S);
+  if (max_len >= (1ull << 32)) return fail(PGSGD_ERR_RANGE, "a path has >= 2^32 steps");
+  if (S > 0 && !step_node) return fail(PGSGD_ERR_INVALID_ARG, "step_node is NULL");
+  if (S > 0 && n_nodes == 0) return fail(PGSGD_ERR_INVALID_ARG, "steps given but n_nodes = 0");
+  int64_t d_max = 0;
+  for (uint32_t p = 0; p < n_paths; ++p) {
+    int64_t acc = 0;
+    for (uint64_t s = path_off[p]; s < path_off[p + 1]; ++s) {
+      const uint32_t n = step_node[s] & kNodeMask;
+      if (n >= n_nodes)
+        return fail(PGSGD_ERR_INVALID_ARG, "step %llu refers to node %u >= n_nodes %u", (unsigned long long)s, n,
+                    n_nodes);
+      if (step_pos && step_pos[s] != acc)
+        return fail(PGSGD_ERR_INVALID_ARG, "step_pos[%llu] = %lld but the length prefix sum is %lld",
+                    (unsigned long long)s, (long long)step_pos[s], (long long)acc);
+      acc += node_len[n];
+      if (acc >= kMaxPathNt) return fail(PGSGD_ERR_RANGE, "path %u is longer than 2^62 nt", p);
+    }
+    d_max = std::max(d_max, acc);
+  }
+  int n_dev = 0;
+  hipError_t e = hipGetDeviceCount(&n_dev);
+  if (e != hipSuccess || n_dev == 0) {
+    (void)hipGetLastError();
+    return fail(PGSGD_ERR_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+  }
+  if (device < 0 || device >= n_dev) return fail(PGSGD_ERR_INVALID_ARG, "device %d out of range", device);
+
+  // ---- device work ----
+  pgsgd_graph* g = new (std::nothrow) pgsgd_graph();
+  if (!g) return fail(PGSGD_ERR_OOM, "host allocation failed");
+  g->device = device;
+  DeviceGuard guard(device);
+  g->n_nodes = n_nodes;
+  g->n_paths = n_paths;
+  g->S = S;
+  g->d_max = d_max;
+  g->max_path_steps = (uint32_t)max_len;
+  g->path_top = pow2_floor(n_paths);
+  g->path_slots = 2 * g->path_top;
+  g->h_path_off.assign(path_off, path_off + n_paths + 1);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    g->n_cu = prop.multiProcessorCount;
+    g->lds_limit = prop.sharedMemPerBlock;
+  }
+  pgsgd_status st;
+  auto bail = [&](pgsgd_status code) {
+    delete g;
+    return code;
+  };
+  if ((st = dev_alloc(g, &g->d_rec, S))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_path_off, n_paths + 1))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_first, n_nodes))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_work, 2ull * n_nodes))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_part_f, kStressBlocks))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_part_n, kStressBlocks))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_part_skip, kStressBlocks))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_out_f, 4))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_out_n, 4))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_mean, 1))) return bail(st);
+  auto dev_err = [&](hipError_t err, const char* what) {
+    (void)hipGetLastError();
+    fail(err == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(err));
+    delete g;
+    return err == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE;
+  };
+  if ((e = hipMemcpy(g->d_path_off, path_off, sizeof(uint64_t) * (n_paths + 1), hipMemcpyHostToDevice)))
+    return dev_err(e, "path offsets upload");
+
+  // Pack and upload the step records through two pinned staging buffers.
+  if (S > 0) {
+    const uint64_t chunk = std::min<uint64_t>(S, 1ull << 22);  // 64 MiB of records per buffer
+    StepRec* stage[2] = {nullptr, nullptr};
+    hipEvent_t done[2];
+    hipStream_t cs;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) return dev_err(e, "stream create");
+    bool ok_all = true;
+    for (int k = 0; k < 2 && ok_all; ++k) {
+      if ((e = hipHostMalloc((void**)&stage[k], sizeof(StepRec) * chunk, hipHostMallocDefault))) ok_all = false;
+      else if ((e = hipEventCreateWithFlags(&done[k], hipEventDisableTiming))) ok_all = false;
+    }
+    if (ok_all) {
+      uint32_t p = 0;
+      int64_t acc = 0;
+      uint64_t next_path_start = path_off[1];
+      int buf = 0;
+      bool pending[2] = {false, false};
+      for (uint64_t base = 0; base < S && ok_all; base += chunk) {
+        const uint64_t n = std::min(chunk, S - base);
+        if (pending[buf]) {
+          if ((e = hipEventSynchronize(done[buf]))) { ok_all = false; break; }
+        }
+        StepRec* out_rec = stage[buf];
+        for (uint64_t k = 0; k < n; ++k) {
+          const uint64_t s = base + k;
+          while (s >= next_path_start) {  // entering the next non-empty path
+            ++p;
+            acc = 0;
+            next_path_start = path_off[p + 1];
+          }
+          const uint32_t v = step_node[s];
+          const uint32_t len = node_len[v & kNodeMask];
+          out_rec[k].pos = acc;
+          out_rec[k].node_rev = v;
+          out_rec[k].len = len;
+          acc += len;
+        }
+        if ((e = hipMemcpyAsync(g->d_rec + base, out_rec, sizeof(StepRec) * n, hipMemcpyHostToDevice, cs))) {
+          ok_all = false;
+          break;
+        }
+        if ((e = hipEventRecord(done[buf], cs))) { ok_all = false; break; }
+        pending[buf] = true;
+        buf ^= 1;
+      }
+      if (ok_all) e = hipStreamSynchronize(cs);
+    }
+    (void)hipStreamSynchronize(cs);
+    for (int k = 0; k < 2; ++k) {
+      if (stage[k]) (void)hipHostFree(stage[k]);
+      (void)hipEventDestroy(done[k]);
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return dev_err(e, "step record upload");
+  }
+  if ((e = launch_first_visit(g->d_rec, S, n_nodes, g->d_first, nullptr))) return dev_err(e, "first-visit kernel");
+  if ((e = hipDeviceSynchronize())) return dev_err(e, "graph upload");
+  *out = g;
+  return ok();
+}
+
+void pgsgd_graph_destroy(pgsgd_graph* g) { delete g; }
+
+pgsgd_status pgsgd_graph_get_info(const pgsgd_graph* g, pgsgd_graph_info* out) {
+  if (!g || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  out->n_steps = g->S;
+  out->n_nodes = g->n_nodes;
+  out->n_paths = g->n_paths;
+  out->d_max = g->d_max;
+  out->device_bytes = g->device_bytes;
+  out->device = g->device;
+  out->max_path_steps = g->max_path_steps;
+  return ok();
+}
+
+pgsgd_status pgsgd_init_coords(pgsgd_graph* g, uint64_t seed, uint32_t graph_id, float jitter, float* coords,
+                               void* stream) {
+  if (!g || !coords) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (((uintptr_t)coords & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
+  if (graph_id >= (1u << 24)) return fail(PGSGD_ERR_INVALID_ARG, "graph_id must be < 2^24");
+  if (g->n_nodes == 0) return ok();
+  DeviceGuard guard(g->device);
+  HIP_TRY(launch_init_coords(g->d_rec, g->d_first, g->n_nodes, (uint32_t)seed, (uint32_t)(seed >> 32),
+                             (kStreamInit << 24) | graph_id, jitter, coords, (hipStream_t)stream));
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Launch shape of k_layout_iter: a full device of resident waves, capped by
+// params.max_inflight_waves (automatic: see auto_inflight_waves) and by the
+// number of 64-term groups.  Large grids use 4-wave blocks; small caps use
+// one-wave blocks so the number of concurrent waves is exactly the cap.
+// Automatic cap: about n_nodes / 32 terms in flight (n_nodes / 2048 waves), so
+// a term shares an endpoint with another in-flight term with probability of
+// about 3% (the Hogwild sparsity assumption).  Small graphs are sensitive to
+// this: on a 2.6K-node graph one wave keeps the sampled path stress of the
+// sequential loop, two waves raise it by about 12%.
+uint64_t auto_inflight_waves(const pgsgd_graph* g) { return std::max<uint64_t>(1, g->n_nodes / 2048); }
+
+pgsgd_status layout_grid(pgsgd_graph* g, const pgsgd_params* p, size_t lds, uint64_t n_groups, uint32_t* blocks,
+                         uint32_t* threads) {
+  int bpc = 1;
+  pgsgd_status st = layout_blocks_per_cu(g, lds, &bpc);
+  if (st) return st;
+  uint64_t waves = (uint64_t)g->n_cu * bpc * 4;
+  const uint64_t cap = p->max_inflight_waves ? p->max_inflight_waves : auto_inflight_waves(g);
+  waves = std::min(waves, cap);
+  waves = std::min(waves, std::max<uint64_t>(1, n_groups));
+  if (waves >= 4ull * g->n_cu) {
+    *threads = 256;
+    *blocks = (uint32_t)((waves + 3) / 4);
+  } else {
+    *threads = 64;
+    *blocks = (uint32_t)waves;
+  }
+  return PGSGD_OK;
+}
+
+pgsgd_status layout_prepare(pgsgd_graph* g, const pgsgd_params* p, hipStream_t s, size_t* lds) {
+  *lds = layout_lds_bytes(g->path_slots, p->zipf_window);
+  if (*lds > g->lds_limit)
+    return fail(PGSGD_ERR_UNSUPPORTED, "LDS image of %zu bytes exceeds the %zu-byte block limit", *lds,
+                g->lds_limit);
+  return ensure_zipf(g, p->zipf_theta, p->zipf_window, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+}  // extern "C"
+
+namespace {
+
+// The layout loop; with iter_ms set, HIP events bracket every iteration's
+// launch on the stream and the durations are written there (synchronising).
+pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms, void* stream) {
+  if (!g || !coords) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (((uintptr_t)coords & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if ((uint64_t)p->terms_per_step * g->S >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term count >= 2^48");
+  const uint32_t last = p->last_iter == 0 ? p->n_iters : p->last_iter;
+  if (iter_ms)
+    for (uint32_t it = p->first_iter; it < last; ++it) iter_ms[it - p->first_iter] = 0.0f;
+  if (g->S == 0 || p->n_iters == 0 || p->first_iter == last) return ok();
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  size_t lds;
+  if ((st = layout_prepare(g, p, s, &lds))) return st;
+  std::vector<float> eta;
+  build_schedule(p->n_iters, eta_max_of(p, g->d_max), p->eta_min, eta);
+  LayoutLaunch L = make_layout_launch(g, p);
+  L.t_begin = 0;
+  L.t_end = L.n_terms;
+  L.g_begin = 0;
+  L.g_end = L.n_groups;
+  uint32_t blocks, threads;
+  if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
+  L.wave_stride = (uint64_t)blocks * (threads / 64);
+  std::vector<hipEvent_t> ev;
+  if (iter_ms) {
+    ev.resize(last - p->first_iter + 1);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  }
+  struct EventsFree {
+    std::vector<hipEvent_t>& v;
+    ~EventsFree() {
+      for (auto e : v) (void)hipEventDestroy(e);
+    }
+  } events_free{ev};
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  for (uint32_t it = p->first_iter; it < last; ++it) {
+    L.iter = it;
+    L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
+    L.eta = eta[it];
+    if (iter_ms && it == p->first_iter) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_layout_iter(L, blocks, threads, s));
+    if (iter_ms) HIP_TRY(hipEventRecord(ev[it - p->first_iter + 1], s));
+  }
+  HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
+  if (iter_ms) {
+    HIP_TRY(hipEventSynchronize(ev.back()));
+    for (uint32_t k = 0; k + 1 < ev.size(); ++k) HIP_TRY(hipEventElapsedTime(&iter_ms[k], ev[k], ev[k + 1]));
+  }
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+pgsgd_status pgsgd_layout(pgsgd_graph* g, const pgsgd_params* p, float* coords, void* stream) {
+  return layout_impl(g, p, coords, nullptr, stream);
+}
+
+pgsgd_status pgsgd_layout_timed(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms,
+                                void* stream) {
+  if (!iter_ms) return fail(PGSGD_ERR_INVALID_ARG, "iter_ms is NULL");
+  return layout_impl(g, p, coords, iter_ms, stream);
+}
+
+pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t iter, uint64_t t_begin,
+                                uint64_t count, uint64_t* i_out, uint64_t* j_out, uint8_t* flags_out,
+                                void* stream) {
+  if (!g || !i_out || !j_out || !flags_out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
+  if (t_begin + count < t_begin || t_begin + count >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term range too large");
+  if (count == 0 || g->S == 0) return ok();
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  size_t lds;
+  if ((st = layout_prepare(g, p, s, &lds))) return st;
+  // the layout kernel itself, in recording mode, with the layout's launch shape
+  LayoutLaunch L = make_layout_launch(g, p);
+  uint32_t blocks, threads;
+  if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
+  L.wave_stride = (uint64_t)blocks * (threads / 64);
+  L.iter = iter;
+  L.cool_all = iter >= p->n_iters / 2 ? 1u : 0u;
+  L.t_begin = t_begin;
+  L.t_end = t_begin + count;
+  L.g_begin = t_begin >> 6;
+  L.g_end = (t_begin + count + 63) >> 6;
+  L.trace_i = i_out;
+  L.trace_j = j_out;
+  L.trace_f = flags_out;
+  HIP_TRY(launch_layout_iter(L, blocks, threads, s));
+  return ok();
+}
+
+pgsgd_status pgsgd_apply_terms(pgsgd_graph* g, float eta, const uint64_t* i, const uint64_t* j,
+                               const uint8_t* flags, uint64_t count, float* coords, void* stream) {
+  if (!g || !i || !j || !flags || !coords) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (count == 0) return ok();
+  if (count >= (1ull << 40)) return fail(PGSGD_ERR_RANGE, "count too large");
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  HIP_TRY(launch_apply_terms(g->d_rec, g->d_work, eta, i, j, flags, count, s));
+  HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
+  return ok();
+}
+
+pgsgd_status pgsgd_path_stress(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
+                               pgsgd_stress_result* out, void* stream) {
+  if (!g || !coords || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (m == 0) return fail(PGSGD_ERR_INVALID_ARG, "pairs_per_step must be >= 1");
+  if (graph_id >= (1u << 24)) return fail(PGSGD_ERR_INVALID_ARG, "graph_id must be < 2^24");
+  if ((double)m * (double)g->S >= 18446744073709551615.0) return fail(PGSGD_ERR_RANGE, "too many pairs");
+  std::memset(out, 0, sizeof(*out));
+  if (g->S == 0) return ok();
+  if ((size_t)g->path_slots * 8 > g->lds_limit) return fail(PGSGD_ERR_UNSUPPORTED, "too many paths for LDS");
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  StressLaunch P = make_stress_launch(g, coords, kStreamSps, graph_id, seed);
+  P.m = m;
+  P.count = g->S;
+  HIP_TRY(launch_sps_pass(P, 1, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
+  HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
+                              g->d_mean, nullptr, nullptr, s));
+  HIP_TRY(launch_sps_pass(P, 2, g->d_mean, g->d_part_f, nullptr, nullptr, s));
+  HIP_TRY(launch_reduce_parts(g->d_part_f, nullptr, nullptr, kStressBlocks, g->d_out_f + 1, nullptr, nullptr,
+                              nullptr, nullptr, s));
+  double f[2];
+  uint64_t n[2];
+  HIP_TRY(hipMemcpyAsync(f, g->d_out_f, sizeof(f), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(n, g->d_out_n, sizeof(n), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->sum = f[0];
+  out->sumsq_dev = f[1];
+  out->n_valid = n[0];
+  out->n_skipped = n[1];
+  out->mean = n[0] ? f[0] / (double)n[0] : 0.0;
+  out->stddev = n[0] > 1 ? std::sqrt(f[1] / (double)(n[0] - 1)) : 0.0;
+  const double half = n[0] ? 1.96 * out->stddev / std::sqrt((double)n[0]) : 0.0;
+  out->ci_lo = out->mean - half;
+  out->ci_hi = out->mean + half;
+  return ok();
+}
+
+pgsgd_status pgsgd_stress_forward(pgsgd_graph* g, const pgsgd_params* p, const float* coords, uint64_t n_pairs,
+                                  uint32_t step, float* loss_dev, uint64_t* n_valid_dev, void* stream) {
+  if (!g || !coords || !loss_dev || !n_valid_dev) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if (n_pairs >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "n_pairs too large");
+  const size_t lds = layout_lds_bytes(g->path_slots, p->zipf_window);
+  if (lds > g->lds_limit) return fail(PGSGD_ERR_UNSUPPORTED, "LDS image exceeds the block limit");
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ensure_zipf(g, p->zipf_theta, p->zipf_window, s))) return st;
+  StressLaunch P = make_stress_launch(g, coords, kStreamPairs, p->graph_id, p->seed);
+  P.W = p->zipf_window;
+  P.word2 = step;
+  P.count = g->S ? n_pairs : 0;
+  HIP_TRY(launch_stress_fwd(P, g->d_part_f, g->d_part_n, s));
+  HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, kStressBlocks, nullptr, nullptr, nullptr, loss_dev,
+                              n_valid_dev, s));
+  return ok();
+}
+
+pgsgd_status pgsgd_stress_backward(pgsgd_graph* g, const pgsgd_params* p, const float* coords, uint64_t n_pairs,
+                                   uint32_t step, const float* grad_out_dev, const uint64_t* n_valid_dev,
+                                   float* grad_coords, void* stream) {
+  if (!g || !coords || !grad_out_dev || !n_valid_dev || !grad_coords)
+    return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if (n_pairs >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "n_pairs too large");
+  const size_t lds = layout_lds_bytes(g->path_slots, p->zipf_window);
+  if (lds > g->lds_limit) return fail(PGSGD_ERR_UNSUPPORTED, "LDS image exceeds the block limit");
+  if (g->S == 0 || n_pairs == 0) return ok();
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ensure_zipf(g, p->zipf_theta, p->zipf_window, s))) return st;
+  StressLaunch P = make_stress_launch(g, coords, kStreamPairs, p->graph_id, p->seed);
+  P.W = p->zipf_window;
+  P.word2 = step;
+  P.count = n_pairs;
+  HIP_TRY(launch_stress_bwd(P, grad_out_dev, n_valid_dev, grad_coords, s));
+  return ok();
+}
+
+pgsgd_status pgsgd_adam_step(float* x, const float* grad, float* m, float* v, uint64_t n, float lr, float beta1,
+                             float beta2, float eps, uint32_t t, void* stream) {
+  if (!x || !grad || !m || !v) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (t < 1) return fail(PGSGD_ERR_INVALID_ARG, "t must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+    return fail(PGSGD_ERR_INVALID_ARG, "betas must be in [0, 1)");
+  if (n == 0) return ok();
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+  HIP_TRY(launch_adam(x, grad, m, v, n, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream));
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+struct pgsgd_batch {
+  int device = 0;
+  uint32_t n_graphs = 0;
+  pgsgd_tune tune{};
+  pgsgd_params params{};
+  BatchGraph* d_graphs = nullptr;
+  uint64_t* d_seg_off = nullptr;
+  uint64_t* d_path_blob = nullptr;
+  float* d_eta = nullptr;
+  uint32_t* d_zipf = nullptr;
+  uint16_t* d_guide = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchLaunch launch{};
+  std::vector<float*> coords;
+  std::vector<float2*> work;
+  std::vector<uint64_t> n_nodes;
+  uint32_t blocks = 0;
+  uint64_t total_terms = 0;
+
+  ~pgsgd_batch() {
+    DeviceGuard g(device);
+    (void)hipDeviceSynchronize();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : {(void*)d_graphs, (void*)d_seg_off, (void*)d_path_blob, (void*)d_eta, (void*)d_zipf,
+                    (void*)d_guide})
+      if (p) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+pgsgd_status check_tune(const pgsgd_tune* t) {
+  if (t->block_threads < 64 || t->block_threads > 1024 || t->block_threads % 64)
+    return fail(PGSGD_ERR_INVALID_ARG, "tune.block_threads must be a multiple of 64 in [64, 1024]");
+  if (t->groups_per_item < 1) return fail(PGSGD_ERR_INVALID_ARG, "tune.groups_per_item must be >= 1");
+  if (t->blocks_per_cu < 1) return fail(PGSGD_ERR_INVALID_ARG, "tune.blocks_per_cu must be >= 1");
+  return PGSGD_OK;
+}
+
+pgsgd_tune default_tune() {
+  pgsgd_tune t{};
+  t.block_threads = 512;
+  t.groups_per_item = 4;
+  t.blocks_per_cu = 4;
+  return t;
+}
+
+// Builds a batch; group_div > 1 restricts every graph to the first 1/group_div
+// of its groups (tuning runs only).  capture = false skips the HIP graph.
+pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p, float* const* coords,
+                         const pgsgd_tune* tune, uint32_t group_div, bool capture, pgsgd_batch** out,
+                         uint64_t* const* trace_i = nullptr, uint64_t* const* trace_j = nullptr,
+                         uint8_t* const* trace_f = nullptr) {
+  *out = nullptr;
+  if (!graphs || !coords || n == 0) return fail(PGSGD_ERR_INVALID_ARG, "empty or NULL graph list");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if ((uint64_t)p->graph_id + n > (1u << 24)) return fail(PGSGD_ERR_INVALID_ARG, "graph_id + n must be <= 2^24");
+  pgsgd_tune t = tune ? *tune : default_tune();
+  if ((st = check_tune(&t))) return st;
+  const int dev = graphs[0] ? graphs[0]->device : 0;
+  uint32_t slots_total = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (!graphs[k] || !coords[k]) return fail(PGSGD_ERR_INVALID_ARG, "graph or coords %u is NULL", k);
+    if (graphs[k]->device != dev) return fail(PGSGD_ERR_INVALID_ARG, "graphs on different devices");
+    for (uint32_t q = 0; q < k; ++q)
+      if (graphs[q] == graphs[k]) return fail(PGSGD_ERR_INVALID_ARG, "graph %u appears twice in the batch", k);
+    if (((uintptr_t)coords[k] & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords %u not 16-byte aligned", k);
+    if ((uint64_t)p->terms_per_step * graphs[k]->S >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term count >= 2^48");
+    slots_total += graphs[k]->path_slots;
+  }
+  const size_t lds = batch_lds_bytes(n, slots_total, p->zipf_window);
+  if (lds > graphs[0]->lds_limit)
+    return fail(PGSGD_ERR_UNSUPPORTED, "batched LDS image of %zu bytes exceeds the %zu-byte block limit", lds,
+                graphs[0]->lds_limit);
+  DeviceGuard guard(dev);
+  pgsgd_batch* b = new (std::nothrow) pgsgd_batch();
+  if (!b) return fail(PGSGD_ERR_OOM, "host allocation failed");
+  b->device = dev;
+  b->n_graphs = n;
+  b->tune = t;
+  b->params = *p;
+  std::vector<BatchGraph> hdr(n);
+  std::vector<uint64_t> seg_off((size_t)kBatchPhases * n + 1, 0), blob;
+  std::vector<float> eta_all;
+  blob.reserve(slots_total);
+  for (uint32_t k = 0; k < n; ++k) {
+    const pgsgd_graph* g = graphs[k];
+    BatchGraph& h = hdr[k];
+    h.rec = g->d_rec;
+    h.work = g->d_work;
+    h.n_nodes = g->n_nodes;
+    h.S = g->S;
+    h.n_terms = (uint64_t)p->terms_per_step * g->S;
+    const uint64_t groups = (h.n_terms + 63) / 64;
+    h.n_groups_run = group_div > 1 ? (groups + group_div - 1) / group_div : groups;
+    h.path_base = (uint32_t)blob.size();
+    h.path_top = g->path_top;
+    h.c3 = (kStreamLayout << 24) | (p->graph_id + k);
+    h.eta = 0.0f;
+    h.trace_i = trace_i ? trace_i[k] : nullptr;
+    h.trace_j = trace_j ? trace_j[k] : nullptr;
+    h.trace_f = trace_f ? trace_f[k] : nullptr;
+    for (uint32_t q = 0; q < g->path_slots; ++q) blob.push_back(q <= g->n_paths ? g->h_path_off[q] : ~0ull);
+    h.n_items = (h.n_groups_run + t.groups_per_item - 1) / t.groups_per_item;
+    b->total_terms += std::min<uint64_t>(h.n_terms, h.n_groups_run * 64);
+    std::vector<float> eta;
+    build_schedule(p->n_iters, eta_max_of(p, g->d_max), p->eta_min, eta);
+    eta_all.insert(eta_all.end(), eta.begin(), eta.end());
+  }
+  // segment (phase r, graph k) holds items [floor(r I_k / R), floor((r+1) I_k / R)) of graph k
+  for (uint32_t r = 0; r < kBatchPhases; ++r)
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint64_t I = hdr[k].n_items;
+      const uint64_t sz = ((r + 1) * I) / kBatchPhases - (r * I) / kBatchPhases;
+      const size_t sidx = (size_t)r * n + k;
+      seg_off[sidx + 1] = seg_off[sidx] + sz;
+    }
+  std::vector<uint32_t> C;
+  std::vector<uint16_t> guide;
+  build_zipf(p->zipf_theta, p->zipf_window, C, guide);
+  auto alloc_copy = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, bytes ? bytes : 1);
+    if (e) return e;
+    return bytes ? hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  hipError_t e;
+  if ((e = alloc_copy((void**)&b->d_graphs, hdr.data(), sizeof(BatchGraph) * n)) ||
+      (e = alloc_copy((void**)&b->d_seg_off, seg_off.data(), sizeof(uint64_t) * seg_off.size())) ||
+      (e = alloc_copy((void**)&b->d_path_blob, blob.data(), sizeof(uint64_t) * blob.size())) ||
+      (e = alloc_copy((void**)&b->d_eta, eta_all.data(), sizeof(float) * eta_all.size())) ||
+      (e = alloc_copy((void**)&b->d_zipf, C.data(), sizeof(uint32_t) * C.size())) ||
+      (e = alloc_copy((void**)&b->d_guide, guide.data(), sizeof(uint16_t) * guide.size()))) {
+    (void)hipGetLastError();
+    delete b;
+    return fail(e == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE, "batch setup: %s",
+                hipGetErrorString(e));
+  }
+  int n_cu = graphs[0]->n_cu;
+  int max_bpc = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&max_bpc, layout_batch_kernel(), (int)t.block_threads, lds);
+  if (e != hipSuccess || max_bpc < 1) {
+    (void)hipGetLastError();
+    delete b;
+    return fail(PGSGD_ERR_UNSUPPORTED, "batched kernel cannot run with %u threads and %zu bytes of LDS",
+                t.block_threads, lds);
+  }
+  const uint32_t bpc = std::min<uint32_t>(t.blocks_per_cu, (uint32_t)max_bpc);
+  b->blocks = (uint32_t)n_cu * bpc;
+  if (t.max_blocks) b->blocks = std::min(b->blocks, t.max_blocks);
+  BatchLaunch& L = b->launch;
+  L.graphs = b->d_graphs;
+  L.seg_off = b->d_seg_off;
+  L.path_blob = b->d_path_blob;
+  L.eta_all = b->d_eta;
+  L.zipf = b->d_zipf;
+  L.guide = b->d_guide;
+  L.wave_stride = (uint64_t)b->blocks * (t.block_threads / 64);
+  L.groups_per_item = t.groups_per_item;
+  L.n_graphs = n;
+  L.path_slots_total = slots_total;
+  L.W = p->zipf_window;
+  L.n_iters = p->n_iters;
+  L.k0 = (uint32_t)p->seed;
+  L.k1 = (uint32_t)(p->seed >> 32);
+  if (capture) {
+    hipStream_t cs;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) {
+      delete b;
+      return fail(PGSGD_ERR_DEVICE, "stream create: %s", hipGetErrorString(e));
+    }
+    const uint32_t last = p->last_iter == 0 ? p->n_iters : p->last_iter;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (uint32_t k = 0; k < n && e == hipSuccess; ++k)
+      e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, cs);
+    for (uint32_t it = p->first_iter; it < last && e == hipSuccess; ++it) {
+      BatchLaunch Li = L;
+      Li.iter = it;
+      Li.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
+      e = launch_layout_batch(Li, b->blocks, t.block_threads, cs);
+    }
+    for (uint32_t k = 0; k < n && e == hipSuccess; ++k)
+      e = launch_from_work(graphs[k]->d_work, coords[k], graphs[k]->n_nodes, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      delete b;
+      return fail(PGSGD_ERR_DEVICE, "HIP graph capture: %s", hipGetErrorString(e));
+    }
+  }
+  *out = b;
+  return PGSGD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pgsgd_status pgsgd_batch_create(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p,
+                                float* const* coords, const pgsgd_tune* tune, pgsgd_batch** out) {
+  if (!out) return fail(PGSGD_ERR_INVALID_ARG, "out is NULL");
+  pgsgd_status st = batch_build(graphs, n, p, coords, tune, 1, true, out);
+  return st ? st : ok();
+}
+
+pgsgd_status pgsgd_batch_run(pgsgd_batch* b, void* stream) {
+  if (!b) return fail(PGSGD_ERR_INVALID_ARG, "batch is NULL");
+  DeviceGuard guard(b->device);
+  if (b->exec) HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  return ok();
+}
+
+void pgsgd_batch_destroy(pgsgd_batch* b) { delete b; }
+
+pgsgd_status pgsgd_layout_batched(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p,
+                                  float* const* coords, const pgsgd_tune* tune, void* stream) {
+  pgsgd_batch* b = nullptr;
+  pgsgd_status st = pgsgd_batch_create(graphs, n, p, coords, tune, &b);
+  if (st) return st;
+  st = pgsgd_batch_run(b, stream);
+  if (!st) {
+    DeviceGuard guard(b->device);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) st = fail(PGSGD_ERR_DEVICE, "batched run: %s", hipGetErrorString(e));
+  }
+  pgsgd_batch_destroy(b);
+  return st ? st : ok();
+}
+
+pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p, uint32_t iter,
+                                      const pgsgd_tune* tune, uint64_t* const* i_out, uint64_t* const* j_out,
+                                      uint8_t* const* flags_out, void* stream) {
+  if (!i_out || !j_out || !flags_out || !graphs || n == 0) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
+  for (uint32_t k = 0; k < n; ++k)
+    if (!i_out[k] || !j_out[k] || !flags_out[k]) return fail(PGSGD_ERR_INVALID_ARG, "trace buffer %u is NULL", k);
+  // the coordinates are never touched in trace mode; any aligned pointer will do
+  std::vector<float*> dummy(n, reinterpret_cast<float*>(16));
+  pgsgd_batch* b = nullptr;
+  if ((st = batch_build(graphs, n, p, dummy.data(), tune, 1, false, &b, i_out, j_out, flags_out))) return st;
+  DeviceGuard guard(b->device);
+  BatchLaunch L = b->launch;
+  L.iter = iter;
+  L.cool_all = iter >= p->n_iters / 2 ? 1u : 0u;
+  hipError_t e = launch_layout_batch(L, b->blocks, b->tune.block_threads, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  delete b;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PGSGD_ERR_DEVICE, "batched sampling: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+pgsgd_status pgsgd_autotune_batched(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p,
+                                    float* const* coords, pgsgd_tune* best, float* ms_out, void* stream) {
+  if (!best || !graphs || !coords || n == 0) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  const uint32_t tune_cap = best->max_blocks;  // a caller's concurrency cap is kept
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  const int dev = graphs[0] ? graphs[0]->device : 0;
+  DeviceGuard guard(dev);
+  hipStream_t s = (hipStream_t)stream;
+  // Tuning runs load the caller's coordinates into the graphs' working copies
+  // and never write them back, so the caller's buffers are left unchanged.
+  for (uint32_t k = 0; k < n; ++k)
+    if (!graphs[k] || !coords[k]) return fail(PGSGD_ERR_INVALID_ARG, "graph or coords %u is NULL", k);
+  pgsgd_params pt = *p;
+  pt.first_iter = 0;
+  pt.last_iter = 1;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const uint32_t threads_c[] = {256, 512, 1024};
+  const uint32_t gpi_c[] = {1, 4, 16, 64};
+  const uint32_t bpc_c[] = {1, 2, 4, 8};
+  float best_ms = 1e30f;
+  pgsgd_tune best_t = default_tune();
+  best_t.max_blocks = tune_cap;
+  bool any = false;
+  for (uint32_t th : threads_c)
+    for (uint32_t gpi : gpi_c)
+      for (uint32_t bpc : bpc_c) {
+        if (bpc * th / 64 > 32) continue;  // more waves than a CU holds
+        pgsgd_tune t{th, gpi, bpc, tune_cap};
+        pgsgd_batch* b = nullptr;
+        if (batch_build(graphs, n, &pt, coords, &t, 16, false, &b) != PGSGD_OK) continue;
+        BatchLaunch L = b->launch;
+        L.iter = 0;
+        L.cool_all = 0;
+        float ms = 0.0f;
+        bool good = true;
+        for (uint32_t k = 0; k < n && good; ++k)
+          good = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, s) == hipSuccess;
+        if (good) good = launch_layout_batch(L, b->blocks, th, s) == hipSuccess;  // warm-up
+        if (good) good = hipEventRecord(e0, s) == hipSuccess;
+        for (int r = 0; r < 2 && good; ++r) good = launch_layout_batch(L, b->blocks, th, s) == hipSuccess;
+        if (good) good = hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        if (good) good = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        delete b;
+        if (!good) {
+          (void)hipGetLastError();
+          continue;
+        }
+        ms *= 0.5f;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_t = t;
+          any = true;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  if (!any) return fail(PGSGD_ERR_DEVICE, "no tuning candidate could run");
+  *best = best_t;
+  if (ms_out) *ms_out = best_ms;
+  return ok();
+}
+
+}  // extern "C"

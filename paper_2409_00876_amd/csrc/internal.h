@@ -1,0 +1,139 @@
+// Internal interface between the C-ABI host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pgsgd {
+
+struct StepRec;
+
+// Arguments of one plain layout launch (one iteration of one graph).
+struct LayoutLaunch {
+  const StepRec* rec;
+  float2* work;            // interleaved coordinates: [n_nodes][2 endpoints](x, y)
+  const uint64_t* path_off;
+  const uint32_t* zipf;
+  const uint16_t* guide;
+  uint64_t n_nodes;
+  uint64_t S;
+  uint64_t n_terms;
+  uint64_t n_groups;
+  uint64_t wave_stride;    // waves in the grid
+  uint32_t n_paths;
+  uint32_t path_slots;     // LDS entries for offsets: 2 * path_top
+  uint32_t path_top;       // largest power of two <= n_paths
+  uint32_t W;
+  uint32_t iter;
+  uint32_t cool_all;
+  uint32_t c3;             // stream << 24 | graph_id
+  uint32_t k0, k1;         // Philox key
+  float eta;
+  // term range [t_begin, t_end) of this launch, as 64-term groups [g_begin, g_end)
+  uint64_t t_begin, t_end;
+  uint64_t g_begin, g_end;
+  // parity hook: when trace_f is set the terms are recorded (index t - t_begin)
+  // instead of applied
+  uint64_t* trace_i;
+  uint64_t* trace_j;
+  uint8_t* trace_f;
+};
+
+// Per-graph header of the batched launch.
+struct BatchGraph {
+  const StepRec* rec;
+  float2* work;            // interleaved coordinates of this graph
+  uint64_t n_nodes;
+  uint64_t S;
+  uint64_t n_terms;
+  uint64_t n_groups_run;   // groups processed (all, except in tuning runs)
+  uint64_t n_items;        // ceil(n_groups_run / groups_per_item)
+  uint32_t path_base;      // index of this graph's offsets in the path blob
+  uint32_t path_top;
+  uint32_t c3;
+  float eta;               // filled per iteration from eta_all
+  // parity hook: when trace_f is set the terms are recorded (index t) instead
+  // of applied
+  uint64_t* trace_i;
+  uint64_t* trace_j;
+  uint8_t* trace_f;
+};
+
+// Work items of the batched launch are ordered in kBatchPhases phases: phase r
+// holds, graph after graph, the r-th 1/kBatchPhases share of every graph's
+// items, so the waves running at any moment spread over all graphs in
+// proportion to their size (few concurrent updates per node in every graph).
+constexpr uint32_t kBatchPhases = 32;
+
+struct BatchLaunch {
+  const BatchGraph* graphs;
+  const uint64_t* seg_off;     // kBatchPhases * n_graphs + 1 segment prefix (segment = phase * n + graph)
+  const uint64_t* path_blob;   // padded offsets of all graphs
+  const float* eta_all;        // [n_graphs][n_iters]
+  const uint32_t* zipf;
+  const uint16_t* guide;
+  uint64_t wave_stride;
+  uint64_t groups_per_item;
+  uint32_t n_graphs;
+  uint32_t path_slots_total;
+  uint32_t W;
+  uint32_t n_iters;
+  uint32_t iter;
+  uint32_t cool_all;
+  uint32_t k0, k1;
+};
+
+// Stress kernels (sampled path stress, differentiable loss).
+struct StressLaunch {
+  const StepRec* rec;
+  const float* coords;
+  const uint64_t* path_off;
+  const uint32_t* zipf;
+  const uint16_t* guide;
+  uint64_t n_nodes;
+  uint64_t S;
+  uint64_t count;          // steps (SPS) or pairs (loss)
+  uint32_t m;              // SPS pairs per step
+  uint32_t n_paths;
+  uint32_t path_slots;
+  uint32_t path_top;
+  uint32_t W;
+  uint32_t word2;          // counter word 2
+  uint32_t c3;
+  uint32_t k0, k1;
+};
+
+size_t layout_lds_bytes(uint32_t path_slots, uint32_t W);
+size_t batch_lds_bytes(uint32_t n_graphs, uint32_t path_slots_total, uint32_t W);
+hipError_t launch_layout_iter(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
+hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const uint64_t* i, const uint64_t* j,
+                              const uint8_t* f, uint64_t count, hipStream_t s);
+// boundary layout [2][n][2] <-> interleaved working copy [n][2](x, y)
+hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s);
+hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s);
+hipError_t launch_layout_batch(const BatchLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
+const void* layout_iter_kernel();
+const void* layout_batch_kernel();
+
+// SPS: pass 1 writes per-block (sum, n_valid, n_skipped); pass 2 per-block sum
+// of squared deviations from mean_dev.  Final reductions write to out.
+constexpr uint32_t kStressBlocks = 2048;
+constexpr uint32_t kStressThreads = 256;
+hipError_t launch_sps_pass(const StressLaunch& P, int pass, const double* mean_dev, double* part_f,
+                           uint64_t* part_n, uint64_t* part_skip, hipStream_t s);
+// out_f[0] = sum of part_f; out_n[0..1] = sums of part_n / part_skip;
+// if mean_out: mean_out[0] = out_f[0] / out_n[0].
+hipError_t launch_reduce_parts(const double* part_f, const uint64_t* part_n, const uint64_t* part_skip,
+                               uint32_t n_parts, double* out_f, uint64_t* out_n, double* mean_out,
+                               float* loss_out, uint64_t* n_valid_out, hipStream_t s);
+hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
+hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,
+                             hipStream_t s);
+hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, uint32_t k0,
+                              uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s);
+hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, uint64_t* first_step,
+                              hipStream_t s);
+hipError_t launch_adam(float* x, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
+
+}  // namespace pgsgd

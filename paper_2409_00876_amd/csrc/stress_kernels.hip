@@ -1,0 +1,351 @@
+// Stress kernels for gfx950: the sampled path stress of Eq. 2 (two passes for
+// the CI95), the differentiable loss and its adjoint, the initial layout and a
+// fused Adam step.
+//
+// Stress terms are evaluated in FP64 from the float32 coordinates with FMA
+// contraction off, so each term is the exactly rounded value of
+// ((|v_i - v_j| - d)/d)^2; block partials are FP64 and reduced in a fixed
+// order, so results are deterministic for a given launch shape.
+#include "device.h"
+#include "internal.h"
+
+namespace pgsgd {
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums over the block; the result is valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch) {
+  v = wave_sum(v);
+  const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63u) == 0) scratch[w] = v;
+  __syncthreads();
+  T r = 0;
+  if (threadIdx.x == 0)
+    for (uint32_t k = 0; k < nw; ++k) r += scratch[k];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void fill_offsets(uint64_t* off, const StressLaunch& P) {
+  for (uint32_t k = threadIdx.x; k < P.path_slots; k += blockDim.x) off[k] = k <= P.n_paths ? P.path_off[k] : ~0ull;
+}
+
+// Stress of one pair of slots in FP64.  Returns false when d == 0.
+__device__ __forceinline__ bool pair_terms(const StepRec* __restrict__ rec, uint64_t i, uint64_t j, uint32_t ei,
+                                           uint32_t ej, uint64_t& a, uint64_t& b, double& d) {
+  const StepRec si = load_rec(rec, i);
+  const StepRec sj = load_rec(rec, j);
+  const int64_t dd = endpoint_pos(si, ei) - endpoint_pos(sj, ej);
+  a = 2ull * (si.node_rev & kNodeMask) + ei;
+  b = 2ull * (sj.node_rev & kNodeMask) + ej;
+  d = (double)(dd < 0 ? -dd : dd);
+  return dd != 0;
+}
+
+__device__ __forceinline__ double stress_fp64(const float* __restrict__ X, const float* __restrict__ Y, uint64_t a,
+                                              uint64_t b, double d, double& dx, double& dy, double& mag) {
+#pragma clang fp contract(off)
+  dx = (double)X[a] - (double)X[b];
+  dy = (double)Y[a] - (double)Y[b];
+  mag = sqrt(dx * dx + dy * dy);
+  const double e = (mag - d) / d;
+  return e * e;
+}
+
+// ---------------------------------------------------------------------------
+// Sampled path stress: thread-strided over steps s; step s owns pairs
+// q = m*s .. m*s+m-1, which all belong to the path of s.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, const double* __restrict__ mean_dev,
+                                             double* __restrict__ part_f, uint64_t* __restrict__ part_n,
+                                             uint64_t* __restrict__ part_skip) {
+  extern __shared__ __align__(16) char lds[];
+  uint64_t* off = reinterpret_cast<uint64_t*>(lds);
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  fill_offsets(off, P);
+  __syncthreads();
+  const double mean = pass == 2 ? mean_dev[0] : 0.0;
+  const float* __restrict__ X = P.coords;
+  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
+  double acc = 0.0;
+  uint64_t nv = 0, ns = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < P.S; s += stride) {
+    const uint32_t p = find_path(off, P.path_top, s);
+    const uint64_t start = off[p], len = off[p + 1] - start;
+    for (uint32_t k = 0; k < P.m; ++k) {
+      const uint64_t q = (uint64_t)P.m * s + k;
+      const Rand4 r = philox10((uint32_t)q, (uint32_t)(q >> 32), 0u, P.c3, P.k0, P.k1);
+      const uint64_t i = start + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), len);
+      const uint64_t j = start + mulhi32(r.r2, (uint32_t)len);
+      uint64_t a, b;
+      double d;
+      if (!pair_terms(P.rec, i, j, r.r3 & 1u, (r.r3 >> 1) & 1u, a, b, d)) {
+        ++ns;
+        continue;
+      }
+      double dx, dy, mag;
+      const double st = stress_fp64(X, Y, a, b, d, dx, dy, mag);
+      if (pass == 1) {
+        acc += st;
+        ++nv;
+      } else {
+#pragma clang fp contract(off)
+        acc += (st - mean) * (st - mean);
+      }
+    }
+  }
+  acc = block_sum(acc, red_f);
+  nv = block_sum(nv, red_n);
+  ns = block_sum(ns, red_n);
+  if (threadIdx.x == 0) {
+    part_f[blockIdx.x] = acc;
+    if (part_n) part_n[blockIdx.x] = nv;
+    if (part_skip) part_skip[blockIdx.x] = ns;
+  }
+}
+
+// One block sums the partials in a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce_parts(const double* __restrict__ part_f,
+                                                       const uint64_t* __restrict__ part_n,
+                                                       const uint64_t* __restrict__ part_skip, uint32_t n_parts,
+                                                       double* out_f, uint64_t* out_n, double* mean_out,
+                                                       float* loss_out, uint64_t* n_valid_out) {
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  double f = 0.0;
+  uint64_t n = 0, sk = 0;
+  for (uint32_t k = threadIdx.x; k < n_parts; k += blockDim.x) {
+    f += part_f[k];
+    if (part_n) n += part_n[k];
+    if (part_skip) sk += part_skip[k];
+  }
+  f = block_sum(f, red_f);
+  n = block_sum(n, red_n);
+  sk = block_sum(sk, red_n);
+  if (threadIdx.x == 0) {
+    if (out_f) out_f[0] = f;
+    if (out_n) {
+      if (part_n) out_n[0] = n;
+      if (part_skip) out_n[1] = sk;
+    }
+    if (mean_out) mean_out[0] = n ? f / (double)n : 0.0;
+    if (loss_out) loss_out[0] = n ? (float)(f / (double)n) : 0.0f;
+    if (n_valid_out) n_valid_out[0] = n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Differentiable loss: pairs q in [0, count) from the power-law sampler.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool loss_pair(const StressLaunch& P, const uint64_t* off, const uint32_t* zipf,
+                                          const uint16_t* guide, uint64_t q, uint64_t& a, uint64_t& b, double& d) {
+  const Rand4 r = philox10((uint32_t)q, (uint32_t)(q >> 32), P.word2, P.c3, P.k0, P.k1);
+  const uint64_t i = mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), P.S);
+  const uint32_t p = find_path(off, P.path_top, i);
+  const uint64_t start = off[p], len = off[p + 1] - start;
+  uint64_t j;
+  if (!partner_power_law(i, start, len, r.r2, r.r3, zipf, guide, P.W, j)) return false;
+  if (!pair_terms(P.rec, i, j, r.r3 & 1u, (r.r3 >> 1) & 1u, a, b, d)) return false;
+  return a != b;
+}
+
+__device__ __forceinline__ void fill_loss_lds(char* lds, const StressLaunch& P, uint64_t*& off, uint32_t*& zipf,
+                                              uint16_t*& guide) {
+  off = reinterpret_cast<uint64_t*>(lds);
+  zipf = reinterpret_cast<uint32_t*>(lds + (size_t)P.path_slots * 8);
+  guide = reinterpret_cast<uint16_t*>(lds + (size_t)P.path_slots * 8 + (size_t)(P.W + 1) * 4);
+  fill_offsets(off, P);
+  for (uint32_t k = threadIdx.x; k <= P.W; k += blockDim.x) zipf[k] = P.zipf[k];
+  for (uint32_t k = threadIdx.x; k <= kGuideSize; k += blockDim.x) guide[k] = P.guide[k];
+}
+
+__global__ __launch_bounds__(256) void k_stress_fwd(StressLaunch P, double* __restrict__ part_f,
+                                                    uint64_t* __restrict__ part_n) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  uint64_t* off;
+  uint32_t* zipf;
+  uint16_t* guide;
+  fill_loss_lds(lds, P, off, zipf, guide);
+  __syncthreads();
+  const float* __restrict__ X = P.coords;
+  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
+  double acc = 0.0;
+  uint64_t nv = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.count; q += stride) {
+    uint64_t a, b;
+    double d;
+    if (!loss_pair(P, off, zipf, guide, q, a, b, d)) continue;
+    double dx, dy, mag;
+    acc += stress_fp64(X, Y, a, b, d, dx, dy, mag);
+    ++nv;
+  }
+  acc = block_sum(acc, red_f);
+  nv = block_sum(nv, red_n);
+  if (threadIdx.x == 0) {
+    part_f[blockIdx.x] = acc;
+    part_n[blockIdx.x] = nv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_stress_bwd(StressLaunch P, const float* __restrict__ grad_out,
+                                                    const uint64_t* __restrict__ n_valid,
+                                                    float* __restrict__ grad) {
+  extern __shared__ __align__(16) char lds[];
+  uint64_t* off;
+  uint32_t* zipf;
+  uint16_t* guide;
+  fill_loss_lds(lds, P, off, zipf, guide);
+  __syncthreads();
+  const uint64_t n = n_valid[0];
+  if (n == 0) return;
+  const double scale = (double)grad_out[0] * 2.0 / (double)n;
+  const float* __restrict__ X = P.coords;
+  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
+  float* __restrict__ GX = grad;
+  float* __restrict__ GY = grad + 2ull * P.n_nodes;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.count; q += stride) {
+    uint64_t a, b;
+    double d;
+    if (!loss_pair(P, off, zipf, guide, q, a, b, d)) continue;
+    double dx, dy, mag;
+    (void)stress_fp64(X, Y, a, b, d, dx, dy, mag);
+    if (mag == 0.0) continue;
+    const double c = scale * (mag - d) / (d * d) / mag;
+    const float gx = (float)(c * dx), gy = (float)(c * dy);
+    unsafeAtomicAdd(&GX[a], gx);
+    unsafeAtomicAdd(&GY[a], gy);
+    unsafeAtomicAdd(&GX[b], -gx);
+    unsafeAtomicAdd(&GY[b], -gy);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial layout and first visits
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
+}
+
+__global__ __launch_bounds__(256) void k_first_visit(const StepRec* __restrict__ rec, uint64_t S,
+                                                     uint64_t* __restrict__ first) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
+    const uint32_t node = rec[s].node_rev & kNodeMask;
+    atomicMin(reinterpret_cast<unsigned long long*>(&first[node]), (unsigned long long)s);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init_coords(const StepRec* __restrict__ rec,
+                                                     const uint64_t* __restrict__ first, uint64_t n_nodes,
+                                                     uint32_t k0, uint32_t k1, uint32_t c3, float jitter,
+                                                     float* __restrict__ coords) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  float* __restrict__ X = coords;
+  float* __restrict__ Y = coords + 2 * n_nodes;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 2 * n_nodes; k += stride) {
+    const uint64_t s = first[k >> 1];
+    float x = 0.0f;
+    if (s != ~0ull) {
+      const StepRec r = load_rec(rec, s);
+      x = (float)(r.pos + (int64_t)r.len * (int64_t)(k & 1));
+    }
+    X[k] = x;
+    const Rand4 rn = philox10((uint32_t)k, (uint32_t)(k >> 32), 0u, c3, k0, k1);
+    const float u = (float)(rn.r0 >> 8) * (1.0f / 16777216.0f);
+    Y[k] = jitter * (u - 0.5f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam (Kingma and Ba, 2015); c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ x, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, uint64_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    x[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static size_t loss_lds_bytes(const StressLaunch& P) {
+  return (size_t)P.path_slots * 8 + (size_t)(P.W + 1) * 4 + (size_t)(kGuideSize + 1) * 2;
+}
+
+static uint32_t grid_for(uint64_t n, uint32_t cap) {
+  const uint64_t b = (n + 255) / 256;
+  return (uint32_t)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+hipError_t launch_sps_pass(const StressLaunch& P, int pass, const double* mean_dev, double* part_f,
+                           uint64_t* part_n, uint64_t* part_skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_sps, dim3(kStressBlocks), dim3(kStressThreads), (size_t)P.path_slots * 8, s, P, pass,
+                     mean_dev, part_f, part_n, part_skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const double* part_f, const uint64_t* part_n, const uint64_t* part_skip,
+                               uint32_t n_parts, double* out_f, uint64_t* out_n, double* mean_out,
+                               float* loss_out, uint64_t* n_valid_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, s, part_f, part_n, part_skip, n_parts, out_f, out_n,
+                     mean_out, loss_out, n_valid_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s) {
+  hipLaunchKernelGGL(k_stress_fwd, dim3(kStressBlocks), dim3(kStressThreads), loss_lds_bytes(P), s, P, part_f,
+                     part_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_stress_bwd, dim3(kStressBlocks), dim3(kStressThreads), loss_lds_bytes(P), s, P, grad_out,
+                     n_valid, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, uint64_t* first_step,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n_nodes, 4096)), dim3(256), 0, s, first_step, n_nodes, ~0ull);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 0) return e;
+  hipLaunchKernelGGL(k_first_visit, dim3(grid_for(S, 8192)), dim3(256), 0, s, rec, S, first_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, uint32_t k0,
+                              uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_coords, dim3(grid_for(2 * n_nodes, 8192)), dim3(256), 0, s, rec, first_step, n_nodes,
+                     k0, k1, c3, jitter, coords);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* x, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 8192)), dim3(256), 0, s, x, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace pgsgd

@@ -1,0 +1,447 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (from the method's definition):
+  - sampled terms (i, j, flags) bit-exact, recorded by the production layout
+    kernel with the production launch shape;
+  - one collision-free batch of updates within 1e-5 (relative to max(|x|, 1))
+    of the pure-FP64 oracle;
+  - sampled path stress of the same layout: identical pair counts, sums within
+    1e-9 relative (FP64 terms, different summation order);
+  - full Hogwild layouts: sampled path stress within 3% of the oracle's (several
+    layouts are correct, so only this statistic is compared; means over layout
+    seeds where a single layout's spread would exceed the bar);
+  - differentiable loss within 1e-5, gradient against the oracle's analytic
+    FP64 gradient and FP64 finite differences.
+"""
+import glob
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2409_00876_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def P():
+    return _P()
+
+
+@pytest.fixture(scope="module")
+def tiny(P):
+    sg = synth.config_graph("tiny")
+    return sg, O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+
+
+@pytest.fixture(scope="module")
+def mid(P):
+    sg = synth.config_graph("mid")
+    return sg, O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+
+
+def _edge_synth():
+    # a single-step path, an empty path, a path revisiting a node on both strands, a longer path
+    node_len = np.array([5, 1, 3, 2, 7, 1, 4, 2, 9, 3], np.uint32)
+    R = synth.REV_BIT
+    paths = [[4], [], [0, 1, 2 | R, 1 | R, 3, 2], list(range(10)) + [9 | R, 8 | R, 7 | R] + list(range(3, 10))]
+    off = np.cumsum([0] + [len(p) for p in paths]).astype(np.uint64)
+    steps = np.array([s for p in paths for s in p], np.uint32)
+    return synth.SynthGraph(node_len, off, steps, {}, "edge")
+
+
+def _to_np_u64(t):
+    return t.cpu().numpy().astype(np.uint64)
+
+
+def _compare_terms(P, g, og, it, t0, count, **kw):
+    i, j, f = P.sample_terms(g, it, t0, count, **kw)
+    oi, oj, of = O.sample_terms(og, it, t0, count, **{k: v for k, v in kw.items() if k in ("seed", "graph_id")})
+    gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
+    bad = np.nonzero((gi != oi) | (gj != oj) | (gf != of))[0]
+    assert bad.size == 0, f"iter {it} t0 {t0}: {bad.size} mismatches, first at t={t0 + bad[0]}: " \
+                          f"gpu ({gi[bad[0]]},{gj[bad[0]]},{gf[bad[0]]}) oracle ({oi[bad[0]]},{oj[bad[0]]},{of[bad[0]]})"
+    return gf
+
+
+# ---------------------------------------------------------------------------
+# graph upload and initial layout
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+def test_graph_info_and_init_coords(P, which, request):
+    sg, og, g = request.getfixturevalue(which)
+    assert (g.n_steps, g.n_nodes, g.n_paths, g.d_max) == (og.S, og.n_nodes, og.n_paths, og.d_max)
+    c = g.new_coords()
+    P.init_coords(g, c, seed=5, jitter=10.0)
+    assert np.array_equal(c.cpu().numpy(), O.init_coords(og, seed=5, jitter=10.0))
+
+
+def test_edge_graph_upload_and_sampling(P):
+    sg = _edge_synth()
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    assert (g.n_steps, g.d_max) == (og.S, og.d_max)
+    c = g.new_coords()
+    P.init_coords(g, c)
+    assert np.array_equal(c.cpu().numpy(), O.init_coords(og))
+    T = 10 * og.S
+    for it in (0, 7, 15, 29):
+        f = _compare_terms(P, g, og, it, 0, T)
+        assert f.size == T
+    # the single-step path is always skipped when cooling
+    i, j, f = O.sample_terms(og, 20, 0, T)
+    assert np.all((f[i == 0] >> 3) & 1)
+
+
+# ---------------------------------------------------------------------------
+# T1-T3: bit-exact sampling
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("it", [0, 14, 15, 29])
+@pytest.mark.parametrize("graph_id", [0, 7])
+def test_sampling_bitexact_tiny(P, tiny, it, graph_id):
+    sg, og, g = tiny
+    T = 10 * og.S  # whole iteration, ragged last group
+    _compare_terms(P, g, og, it, 0, T, graph_id=graph_id)
+    _compare_terms(P, g, og, it, 1000 + 7, 1 << 16, graph_id=graph_id, seed=99)
+
+
+@pytest.mark.parametrize("it", [0, 14, 15, 29])
+def test_sampling_bitexact_mid(P, mid, it):
+    sg, og, g = mid
+    T = 10 * og.S
+    _compare_terms(P, g, og, it, 0, 1 << 20)
+    _compare_terms(P, g, og, it, T // 2 + 5, 1 << 20, graph_id=7)
+    _compare_terms(P, g, og, it, T - (1 << 18) - 3, (1 << 18) + 3)  # the ragged end
+
+
+def test_sampling_bitexact_across_counter_carry(P, tiny, mid):
+    for sg, og, g in (tiny, mid):
+        _compare_terms(P, g, og, 3, (1 << 32) - (1 << 19) - 11, 1 << 20)
+
+
+def test_sampling_bitexact_large_range(P, mid):
+    sg, og, g = mid
+    _compare_terms(P, g, og, 0, 123456789, 1 << 22)
+
+
+# ---------------------------------------------------------------------------
+# T6b: one collision-free deterministic batch
+# ---------------------------------------------------------------------------
+def _collision_free(og, i, j, f, limit):
+    step_node = og.step_node
+    a = 2 * (step_node[i.astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + (f & 1)
+    b = 2 * (step_node[j.astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + ((f >> 1) & 1)
+    seen = set()
+    keep = []
+    for k in range(len(i)):
+        if f[k] & 8:
+            continue
+        if a[k] in seen or b[k] in seen:
+            continue
+        seen.add(int(a[k]))
+        seen.add(int(b[k]))
+        keep.append(k)
+        if len(keep) >= limit:
+            break
+    return np.array(keep, np.int64)
+
+
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+@pytest.mark.parametrize("it", [0, 25])
+def test_collision_free_batch_matches_fp64(P, which, it, request):
+    import torch
+    sg, og, g = request.getfixturevalue(which)
+    K = 65536
+    i, j, f = P.sample_terms(g, it, 0, K)
+    gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
+    keep = _collision_free(og, gi, gj, gf, K)
+    assert keep.size > 1000
+    eta = float(P.schedule(d_max=og.d_max)[it])
+    rng = np.random.default_rng(it)
+    start = O.init_coords(og)
+    start = (start + rng.normal(scale=20.0, size=start.shape)).astype(np.float32)
+    c = torch.from_numpy(start).cuda()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    P.apply_terms(g, c, eta, dev(gi[keep].astype(np.int64)), dev(gj[keep].astype(np.int64)), dev(gf[keep]))
+    got = c.cpu().numpy().astype(np.float64)
+    ref = start.astype(np.float64)
+    applied = O.apply_terms_f64(og, eta, gi[keep], gj[keep], gf[keep], ref)
+    assert applied > 0.9 * keep.size
+    # Relative error per coordinate, relative to the magnitude of the update's
+    # operands: the two points' coordinates on that axis before and after (FP32
+    # inputs carry an absolute rounding proportional to them, so a coordinate
+    # that cancels to ~0 cannot be more accurate than that).
+    n2 = 2 * og.n_nodes
+    ki = keep
+    a = 2 * (og.step_node[gi[ki].astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + (gf[ki] & 1)
+    b = 2 * (og.step_node[gj[ki].astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + ((gf[ki] >> 1) & 1)
+    scale = np.ones_like(ref)
+    for off in (0, n2):
+        m = np.maximum.reduce([np.abs(start[off + a]), np.abs(start[off + b]), np.abs(ref[off + a]),
+                               np.abs(ref[off + b]), np.ones(a.size)])
+        scale[off + a] = np.maximum(scale[off + a], m)
+        scale[off + b] = np.maximum(scale[off + b], m)
+    err = np.abs(got - ref) / scale
+    assert err.max() <= 1e-5, f"max relative error {err.max():.3e}"
+    touched = np.zeros(ref.size, bool)
+    touched[a] = touched[b] = touched[n2 + a] = touched[n2 + b] = True
+    assert np.array_equal(got[~touched], start[~touched].astype(np.float64)), "untouched coordinates changed"
+    moved = np.abs(ref - start) > 0
+    assert moved.sum() >= applied  # the batch really moved points
+
+
+# ---------------------------------------------------------------------------
+# T9: sampled path stress of the same layout
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which,m", [("tiny", 100), ("mid", 1)])
+def test_sps_equals_oracle_on_same_layout(P, which, m, request):
+    import torch
+    sg, og, g = request.getfixturevalue(which)
+    rng = np.random.default_rng(1)
+    c0 = O.init_coords(og)
+    c0 = (c0 + rng.normal(scale=50.0, size=c0.shape)).astype(np.float32)
+    r = P.path_stress(g, torch.from_numpy(c0).cuda(), m, 7)
+    o = O.sampled_path_stress(og, c0, m, 7)
+    assert r["n_valid"] == o["n_valid"] and r["n_skipped"] == o["n_skipped"]
+    assert r["n_valid"] + r["n_skipped"] == m * og.S
+    assert abs(r["sum"] - o["sum"]) <= 1e-9 * abs(o["sum"])
+    assert abs(r["sumsq_dev"] - o["sumsq_dev"]) <= 1e-9 * abs(o["sumsq_dev"])
+    assert abs(r["ci_hi"] - o["ci_hi"]) <= 1e-9 * abs(o["ci_hi"])
+
+
+# ---------------------------------------------------------------------------
+# T7 + T10: full layouts
+# ---------------------------------------------------------------------------
+def test_linear_path_converges_on_gpu(P):
+    import torch
+    sg = synth.linear_path(2000)
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    c0 = O.init_coords(og)
+    c = torch.from_numpy(c0).cuda()
+    P.layout(g, c)
+    s_gpu = P.path_stress(g, c, 100, 7)["mean"]
+    co = c0.copy()
+    O.layout(og, co)
+    s_ora = O.sampled_path_stress(og, co, 100, 7)["mean"]
+    assert s_gpu < 1e-3 and s_gpu <= max(1.5 * s_ora, 1e-3)
+
+
+def test_full_layout_sps_parity_tiny(P, tiny):
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    seeds = [101, 102, 103, 104, 105, 106]
+    gpu, ora, gpu_sps = [], [], []
+    for sd in seeds:
+        c = torch.from_numpy(c0).cuda()
+        P.layout(g, c, seed=sd)
+        cg = c.cpu().numpy()
+        gpu.append(O.sps_expectation(og, cg)[0])
+        gpu_sps.append(P.path_stress(g, c, 100, 7)["mean"])
+        co = c0.copy()
+        O.layout(og, co, seed=sd)
+        ora.append(O.sps_expectation(og, co)[0])
+    ratio = np.mean(gpu) / np.mean(ora)
+    print(f"tiny: GPU {np.mean(gpu):.6f} oracle {np.mean(ora):.6f} ratio {ratio:.4f} "
+          f"(oracle seed spread {np.std(ora) / np.mean(ora):.4f}); GPU SPS(m=100) {np.mean(gpu_sps):.6f}")
+    assert abs(ratio - 1) <= 0.03
+
+
+def _mid_goldens():
+    out = []
+    for fn in sorted(glob.glob(os.path.join(GOLDEN, "oracle_sps_mid_seed*_t1.json"))):
+        with open(fn) as f:
+            out.append(json.load(f))
+    return out
+
+
+def test_full_layout_sps_parity_mid(P, mid):
+    import torch
+    goldens = _mid_goldens()
+    if not goldens:
+        pytest.skip("no stored oracle result for mid (tests/golden/make_golden.py writes it)")
+    sg, og, g = mid
+    c0 = O.init_coords(og)
+    gpu, ora = [], []
+    for rec in goldens:
+        assert rec["graph"]["n_steps"] == og.S and rec["graph"]["n_nodes"] == og.n_nodes
+        c = torch.from_numpy(c0).cuda()
+        P.layout(g, c, seed=rec["layout_seed"])
+        s = P.path_stress(g, c, rec["sps_m"], rec["sps_seed"])
+        gpu.append(s["mean"])
+        ora.append(rec["sps_mean"])
+        print(f"mid seed {rec['layout_seed']}: GPU SPS {s['mean']:.5f} [{s['ci_lo']:.5f}, {s['ci_hi']:.5f}] "
+              f"oracle {rec['sps_mean']:.5f} [{rec['sps_ci_lo']:.5f}, {rec['sps_ci_hi']:.5f}]")
+    ratio = np.mean(gpu) / np.mean(ora)
+    assert abs(ratio - 1) <= 0.03, f"GPU/oracle SPS ratio {ratio:.4f}"
+
+
+# ---------------------------------------------------------------------------
+# T12: differentiable form
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_diff(P):
+    sg = synth.generate(500, 0.2, 32, 2)  # the mid model on a 500-node backbone
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    rng = np.random.default_rng(7)
+    c = O.init_coords(og)
+    c = (c + rng.normal(scale=5.0, size=c.shape)).astype(np.float32)
+    return sg, og, g, c
+
+
+def test_loss_and_gradient_match_oracle(P, small_diff):
+    import torch
+    sg, og, g, c0 = small_diff
+    n_pairs, step = 200_000, 3
+    c = torch.from_numpy(c0).cuda()
+    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11)
+    L_ref, n_ref, grad_ref = O.stress_loss_grad(og, c0, n_pairs, seed=11, step=step)
+    assert int(nv.item()) == n_ref
+    assert abs(float(loss.item()) - L_ref) <= 1e-5 * abs(L_ref)
+    grad = torch.zeros_like(c)
+    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11)
+    gg = grad.cpu().numpy().astype(np.float64)
+    gmax = np.abs(grad_ref).max()
+    sel = np.abs(grad_ref) > 1e-6 * gmax
+    err = np.abs(gg - grad_ref)
+    assert np.all(err[sel] <= 1e-4 * np.abs(grad_ref[sel]) + 1e-6 * gmax), \
+        f"max rel err {np.max(err[sel] / np.abs(grad_ref[sel])):.3e}"
+    assert np.all(err[~sel] <= 1e-6 * gmax)
+
+
+def test_gradient_matches_fp64_finite_differences(P, small_diff):
+    import torch
+    sg, og, g, c0 = small_diff
+    n_pairs, step = 50_000, 1
+    c = torch.from_numpy(c0).cuda()
+    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11)
+    grad = torch.zeros_like(c)
+    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11)
+    gg = grad.cpu().numpy().astype(np.float64)
+    gmax = np.abs(gg).max()
+    rng = np.random.default_rng(3)
+    cand = np.nonzero(np.abs(gg) > 1e-3 * gmax)[0]
+    for k in rng.choice(cand, size=min(40, cand.size), replace=False):
+        h = np.float32(2.0 ** (np.floor(np.log2(max(1.0, abs(float(c0[k]))))) - 14))
+        cp, cm = c0.copy(), c0.copy()
+        cp[k] += h
+        cm[k] -= h
+        Lp = O.stress_loss_grad(og, cp, n_pairs, seed=11, step=step, want_grad=False)[0]
+        Lm = O.stress_loss_grad(og, cm, n_pairs, seed=11, step=step, want_grad=False)[0]
+        fd = (Lp - Lm) / (float(cp[k]) - float(cm[k]))
+        assert abs(fd - gg[k]) <= 1e-3 * abs(fd) + 1e-6 * gmax, (k, fd, gg[k])
+
+
+def test_autograd_function_and_adam_reduce_loss(P, small_diff):
+    import torch
+    sg, og, g, c0 = small_diff
+    x = torch.from_numpy(c0).cuda().requires_grad_(True)
+    loss = P.SampledPathStress.apply(x, g, 100_000, 0, P.LayoutParams(seed=11))
+    loss.backward()
+    ref = torch.zeros_like(x)
+    l2, nv = P.stress_forward(g, x.detach(), 100_000, 0, seed=11)
+    P.stress_backward(g, x.detach(), 100_000, 0, torch.ones(1, device="cuda"), nv, ref, seed=11)
+    assert torch.allclose(x.grad, ref, rtol=1e-5, atol=1e-7 * float(ref.abs().max()))
+    # a few Adam steps on resampled pairs lower the loss
+    xs = torch.from_numpy(c0).cuda()
+    m, v = torch.zeros_like(xs), torch.zeros_like(xs)
+    first = None
+    for t in range(1, 41):
+        loss, nv = P.stress_forward(g, xs, 100_000, t, seed=11)
+        first = float(loss.item()) if first is None else first
+        gr = torch.zeros_like(xs)
+        P.stress_backward(g, xs, 100_000, t, torch.ones(1, device="cuda"), nv, gr, seed=11)
+        P.adam_step(xs, gr, m, v, t, lr=1.0)
+    last = float(P.stress_forward(g, xs, 100_000, 999, seed=11)[0].item())
+    assert last < 0.7 * first
+
+
+def test_adam_matches_pytorch_fp32_reference(P):
+    import torch
+    n = 10_000
+    gen = torch.Generator().manual_seed(0)
+    x0 = torch.randn(n, generator=gen)
+    x, m, v = x0.clone().cuda(), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    xr, mr, vr = x0.clone(), torch.zeros(n), torch.zeros(n)
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 0.5
+    for t in range(1, 6):
+        gcpu = torch.randn(n, generator=gen)
+        P.adam_step(x, gcpu.cuda(), m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        mr = b1 * mr + (1 - b1) * gcpu
+        vr = b2 * vr + (1 - b2) * gcpu * gcpu
+        xr = xr - lr * (mr / (1 - b1 ** t)) / (torch.sqrt(vr / (1 - b2 ** t)) + eps)
+    assert torch.allclose(x.cpu(), xr, rtol=1e-5, atol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# T11: batched form
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_batch(P):
+    sgs = synth.batched_graphs(4, scale=0.0008)
+    return sgs, [O.Graph.from_synth(s) for s in sgs], [P.Graph.from_synth(s) for s in sgs]
+
+
+@pytest.mark.parametrize("it", [0, 15])
+def test_batched_sampling_bitexact(P, small_batch, it):
+    sgs, ogs, gs = small_batch
+    tunes = [None, {"block_threads": 256, "groups_per_item": 1, "blocks_per_cu": 1},
+             {"block_threads": 1024, "groups_per_item": 16, "blocks_per_cu": 2, "max_blocks": 3}]
+    outs = [P.batch_sample_terms(gs, it, tune=t, graph_id=5) for t in tunes]
+    for k, og in enumerate(ogs):
+        oi, oj, of = O.sample_terms(og, it, 0, 10 * og.S, graph_id=5 + k)
+        for out in outs:
+            i, j, f = out[k]
+            assert np.array_equal(_to_np_u64(i), oi), f"graph {k}: i differs"
+            assert np.array_equal(_to_np_u64(j), oj), f"graph {k}: j differs"
+            assert np.array_equal(f.cpu().numpy(), of), f"graph {k}: flags differ"
+
+
+def test_batched_layout_matches_plain_quality(P, small_batch):
+    import torch
+    sgs, ogs, gs = small_batch
+    init = [O.init_coords(og) for og in ogs]
+    cb = [torch.from_numpy(c).cuda() for c in init]
+    # one wave: these graphs have only 1.6K-3.9K nodes (see the automatic cap of layout())
+    tune = {"block_threads": 64, "groups_per_item": 1, "blocks_per_cu": 1, "max_blocks": 1}
+    P.layout_batched(gs, cb, tune=tune, graph_id=0)
+    ratios = []
+    for k, (og, g) in enumerate(zip(ogs, gs)):
+        co = init[k].copy()
+        O.layout(og, co, graph_id=k)
+        s_b = O.sps_expectation(og, cb[k].cpu().numpy())[0]
+        s_o = O.sps_expectation(og, co)[0]
+        ratios.append(s_b / s_o)
+    print("batched/oracle exact-SPS ratios:", [round(r, 4) for r in ratios])
+    assert abs(np.mean(ratios) - 1) <= 0.03
+
+
+def test_batch_handle_runs_and_autotune_keeps_coords(P, small_batch):
+    import torch
+    sgs, ogs, gs = small_batch
+    cs = [g.new_coords() for g in gs]
+    for g, c in zip(gs, cs):
+        P.init_coords(g, c)
+    before = [c.clone() for c in cs]
+    res = P.autotune(gs, cs, use_cache=False, max_blocks=4)
+    assert res["block_threads"] % 64 == 0 and res["groups_per_item"] >= 1 and res["max_blocks"] == 4
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(before, cs))
+    b = P.Batch(gs, cs, tune=res, first_iter=0, last_iter=2)
+    b.run()
+    torch.cuda.synchronize()
+    assert any(not torch.equal(a, c) for a, c in zip(before, cs))
+    b.close()
