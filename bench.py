@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DOMINANT = {False: "k_layout_iter", True: "k_bin_layout"}  # by schedule: plain, binned
 ALG_BYTES_PER_TERM = 64  # 2 step records (16 B each) + 2 endpoints read (8 B each) + written (8 B each)
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
 PROFILE_COMMANDS = """rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline
@@ -38,8 +39,8 @@ rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o fetch -- python3 b
 rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o write -- python3 bench.py --profile
 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d gpurun_out/prof_tcc -o tcc -- python3 bench.py --profile
 python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv"""
-KERNEL_SOURCES = ["paper_2409_00876_amd/csrc/layout_kernels.hip", "paper_2409_00876_amd/csrc/device.h",
-                  "paper_2409_00876_amd/csrc/internal.h"]
+KERNEL_SOURCES = ["paper_2409_00876_amd/csrc/layout_kernels.hip", "paper_2409_00876_amd/csrc/binned_kernels.hip",
+                  "paper_2409_00876_amd/csrc/device.h", "paper_2409_00876_amd/csrc/internal.h"]
 
 
 def kernel_source_hash() -> str:
@@ -58,7 +59,7 @@ def stored_traffic(terms_per_launch: int):
             rec = json.load(f)
     except (OSError, ValueError):
         return None, None
-    if rec.get("kernel_source_sha") != kernel_source_hash() or rec.get("terms_per_launch") != terms_per_launch:
+    if rec.get("kernel_source_sha") != kernel_source_hash() or rec.get("terms_per_iteration") != terms_per_launch:
         return None, rec
     return rec.get("traffic_bytes_per_launch"), rec
 
@@ -79,51 +80,63 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
     import csv
     copy_bytes = 1 << 30
 
-    def per_kernel(rows, counter):
-        lay = [v for k, c, v in rows if c == counter and k.startswith("pgsgd::k_layout_iter")]
-        cp = [v for k, c, v in rows if c == counter and "copyBuffer" in k]
-        return lay, max(cp)  # the 1 GiB calibration copy is the largest copy
+    fetch_rows = _read_counters(fetch_csv)
+    names = {k for k, c, v in fetch_rows}
+    dom = "pgsgd::k_bin_layout" if any(k.startswith("pgsgd::k_bin_layout") for k in names) else "pgsgd::k_layout_iter"
+    iter_kernels = ("pgsgd::k_bin_", "pgsgd::k_layout_iter")
 
-    f_lay, f_copy = per_kernel(_read_counters(fetch_csv), "FETCH_SIZE")
-    w_lay, w_copy = per_kernel(_read_counters(write_csv), "WRITE_SIZE")
+    def per_kernel(rows, counter):
+        lay = [v for k, c, v in rows if c == counter and k.startswith(dom)]
+        it = sum(v for k, c, v in rows if c == counter and k.startswith(iter_kernels))
+        cp = [v for k, c, v in rows if c == counter and "copyBuffer" in k]
+        return lay, it, max(cp)  # the 1 GiB calibration copy is the largest copy
+
+    f_lay, f_it, f_copy = per_kernel(fetch_rows, "FETCH_SIZE")
+    w_lay, w_it, w_copy = per_kernel(_read_counters(write_csv), "WRITE_SIZE")
     tcc = _read_counters(tcc_csv)
-    hits = [v for k, c, v in tcc if c == "TCC_HIT_sum" and k.startswith("pgsgd::k_layout_iter")]
-    miss = [v for k, c, v in tcc if c == "TCC_MISS_sum" and k.startswith("pgsgd::k_layout_iter")]
+    hits = [v for k, c, v in tcc if c == "TCC_HIT_sum" and k.startswith(dom)]
+    miss = [v for k, c, v in tcc if c == "TCC_MISS_sum" and k.startswith(dom)]
     f_factor = copy_bytes / (f_copy * 1024)
     w_factor = copy_bytes / (w_copy * 1024)
     fetch_b = [v * 1024 * f_factor for v in f_lay]
     write_b = [v * 1024 * w_factor for v in w_lay]
+    n_iter_profiled = 2  # --profile runs iterations 0 and 15
+    launches = len(fetch_b) // n_iter_profiled
     stats = None
     for name in os.listdir(trace_dir):
         if name.endswith("kernel_stats.csv"):
             with open(os.path.join(trace_dir, name)) as f:
                 for r in csv.DictReader(f):
-                    if r["Name"].startswith("pgsgd::k_layout_iter"):
+                    if r["Name"].startswith(dom):
                         stats = r
     import synth
     sg = synth.config_graph("chromosome")
     T = 10 * sg.n_steps
     avg_ns = float(stats["AverageNs"])
     traffic = (sum(fetch_b) + sum(write_b)) / len(fetch_b)
-    rec = {"kernel": "k_layout_iter", "workload": "chromosome", "terms_per_launch": T,
+    it_traffic = (f_it * 1024 * f_factor + w_it * 1024 * w_factor) / n_iter_profiled
+    rec = {"kernel": dom.split("::")[1], "workload": "chromosome", "terms_per_launch": T / launches,
+           "launches_per_iteration": launches, "terms_per_iteration": T,
            "kernel_source_sha": kernel_source_hash(), "command": command,
            "trace_avg_launch_ms": avg_ns / 1e6, "trace_calls": int(stats["Calls"]),
            "fetch_calibration_factor": f_factor, "write_calibration_factor": w_factor,
            "fetch_bytes_per_launch": sum(fetch_b) / len(fetch_b), "write_bytes_per_launch": sum(write_b) / len(write_b),
-           "traffic_bytes_per_launch": traffic, "traffic_bytes_per_term": traffic / T,
+           "traffic_bytes_per_launch": traffic, "traffic_bytes_per_term": traffic / (T / launches),
            "traffic_gbs_at_trace_duration": traffic / (avg_ns * 1e-9) / 1e9,
+           "iteration_traffic_bytes": it_traffic, "iteration_traffic_bytes_per_term": it_traffic / T,
            "l2_hit_rate": sum(hits) / (sum(hits) + sum(miss)),
-           "l2_misses_per_term": sum(miss) / len(miss) / T}
+           "l2_misses_per_term": sum(miss) / len(miss) / (T / launches)}
     out = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
     md = out[:-5] + ".md"
     with open(md, "w") as f:
-        f.write(f"# k_layout_iter, chromosome workload: rocprofv3 summary\n\n")
+        f.write(f"# {rec['kernel']}, chromosome workload: rocprofv3 summary\n\n")
         f.write(f"Commands (from the repository root, with TMPDIR=/tmp):\n\n```\n{command}\n```\n\n")
         f.write("| quantity | value |\n|---|---|\n")
         f.write(f"| kernel-trace calls / average duration | {rec['trace_calls']} / {rec['trace_avg_launch_ms']:.2f} ms |\n")
-        f.write(f"| terms per launch | {T:,} |\n")
+        f.write(f"| terms per launch / launches per iteration | {T / launches:,.0f} / {launches} |\n")
+        f.write(f"| all kernels of an iteration: traffic per term | {it_traffic / T:.1f} B |\n")
         f.write(f"| FETCH_SIZE calibration (1 GiB copy) | x{f_factor:.4f} |\n")
         f.write(f"| WRITE_SIZE calibration (1 GiB copy) | x{w_factor:.4f} |\n")
         f.write(f"| fetched bytes per launch (calibrated) | {rec['fetch_bytes_per_launch'] / 1e9:.1f} GB |\n")
@@ -135,6 +148,107 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
         f.write(f"| L2 misses per term | {rec['l2_misses_per_term']:.2f} |\n")
         f.write(f"\nkernel source sha256[:16]: `{rec['kernel_source_sha']}`\n")
     print(json.dumps(rec, indent=1))
+
+
+def form_batched(n_graphs: int = 24, scale: float = 1.0) -> dict:
+    """Batched form: the uneven chromosome-like graphs laid out by one captured
+    HIP graph of persistent launches, against sequential plain runs of the same
+    graphs on the same GPU, compared at equal sampled path stress (per graph)."""
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    t0 = time.time()
+    sgs = synth.batched_graphs(n_graphs, scale=scale)
+    gen_s = time.time() - t0
+    t0 = time.time()
+    gs = [P.Graph.from_synth(s) for s in sgs]
+    create_s = time.time() - t0
+    cs = [g.new_coords() for g in gs]
+    for g, c in zip(gs, cs):
+        P.init_coords(g, c)
+    tune = P.autotune(gs, cs, use_cache=False)
+    terms = 30 * 10 * sum(g.n_steps for g in gs)
+    # sequential plain runs
+    for g, c in zip(gs, cs):
+        P.init_coords(g, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, (g, c) in enumerate(zip(gs, cs)):
+        P.layout(g, c, graph_id=k)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    sps_seq = [P.path_stress(g, c, 10, 7, graph_id=k)["mean"] for k, (g, c) in enumerate(zip(gs, cs))]
+    # one batched run
+    for g, c in zip(gs, cs):
+        P.init_coords(g, c)
+    b = P.Batch(gs, cs, tune=tune, graph_id=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - t0
+    sps_bat = [P.path_stress(g, c, 10, 7, graph_id=k)["mean"] for k, (g, c) in enumerate(zip(gs, cs))]
+    b.close()
+    ratios = [x / y for x, y in zip(sps_bat, sps_seq)]
+    import math
+    geo = math.exp(sum(math.log(r) for r in ratios) / len(ratios))
+    return {"graphs": n_graphs, "nodes": sum(g.n_nodes for g in gs), "path_steps": sum(g.n_steps for g in gs),
+            "term_updates": terms, "tune": tune, "generate_s": gen_s, "create_s": create_s,
+            "sequential_s": seq_s, "batched_s": bat_s, "sequential_terms_per_s": terms / seq_s,
+            "batched_terms_per_s": terms / bat_s, "speedup": seq_s / bat_s,
+            "sps_ratio_batched_over_sequential_geomean": geo,
+            "sps_ratio_min": min(ratios), "sps_ratio_max": max(ratios)}
+
+
+def form_autograd(workload: str = "mid", n_pairs: int = 10_000_000, budget: int = 1000,
+                  lrs=(1.0, 10.0, 100.0), check_every: int = 50) -> dict:
+    """Differentiable form: sampled stress over power-law pairs as a loss,
+    minimised with Adam on the device, against the plain PG-SGD loop; both
+    judged by the paper's sampled path stress (uniform pairs)."""
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    sg = synth.config_graph(workload)
+    g = P.Graph.from_synth(sg)
+    c = g.new_coords()
+    P.init_coords(g, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.layout(g, c)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    target = P.path_stress(g, c, 10, 7)["mean"]
+    P.init_coords(g, c)
+    init_sps = P.path_stress(g, c, 10, 7)["mean"]
+    runs = []
+    one = torch.ones(1, device=c.device)
+    for lr in lrs:
+        x = g.new_coords()
+        P.init_coords(g, x)
+        m, v, gr = torch.zeros_like(x), torch.zeros_like(x), torch.zeros_like(x)
+        hist = []
+        reached = None
+        elapsed = 0.0
+        for step in range(1, budget + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loss, nv = P.stress_forward(g, x, n_pairs, step, seed=11)
+            gr.zero_()
+            P.stress_backward(g, x, n_pairs, step, one, nv, gr, seed=11)
+            P.adam_step(x, gr, m, v, step, lr=lr)
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            if step % check_every == 0 or step == budget:
+                s = P.path_stress(g, x, 10, 7)["mean"]
+                hist.append((step, elapsed, s))
+                if reached is None and s <= target:
+                    reached = (step, elapsed)
+                    break
+        runs.append({"lr": lr, "best_sps": min(h[2] for h in hist), "steps_run": hist[-1][0],
+                     "seconds": elapsed, "reached_plain_sps_at": reached,
+                     "ms_per_step": elapsed / hist[-1][0] * 1e3})
+    return {"workload": workload, "n_pairs": n_pairs, "plain_seconds": plain_s, "plain_sps": target,
+            "initial_sps": init_sps, "adam": runs}
 
 
 def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:
@@ -164,6 +278,9 @@ def main():
     ap.add_argument("--workload", default="chromosome", choices=["tiny", "mid", "chromosome"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--form", choices=["batched", "autograd"], default=None,
+                    help="measure one of the two forms against the plain loop instead (separate JSON line)")
+    ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--summarize", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "TCC_CSV"),
                     help="write the committed counter summaries from rocprofv3 outputs (no GPU)")
     a = ap.parse_args()
@@ -174,6 +291,13 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU (the layout of one graph is not "
                                    "sharded); run with --gpus 1"}))
         sys.exit(2)
+
+    if a.form == "batched":
+        print(json.dumps({"form": "batched", **form_batched(scale=a.batched_scale)}))
+        return
+    if a.form == "autograd":
+        print(json.dumps({"form": "autograd", **form_autograd()}))
+        return
 
     import torch
     import synth
@@ -203,21 +327,29 @@ def main():
         P.layout(g, coords, seed=params.seed + 1)
     torch.cuda.synchronize()
 
-    iter_ms = []
+    iter_ms, main_ms = [], []
+    launches = 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         P.init_coords(g, coords)
-        iter_ms.append(P.layout_timed(g, coords, params))
+        it_ms, mk_ms, launches = P.layout_timed(g, coords, params)
+        iter_ms += [float(x) for x in it_ms]
+        main_ms += [float(x) for x in mk_ms]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     n_terms = a.steps * params.n_iters * T
     value = n_terms / wall
-    all_ms = [float(x) for arr in iter_ms for x in arr]
-    avg_ms = sum(all_ms) / len(all_ms)
-    achieved = ALG_BYTES_PER_TERM * T / (avg_ms * 1e-3) / 1e9
+    avg_iter_ms = sum(iter_ms) / len(iter_ms)
+    avg_ms = sum(main_ms) / (len(main_ms) * launches)  # one launch of the dominant kernel
+    terms_per_launch = T / launches
+    achieved = ALG_BYTES_PER_TERM * terms_per_launch / (avg_ms * 1e-3) / 1e9
+    binned = params.schedule == 2 or (params.schedule == 0 and g.n_steps >= (1 << 22))
     traffic, counters = stored_traffic(T)
+    if traffic is not None and (counters.get("launches_per_iteration") != launches
+                                or counters.get("kernel") != DOMINANT[binned]):
+        traffic = None
 
     sps = P.path_stress(g, coords, pairs_per_step=10, seed=7)
     oracle_sps = None
@@ -249,14 +381,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_layout_iter", "avg_launch_ms": avg_ms,
-                     "bytes_per_term_algorithmic": ALG_BYTES_PER_TERM},
+                     "kernel": DOMINANT[binned], "avg_launch_ms": avg_ms,
+                     "launches_per_iteration": launches, "terms_per_launch": terms_per_launch,
+                     "bytes_per_term_algorithmic": ALG_BYTES_PER_TERM,
+                     "iteration_ms": avg_iter_ms,
+                     "iteration_frac": ALG_BYTES_PER_TERM * T / (avg_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "sps": {"mean": sps["mean"], "ci_lo": sps["ci_lo"], "ci_hi": sps["ci_hi"], "pairs_per_step": 10,
                 "oracle_mean": oracle_sps["sps_mean"] if oracle_sps else None,
                 "ratio_to_oracle": sps["mean"] / oracle_sps["sps_mean"] if oracle_sps else None},
     }
     if traffic is not None:
         rec["roofline"]["traffic_frac"] = traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        rec["roofline"]["iteration_traffic"] = counters.get("iteration_traffic_bytes")
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sg)
     print(json.dumps(rec))

@@ -119,9 +119,22 @@ typedef struct {
   uint64_t seed;              /* Philox key */
   uint32_t first_iter;        /* run iterations [first_iter, last_iter) ... */
   uint32_t last_iter;         /* ... ; last_iter = 0 means n_iters */
-  uint32_t max_inflight_waves;/* cap on concurrently running 64-term groups; 0 = automatic */
+  uint32_t max_inflight_waves;/* plain schedule: cap on concurrently running 64-term groups; 0 = automatic */
   uint32_t flags;             /* reserved, must be 0 */
+  uint32_t schedule;          /* processing order of an iteration's terms: PGSGD_SCHEDULE_* */
+  uint32_t reserved;          /* must be 0 */
 } pgsgd_params;
+
+/* Processing order of the terms of an iteration.  The sampled terms are the
+ * same in every schedule; only the order (and so the Hogwild interleaving)
+ * differs.
+ *   PLAIN   term groups in index order over a grid capped by max_inflight_waves
+ *   BINNED  terms binned by the window of consecutive path steps holding their
+ *           step i, windows processed XCD by XCD for L2 locality of the step
+ *           records and coordinates (uses scratch of 6 bytes per term of a
+ *           chunk of up to 2^30 terms, allocated on first use)
+ *   AUTO    BINNED for graphs with at least 2^22 steps, else PLAIN */
+enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_BINNED = 2 };
 
 /* Fills the defaults listed above (seed 24301, graph_id 0). */
 void pgsgd_params_default(pgsgd_params *p);
@@ -181,14 +194,17 @@ pgsgd_status pgsgd_init_coords(pgsgd_graph *g, uint64_t seed, uint32_t graph_id,
 pgsgd_status pgsgd_layout(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);
 
 /*
- * pgsgd_layout with measurement: HIP events recorded on `stream` right before
- * and after every iteration's kernel launch give that launch's duration in
- * milliseconds, written to iter_ms (host, last_iter - first_iter entries).
- * Synchronises the stream.  Same errors as pgsgd_layout, plus INVALID_ARG
- * when iter_ms is NULL.
+ * pgsgd_layout with measurement, by HIP events recorded on `stream`:
+ *   iter_ms[k]   duration of iteration first_iter + k (all its kernels)
+ *   main_ms[k]   summed duration of that iteration's launches of the dominant
+ *                kernel (the fused layout kernel of the schedule in use)
+ *   *main_launches  launches of the dominant kernel per iteration
+ * iter_ms and main_ms: host, last_iter - first_iter entries (main_ms and
+ * main_launches may be NULL).  Synchronises the stream.  Same errors as
+ * pgsgd_layout, plus INVALID_ARG when iter_ms is NULL.
  */
 pgsgd_status pgsgd_layout_timed(pgsgd_graph *g, const pgsgd_params *p, float *coords, float *iter_ms,
-                                void *stream);
+                                float *main_ms, uint32_t *main_launches, void *stream);
 
 /* ------------------------------------------------------------------------- */
 /* Sampled path stress (Eq. 2)                                               */
@@ -308,6 +324,11 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph *const *graphs, uint32_t n, co
  * Writes the terms t in [t_begin, t_begin + count) of iteration iter, sampled
  * exactly as pgsgd_layout samples them: i_out, j_out (device uint64) and
  * flags_out (device uint8: bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped).
+ * The terms are recorded by the layout kernel itself, with the launch shape
+ * pgsgd_layout uses: the plain kernel unless p->schedule is
+ * PGSGD_SCHEDULE_BINNED, in which case the binning kernels and the binned
+ * layout kernel process the whole iteration (without updating coordinates)
+ * and record the terms of the range, which must lie in [0, terms_per_step * S).
  * Async.
  */
 pgsgd_status pgsgd_sample_terms(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,

@@ -63,6 +63,8 @@ class LayoutParams:
     last_iter: int = 0
     max_inflight_waves: int = 0
     flags: int = 0
+    schedule: int = 0           # 0 auto, 1 plain, 2 binned
+    reserved: int = 0
 
     def to_c(self) -> Params:
         p = Params()
@@ -156,16 +158,21 @@ def layout(g: Graph, coords, params: LayoutParams | None = None, **kw):
     return coords
 
 
-def layout_timed(g: Graph, coords, params: LayoutParams | None = None, **kw) -> np.ndarray:
-    """layout() that also returns each iteration's kernel duration in ms (HIP events
-    on the current stream around every launch); synchronises."""
+def layout_timed(g: Graph, coords, params: LayoutParams | None = None, **kw):
+    """layout() with HIP-event timing on the current stream; synchronises.
+    Returns (iter_ms, main_ms, main_launches): each iteration's duration, the
+    summed duration of its dominant-kernel launches, and that kernel's launches
+    per iteration."""
     _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
     p = _params(params, kw)
     last = p.last_iter or p.n_iters
-    ms = np.zeros(max(1, last - p.first_iter), dtype=np.float32)
-    check(lib().pgsgd_layout_timed(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()), _np_ptr(ms),
-                                   _stream(torch, coords.device)))
-    return ms[: last - p.first_iter]
+    n = max(1, last - p.first_iter)
+    it_ms = np.zeros(n, dtype=np.float32)
+    main_ms = np.zeros(n, dtype=np.float32)
+    launches = ctypes.c_uint32()
+    check(lib().pgsgd_layout_timed(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()), _np_ptr(it_ms),
+                                   _np_ptr(main_ms), ctypes.byref(launches), _stream(torch, coords.device)))
+    return it_ms[: last - p.first_iter], main_ms[: last - p.first_iter], int(launches.value)
 
 
 def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, graph_id: int = 0) -> dict:
@@ -185,7 +192,7 @@ def sample_terms(g: Graph, iter: int, t_begin: int, count: int, params: LayoutPa
     dev = f"cuda:{g.device}"
     i = torch.empty(count, dtype=torch.int64, device=dev)
     j = torch.empty(count, dtype=torch.int64, device=dev)
-    f = torch.empty(count, dtype=torch.uint8, device=dev)
+    f = torch.full((count,), 255, dtype=torch.uint8, device=dev)  # 255 marks a term never recorded
     check(lib().pgsgd_sample_terms(g.handle, ctypes.byref(p), int(iter), int(t_begin), int(count),
                                    ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
                                    ctypes.c_void_p(f.data_ptr()), _stream(torch, dev)))

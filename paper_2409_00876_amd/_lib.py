@@ -18,6 +18,7 @@ ERR_RANGE = -2
 ERR_OOM = -3
 ERR_DEVICE = -4
 ERR_UNSUPPORTED = -5
+SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_BINNED = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "RANGE", -3: "OOM", -4: "DEVICE", -5: "UNSUPPORTED"}
 
 
@@ -41,6 +42,8 @@ class Params(ctypes.Structure):
         ("last_iter", ctypes.c_uint32),
         ("max_inflight_waves", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
+        ("schedule", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -93,7 +96,7 @@ SIGNATURES = {
     "pgsgd_zipf_table": ([_f64, _u32, _P], _i32),
     "pgsgd_init_coords": ([_P, _u64, _u32, _f32, _P, _P], _i32),
     "pgsgd_layout": ([_P, _P, _P, _P], _i32),
-    "pgsgd_layout_timed": ([_P, _P, _P, _P, _P], _i32),
+    "pgsgd_layout_timed": ([_P, _P, _P, _P, _P, _P, _P], _i32),
     "pgsgd_path_stress": ([_P, _P, _u32, _u64, _u32, _P, _P], _i32),
     "pgsgd_stress_forward": ([_P, _P, _P, _u64, _u32, _P, _P, _P], _i32),
     "pgsgd_stress_backward": ([_P, _P, _P, _u64, _u32, _P, _P, _P, _P], _i32),

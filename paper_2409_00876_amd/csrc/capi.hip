@@ -136,12 +136,23 @@ struct pgsgd_graph {
   double* d_mean = nullptr;
   size_t device_bytes = 0;
   int layout_blocks_per_cu = 0;  // occupancy of k_layout_iter, filled on first use
+  int bin_blocks_per_cu = 0;     // occupancy of k_bin_layout, filled on first use
+  // binning scratch (allocated on first binned layout)
+  uint64_t bin_chunk = 0;
+  uint32_t bin_nwin = 0, bin_shift = 0, bin_xstride = 0;
+  uint16_t* d_tag = nullptr;
+  uint32_t* d_entries = nullptr;
+  uint32_t* d_wcount = nullptr;
+  uint32_t* d_woff = nullptr;
+  uint32_t* d_cursor = nullptr;
+  uint32_t* d_xitem = nullptr;
 
   ~pgsgd_graph() {
     DeviceGuard g(device);
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
-                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean})
+                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_tag,
+                    (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem})
       if (p) (void)hipFree(p);
   }
 };
@@ -186,7 +197,8 @@ pgsgd_status ensure_zipf(pgsgd_graph* g, double theta, uint32_t W, hipStream_t s
 
 pgsgd_status check_params(const pgsgd_params* p) {
   if (!p) return fail(PGSGD_ERR_INVALID_ARG, "params is NULL");
-  if (p->flags != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags must be 0");
+  if (p->flags != 0 || p->reserved != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags and reserved must be 0");
+  if (p->schedule > PGSGD_SCHEDULE_BINNED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
   if (p->zipf_window < 1 || p->zipf_window > 65535)
     return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", p->zipf_window);
   if (!(p->zipf_theta >= 0.0) || !std::isfinite(p->zipf_theta))
@@ -280,6 +292,8 @@ void pgsgd_params_default(pgsgd_params* p) {
   p->last_iter = 0;
   p->max_inflight_waves = 0;
   p->flags = 0;
+  p->schedule = PGSGD_SCHEDULE_AUTO;
+  p->reserved = 0;
 }
 
 pgsgd_status pgsgd_schedule(const pgsgd_params* p, int64_t d_max, float* eta_out) {
@@ -531,18 +545,75 @@ extern "C" {
 
 namespace {
 
-// The layout loop; with iter_ms set, HIP events bracket every iteration's
-// launch on the stream and the durations are written there (synchronising).
-pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms, void* stream) {
-  if (!g || !coords) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
-  if (((uintptr_t)coords & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
+bool use_binned(const pgsgd_graph* g, const pgsgd_params* p) {
+  if (p->schedule == PGSGD_SCHEDULE_BINNED) return true;
+  if (p->schedule == PGSGD_SCHEDULE_PLAIN) return false;
+  return g->S >= (1ull << 22);
+}
+
+// Binning scratch for chunks of up to min(T, kBinChunk) terms: windows of
+// 2^shift steps (shift >= 16, at most kMaxBinWindows windows).
+pgsgd_status ensure_bins(pgsgd_graph* g, uint64_t n_terms, hipStream_t s) {
+  const uint64_t chunk = std::min<uint64_t>(((n_terms + 63) / 64) * 64, kBinChunk);
+  uint32_t shift = 16;
+  while (((g->S + (1ull << shift) - 1) >> shift) > kMaxBinWindows) ++shift;
+  const uint32_t nwin = (uint32_t)((g->S + (1ull << shift) - 1) >> shift);
+  if (g->d_tag && g->bin_chunk >= chunk && g->bin_nwin == nwin) return PGSGD_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  for (void** q : {(void**)&g->d_tag, (void**)&g->d_entries, (void**)&g->d_wcount, (void**)&g->d_woff,
+                   (void**)&g->d_cursor, (void**)&g->d_xitem})
+    if (*q) {
+      (void)hipFree(*q);
+      *q = nullptr;
+    }
+  g->bin_chunk = chunk;
+  g->bin_nwin = nwin;
+  g->bin_shift = shift;
+  g->bin_xstride = nwin / kXcds + 2;
+  pgsgd_status st;
+  if ((st = dev_alloc(g, &g->d_tag, chunk))) return st;
+  if ((st = dev_alloc(g, &g->d_entries, chunk))) return st;
+  if ((st = dev_alloc(g, &g->d_wcount, nwin))) return st;
+  if ((st = dev_alloc(g, &g->d_woff, nwin + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_cursor, nwin))) return st;
+  if ((st = dev_alloc(g, &g->d_xitem, (size_t)kXcds * g->bin_xstride))) return st;
+  HIP_TRY(launch_fill_u32(g->d_wcount, nwin, 0u, s));  // the histogram must start at zero
+  return PGSGD_OK;
+}
+
+pgsgd_status bin_blocks(pgsgd_graph* g, size_t lds, uint32_t* blocks) {
+  if (g->bin_blocks_per_cu <= 0) {
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bin_layout_kernel(), 256, lds));
+    g->bin_blocks_per_cu = nb > 0 ? nb : 1;
+  }
+  *blocks = (uint32_t)g->n_cu * (uint32_t)g->bin_blocks_per_cu;
+  *blocks = std::max<uint32_t>(kXcds, *blocks / kXcds * kXcds);
+  return PGSGD_OK;
+}
+
+// The layout loop.  With iter_ms set, HIP events bracket every iteration and
+// every launch of the dominant kernel, and the durations are written out
+// (synchronising).  With trace set (binned schedule only), iteration
+// first_iter is recorded instead of applied.
+pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms, float* main_ms,
+                         uint32_t* main_launches, void* stream, uint64_t* trace_i = nullptr,
+                         uint64_t* trace_j = nullptr, uint8_t* trace_f = nullptr, uint64_t trace_begin = 0,
+                         uint64_t trace_count = 0) {
+  const bool tracing = trace_f != nullptr;
+  if (!g || (!coords && !tracing)) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (coords && ((uintptr_t)coords & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
   pgsgd_status st = check_params(p);
   if (st) return st;
   if ((uint64_t)p->terms_per_step * g->S >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term count >= 2^48");
   const uint32_t last = p->last_iter == 0 ? p->n_iters : p->last_iter;
+  const uint32_t n_run = last - p->first_iter;
   if (iter_ms)
-    for (uint32_t it = p->first_iter; it < last; ++it) iter_ms[it - p->first_iter] = 0.0f;
-  if (g->S == 0 || p->n_iters == 0 || p->first_iter == last) return ok();
+    for (uint32_t k = 0; k < n_run; ++k) iter_ms[k] = 0.0f;
+  if (main_ms)
+    for (uint32_t k = 0; k < n_run; ++k) main_ms[k] = 0.0f;
+  if (main_launches) *main_launches = 0;
+  if (g->S == 0 || p->n_iters == 0 || n_run == 0) return ok();
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
   size_t lds;
@@ -554,12 +625,41 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   L.t_end = L.n_terms;
   L.g_begin = 0;
   L.g_end = L.n_groups;
-  uint32_t blocks, threads;
-  if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
-  L.wave_stride = (uint64_t)blocks * (threads / 64);
+  const bool binned = tracing || use_binned(g, p);
+  uint32_t blocks = 0, threads = 256;
+  BinLaunch B{};
+  uint64_t n_chunks = 1;
+  if (binned) {
+    if ((st = ensure_bins(g, L.n_terms, s))) return st;
+    if ((st = bin_blocks(g, lds, &blocks))) return st;
+    B.n_win = g->bin_nwin;
+    B.win_shift = g->bin_shift;
+    B.count_blocks = (uint32_t)g->n_cu * 2;
+    B.xstride = g->bin_xstride;
+    B.tag = g->d_tag;
+    B.entries = g->d_entries;
+    B.wcount = g->d_wcount;
+    B.woff = g->d_woff;
+    B.cursor = g->d_cursor;
+    B.xitem = g->d_xitem;
+    n_chunks = (L.n_terms + g->bin_chunk - 1) / g->bin_chunk;
+    L.wave_stride = 0;
+    L.trace_i = trace_i;
+    L.trace_j = trace_j;
+    L.trace_f = trace_f;
+    if (tracing) {
+      L.t_begin = trace_begin;
+      L.t_end = trace_begin + trace_count;
+    }
+  } else {
+    if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
+    L.wave_stride = (uint64_t)blocks * (threads / 64);
+  }
+  if (main_launches) *main_launches = (uint32_t)n_chunks;
   std::vector<hipEvent_t> ev;
+  const size_t ev_per_iter = 1 + 2 * n_chunks;
   if (iter_ms) {
-    ev.resize(last - p->first_iter + 1);
+    ev.resize(n_run * ev_per_iter + 1);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   }
   struct EventsFree {
@@ -568,19 +668,45 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
       for (auto e : v) (void)hipEventDestroy(e);
     }
   } events_free{ev};
-  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  if (!tracing) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
   for (uint32_t it = p->first_iter; it < last; ++it) {
+    const size_t e0 = (size_t)(it - p->first_iter) * ev_per_iter;
     L.iter = it;
     L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
     L.eta = eta[it];
-    if (iter_ms && it == p->first_iter) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_layout_iter(L, blocks, threads, s));
-    if (iter_ms) HIP_TRY(hipEventRecord(ev[it - p->first_iter + 1], s));
+    if (iter_ms) HIP_TRY(hipEventRecord(ev[e0], s));
+    if (binned) {
+      for (uint64_t c = 0; c < n_chunks; ++c) {
+        B.L = L;
+        B.c0 = c * g->bin_chunk;
+        B.c1 = std::min(L.n_terms, B.c0 + g->bin_chunk);
+        HIP_TRY(launch_bin_count_scan_scatter(B, s));
+        if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1 + 2 * c], s));
+        HIP_TRY(launch_bin_layout(B, blocks, s));
+        if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2 + 2 * c], s));
+      }
+    } else {
+      if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1], s));
+      HIP_TRY(launch_layout_iter(L, blocks, threads, s));
+      if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
+    }
+    if (tracing) break;
   }
-  HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
+  if (iter_ms) HIP_TRY(hipEventRecord(ev.back(), s));
+  if (!tracing) HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
   if (iter_ms) {
     HIP_TRY(hipEventSynchronize(ev.back()));
-    for (uint32_t k = 0; k + 1 < ev.size(); ++k) HIP_TRY(hipEventElapsedTime(&iter_ms[k], ev[k], ev[k + 1]));
+    for (uint32_t k = 0; k < n_run; ++k) {
+      const size_t e0 = (size_t)k * ev_per_iter;
+      const hipEvent_t end = (k + 1 < n_run) ? ev[e0 + ev_per_iter] : ev.back();
+      HIP_TRY(hipEventElapsedTime(&iter_ms[k], ev[e0], end));
+      if (main_ms)
+        for (uint64_t c = 0; c < n_chunks; ++c) {
+          float ms = 0.0f;
+          HIP_TRY(hipEventElapsedTime(&ms, ev[e0 + 1 + 2 * c], ev[e0 + 2 + 2 * c]));
+          main_ms[k] += ms;
+        }
+    }
   }
   return ok();
 }
@@ -590,13 +716,13 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
 extern "C" {
 
 pgsgd_status pgsgd_layout(pgsgd_graph* g, const pgsgd_params* p, float* coords, void* stream) {
-  return layout_impl(g, p, coords, nullptr, stream);
+  return layout_impl(g, p, coords, nullptr, nullptr, nullptr, stream);
 }
 
 pgsgd_status pgsgd_layout_timed(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms,
-                                void* stream) {
+                                float* main_ms, uint32_t* main_launches, void* stream) {
   if (!iter_ms) return fail(PGSGD_ERR_INVALID_ARG, "iter_ms is NULL");
-  return layout_impl(g, p, coords, iter_ms, stream);
+  return layout_impl(g, p, coords, iter_ms, main_ms, main_launches, stream);
 }
 
 pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t iter, uint64_t t_begin,
@@ -608,6 +734,16 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t 
   if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
   if (t_begin + count < t_begin || t_begin + count >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term range too large");
   if (count == 0 || g->S == 0) return ok();
+  if (p->schedule == PGSGD_SCHEDULE_BINNED) {
+    // the binning kernels and the binned layout kernel process the whole
+    // iteration; the terms of [t_begin, t_begin + count) are recorded
+    if (t_begin + count > (uint64_t)p->terms_per_step * g->S)
+      return fail(PGSGD_ERR_INVALID_ARG, "the binned schedule records terms of the iteration only (t < T)");
+    pgsgd_params q = *p;
+    q.first_iter = iter;
+    q.last_iter = iter + 1;
+    return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, i_out, j_out, flags_out, t_begin, count);
+  }
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
   size_t lds;

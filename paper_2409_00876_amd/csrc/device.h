@@ -128,6 +128,26 @@ __device__ __forceinline__ StepRec load_rec(const StepRec* __restrict__ rec, uin
   return r;
 }
 
+// One sampled term of an iteration.
+struct Term {
+  uint64_t i, j;
+  uint32_t flags;  // bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped by sampling
+};
+
+// Gathers the two step records, forms the slots and the reference distance.
+// Returns false if the term is skipped (same slot or zero distance).
+__device__ __forceinline__ bool resolve_term(const StepRec* __restrict__ rec, const Term& T, uint64_t& a,
+                                             uint64_t& b, float& d) {
+  const StepRec si = load_rec(rec, T.i);
+  const StepRec sj = load_rec(rec, T.j);
+  const uint32_t ei = T.flags & 1u, ej = (T.flags >> 1) & 1u;
+  a = 2ull * (si.node_rev & kNodeMask) + ei;
+  b = 2ull * (sj.node_rev & kNodeMask) + ej;
+  const int64_t dd = endpoint_pos(si, ei) - endpoint_pos(sj, ej);
+  d = (float)(dd < 0 ? -dd : dd);
+  return a != b && dd != 0;
+}
+
 // The clamped SGD step for one pair of points a, b with reference distance d
 // (Zheng et al.'s update, which the paper follows for "move against the
 // gradient"): mu = min(eta / d^2, 1), r = mu (mag - d) / (2 mag), a -= r delta,

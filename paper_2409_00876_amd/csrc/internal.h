@@ -29,6 +29,7 @@ struct LayoutLaunch {
   uint32_t c3;             // stream << 24 | graph_id
   uint32_t k0, k1;         // Philox key
   float eta;
+  uint32_t pad_;
   // term range [t_begin, t_end) of this launch, as 64-term groups [g_begin, g_end)
   uint64_t t_begin, t_end;
   uint64_t g_begin, g_end;
@@ -37,6 +38,28 @@ struct LayoutLaunch {
   uint64_t* trace_i;
   uint64_t* trace_j;
   uint8_t* trace_f;
+};
+
+// Binned processing of one iteration (binned_kernels.hip): terms are binned by
+// the window of 2^win_shift consecutive steps holding their step i and the
+// windows are processed XCD by XCD.
+constexpr uint32_t kXcds = 8;                 // gfx950: 8 XCDs, blocks dispatched round-robin
+constexpr uint32_t kMaxBinWindows = 8192;     // LDS histogram of 32 KB
+constexpr uint64_t kBinChunk = 1ull << 30;    // terms per binning pass (4-byte offsets, bit 31 = coin)
+
+struct BinLaunch {
+  LayoutLaunch L;          // sampling parameters, coordinates, trace pointers
+  uint64_t c0, c1;         // term chunk [c0, c1), c0 a multiple of 64
+  uint32_t n_win;          // ceil(S / 2^win_shift)
+  uint32_t win_shift;
+  uint32_t count_blocks;   // grid of the count and scatter kernels
+  uint32_t xstride;        // row length of xitem
+  uint16_t* tag;           // [chunk] window | coin << 15
+  uint32_t* entries;       // [chunk] term offset | coin << 31, window-contiguous
+  uint32_t* wcount;        // [n_win] histogram (zero between chunks)
+  uint32_t* woff;          // [n_win + 1] window offsets
+  uint32_t* cursor;        // [n_win] scatter cursors
+  uint32_t* xitem;         // [kXcds][xstride] prefix of 64-term items over the windows of each XCD
 };
 
 // Per-graph header of the batched launch.
@@ -113,6 +136,9 @@ hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, h
 hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s);
 hipError_t launch_layout_batch(const BatchLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 const void* layout_iter_kernel();
+hipError_t launch_bin_count_scan_scatter(const BinLaunch& B, hipStream_t s);
+hipError_t launch_bin_layout(const BinLaunch& B, uint32_t blocks, hipStream_t s);
+const void* bin_layout_kernel();
 const void* layout_batch_kernel();
 
 // SPS: pass 1 writes per-block (sum, n_valid, n_skipped); pass 2 per-block sum
@@ -133,6 +159,7 @@ hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, ui
                               uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s);
 hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, uint64_t* first_step,
                               hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_adam(float* x, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
 

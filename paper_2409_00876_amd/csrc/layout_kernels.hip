@@ -40,12 +40,7 @@ __device__ __forceinline__ void lds_fill(const LdsView& v, const uint64_t* __res
   for (uint32_t k = threadIdx.x; k <= kGuideSize; k += blockDim.x) v.guide[k] = guide[k];
 }
 
-// Sampling of term t (all integer).  Returns the flags byte.
-struct Term {
-  uint64_t i, j;
-  uint32_t flags;  // bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped by sampling
-};
-
+// Sampling of term t (all integer): step, path, partner, flags.
 __device__ __forceinline__ Term sample_term(const Rand4& r, bool cooling, uint64_t S, const LdsView& L,
                                             uint32_t path_top, uint32_t W) {
   Term T;
@@ -61,20 +56,6 @@ __device__ __forceinline__ Term sample_term(const Rand4& r, bool cooling, uint64
   }
   T.flags = (r.r3 & 3u) | ((cooling ? 1u : 0u) << 2) | ((ok ? 0u : 1u) << 3);
   return T;
-}
-
-// Gathers the two step records, forms the slots and the reference distance.
-// Returns false if the term is skipped (same slot or zero distance).
-__device__ __forceinline__ bool resolve_term(const StepRec* __restrict__ rec, const Term& T, uint64_t& a,
-                                             uint64_t& b, float& d) {
-  const StepRec si = load_rec(rec, T.i);
-  const StepRec sj = load_rec(rec, T.j);
-  const uint32_t ei = T.flags & 1u, ej = (T.flags >> 1) & 1u;
-  a = 2ull * (si.node_rev & kNodeMask) + ei;
-  b = 2ull * (sj.node_rev & kNodeMask) + ej;
-  const int64_t dd = endpoint_pos(si, ei) - endpoint_pos(sj, ej);
-  d = (float)(dd < 0 ? -dd : dd);
-  return a != b && dd != 0;
 }
 
 __global__ __launch_bounds__(256) void k_layout_iter(LayoutLaunch P) {

@@ -239,6 +239,11 @@ __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p, uint
   for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
 }
 
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
+}
+
 __global__ __launch_bounds__(256) void k_first_visit(const StepRec* __restrict__ rec, uint64_t S,
                                                      uint64_t* __restrict__ first) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -332,6 +337,11 @@ hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || S == 0) return e;
   hipLaunchKernelGGL(k_first_visit, dim3(grid_for(S, 8192)), dim3(256), 0, s, rec, S, first_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 4096)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

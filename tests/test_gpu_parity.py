@@ -138,6 +138,39 @@ def test_sampling_bitexact_large_range(P, mid):
 
 
 # ---------------------------------------------------------------------------
+# The binned schedule: the same terms, recorded by its own kernels
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("it", [0, 15])
+def test_binned_sampling_bitexact_mid(P, mid, it):
+    import torch
+    sg, og, g = mid
+    T = 10 * og.S
+    for t0, n in ((0, 1 << 20), (T // 3 + 17, 1 << 18), (T - (1 << 18) - 3, (1 << 18) + 3)):
+        _compare_terms(P, g, og, it, t0, n, schedule=2)
+    # the whole iteration: every term recorded once, equal to the plain kernel's record
+    bi, bj, bf = P.sample_terms(g, it, 0, T, schedule=2)
+    assert not bool((bf == 255).any()), "a term was not processed by the binned schedule"
+    pi, pj, pf = P.sample_terms(g, it, 0, T, schedule=1)
+    assert torch.equal(bi, pi) and torch.equal(bj, pj) and torch.equal(bf, pf)
+
+
+@pytest.fixture(scope="module")
+def chromosome(P):
+    sg = synth.config_graph("chromosome")
+    return sg, O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+
+
+@pytest.mark.parametrize("it", [0, 29])
+def test_binned_sampling_bitexact_chromosome(P, chromosome, it):
+    # full size, in the launch shape the benchmark times (binned, 4 chunks)
+    sg, og, g = chromosome
+    T = 10 * og.S
+    for t0, n in ((0, 1 << 20), ((1 << 30) - (1 << 19), 1 << 20), (T - (1 << 20) - 5, (1 << 20) + 5)):
+        f = _compare_terms(P, g, og, it, t0, n, schedule=2)
+        assert not np.any(f == 255)
+
+
+# ---------------------------------------------------------------------------
 # T6b: one collision-free deterministic batch
 # ---------------------------------------------------------------------------
 def _collision_free(og, i, j, f, limit):
@@ -268,7 +301,8 @@ def _mid_goldens():
     return out
 
 
-def test_full_layout_sps_parity_mid(P, mid):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_full_layout_sps_parity_mid(P, mid, schedule):
     import torch
     goldens = _mid_goldens()
     if not goldens:
@@ -279,11 +313,11 @@ def test_full_layout_sps_parity_mid(P, mid):
     for rec in goldens:
         assert rec["graph"]["n_steps"] == og.S and rec["graph"]["n_nodes"] == og.n_nodes
         c = torch.from_numpy(c0).cuda()
-        P.layout(g, c, seed=rec["layout_seed"])
+        P.layout(g, c, seed=rec["layout_seed"], schedule=schedule)
         s = P.path_stress(g, c, rec["sps_m"], rec["sps_seed"])
         gpu.append(s["mean"])
         ora.append(rec["sps_mean"])
-        print(f"mid seed {rec['layout_seed']}: GPU SPS {s['mean']:.5f} [{s['ci_lo']:.5f}, {s['ci_hi']:.5f}] "
+        print(f"mid seed {rec['layout_seed']} schedule {schedule}: GPU SPS {s['mean']:.5f} [{s['ci_lo']:.5f}, {s['ci_hi']:.5f}] "
               f"oracle {rec['sps_mean']:.5f} [{rec['sps_ci_lo']:.5f}, {rec['sps_ci_hi']:.5f}]")
     ratio = np.mean(gpu) / np.mean(ora)
     assert abs(ratio - 1) <= 0.03, f"GPU/oracle SPS ratio {ratio:.4f}"
