@@ -157,16 +157,29 @@ def form_batched(n_graphs: int = 24, scale: float = 1.0) -> dict:
     import torch
     import synth
     import paper_2409_00876_amd as P
+
+    def note(msg):
+        print(f"[batched] {msg}", file=sys.stderr, flush=True)
+
     t0 = time.time()
-    sgs = synth.batched_graphs(n_graphs, scale=scale)
+    sizes = synth.batched_backbones(n_graphs)
+    sgs = []
+    for k, b in enumerate(sizes):
+        sgs.append(synth.generate(max(2, int(b * scale)), 0.05, 90, 1000 + k, name=f"batched{k}"))
+        note(f"generated graph {k}: {sgs[-1].n_steps} steps")
     gen_s = time.time() - t0
     t0 = time.time()
-    gs = [P.Graph.from_synth(s) for s in sgs]
+    gs = []
+    for s_ in sgs:
+        gs.append(P.Graph.from_synth(s_))
+        note(f"uploaded graph {len(gs) - 1}")
     create_s = time.time() - t0
     cs = [g.new_coords() for g in gs]
     for g, c in zip(gs, cs):
         P.init_coords(g, c)
+    note("autotuning")
     tune = P.autotune(gs, cs, use_cache=False)
+    note(f"tune {tune}")
     terms = 30 * 10 * sum(g.n_steps for g in gs)
     # sequential plain runs
     for g, c in zip(gs, cs):
@@ -175,7 +188,8 @@ def form_batched(n_graphs: int = 24, scale: float = 1.0) -> dict:
     t0 = time.perf_counter()
     for k, (g, c) in enumerate(zip(gs, cs)):
         P.layout(g, c, graph_id=k)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        note(f"sequential layout {k} done at {time.perf_counter() - t0:.1f} s")
     seq_s = time.perf_counter() - t0
     sps_seq = [P.path_stress(g, c, 10, 7, graph_id=k)["mean"] for k, (g, c) in enumerate(zip(gs, cs))]
     # one batched run
@@ -183,10 +197,12 @@ def form_batched(n_graphs: int = 24, scale: float = 1.0) -> dict:
         P.init_coords(g, c)
     b = P.Batch(gs, cs, tune=tune, graph_id=0)
     torch.cuda.synchronize()
+    note("batched run")
     t0 = time.perf_counter()
     b.run()
     torch.cuda.synchronize()
     bat_s = time.perf_counter() - t0
+    note(f"batched run done in {bat_s:.1f} s")
     sps_bat = [P.path_stress(g, c, 10, 7, graph_id=k)["mean"] for k, (g, c) in enumerate(zip(gs, cs))]
     b.close()
     ratios = [x / y for x, y in zip(sps_bat, sps_seq)]
@@ -251,6 +267,70 @@ def form_autograd(workload: str = "mid", n_pairs: int = 10_000_000, budget: int 
             "initial_sps": init_sps, "adam": runs}
 
 
+def sps_vs_ps_layouts(n_graphs: int = 24, stages=(0, 1, 2, 4, 7, 11, 16, 30), m: int = 100):
+    """Layouts of graded quality on small synthetic graphs (the mid model with
+    200-1000-node backbones, 4-16 paths), each measured with the sampled path
+    stress (Eq. 2) and the exact path stress (Eq. 1) on the GPU."""
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    out = []
+    for k in range(n_graphs):
+        sg = synth.generate(200 + 37 * k, 0.2, 4 + (k % 13), 5000 + k)
+        g = P.Graph.from_synth(sg)
+        c = g.new_coords()
+        P.init_coords(g, c)
+        done = 0
+        for st in stages:
+            if st > done:
+                P.layout(g, c, first_iter=done, last_iter=st, max_inflight_waves=1)
+                done = st
+            sps = P.path_stress(g, c, m, 7)["mean"]
+            ps, pairs = P.path_stress_exact(g, c)
+            out.append({"graph": k, "iterations": st, "sps": sps, "ps": ps, "pairs": pairs})
+        g.close()
+        torch.cuda.synchronize()
+    return out
+
+
+def form_metric() -> dict:
+    """Sampled path stress against exact path stress over graded layouts (the
+    analogue of the paper's correlation study), plus the run time of both
+    metrics on the mid graph's final layout."""
+    import math
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    rows = sps_vs_ps_layouts()
+    xs = [r["sps"] for r in rows]
+    ys = [r["ps"] for r in rows]
+
+    def pearson(a, b):
+        ma, mb = sum(a) / len(a), sum(b) / len(b)
+        sab = sum((x - ma) * (y - mb) for x, y in zip(a, b))
+        sa = math.sqrt(sum((x - ma) ** 2 for x in a))
+        sb = math.sqrt(sum((y - mb) ** 2 for y in b))
+        return sab / (sa * sb)
+
+    r_raw = pearson(xs, ys)
+    r_log = pearson([math.log(x) for x in xs], [math.log(y) for y in ys])
+    sg = synth.config_graph("tiny")
+    g = P.Graph.from_synth(sg)
+    c = g.new_coords()
+    P.init_coords(g, c)
+    P.layout(g, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.path_stress(g, c, 100, 7)
+    t_sps = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P.path_stress_exact(g, c)
+    t_ps = time.perf_counter() - t0
+    return {"layouts": len(rows), "pearson_raw": r_raw, "pearson_log": r_log,
+            "sps_range": [min(xs), max(xs)], "ps_range": [min(ys), max(ys)],
+            "tiny_seconds": {"sps_m100": t_sps, "ps_exact": t_ps}}
+
+
 def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:
     import oracle as O
     og = O.Graph.from_synth(sg)
@@ -278,7 +358,7 @@ def main():
     ap.add_argument("--workload", default="chromosome", choices=["tiny", "mid", "chromosome"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
-    ap.add_argument("--form", choices=["batched", "autograd"], default=None,
+    ap.add_argument("--form", choices=["batched", "autograd", "metric"], default=None,
                     help="measure one of the two forms against the plain loop instead (separate JSON line)")
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--summarize", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "TCC_CSV"),
@@ -297,6 +377,9 @@ def main():
         return
     if a.form == "autograd":
         print(json.dumps({"form": "autograd", **form_autograd()}))
+        return
+    if a.form == "metric":
+        print(json.dumps({"form": "metric", **form_metric()}))
         return
 
     import torch
@@ -345,7 +428,7 @@ def main():
     avg_ms = sum(main_ms) / (len(main_ms) * launches)  # one launch of the dominant kernel
     terms_per_launch = T / launches
     achieved = ALG_BYTES_PER_TERM * terms_per_launch / (avg_ms * 1e-3) / 1e9
-    binned = params.schedule == 2 or (params.schedule == 0 and g.n_steps >= (1 << 22))
+    binned = params.schedule == 2
     traffic, counters = stored_traffic(T)
     if traffic is not None and (counters.get("launches_per_iteration") != launches
                                 or counters.get("kernel") != DOMINANT[binned]):

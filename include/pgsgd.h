@@ -133,7 +133,8 @@ typedef struct {
  *           step i, windows processed XCD by XCD for L2 locality of the step
  *           records and coordinates (uses scratch of 6 bytes per term of a
  *           chunk of up to 2^30 terms, allocated on first use)
- *   AUTO    BINNED for graphs with at least 2^22 steps, else PLAIN */
+ *   AUTO    PLAIN (on MI355X the binned order raises the layout kernel's L2
+ *           hit rate but not its speed, and adds the binning passes) */
 enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_BINNED = 2 };
 
 /* Fills the defaults listed above (seed 24301, graph_id 0). */
@@ -231,6 +232,18 @@ typedef struct {
  */
 pgsgd_status pgsgd_path_stress(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
                                uint32_t graph_id, pgsgd_stress_result *out, void *stream);
+
+/*
+ * Path stress, Eq. 1 (Section "Path Stress"): over every path and every pair of
+ * its steps i < j, the stress averaged over the endpoint combinations with
+ * d > 0 (a pair with none is left out), then the mean over all such pairs.
+ * Each step pair counts once, so paths weigh with |p|^2 (Eq. 2 weighs them
+ * with |p|).  Terms in FP64 from the float32 coordinates.  O(sum |p|^2) work:
+ * meant for small graphs and for validating the sampled metric.  coords:
+ * device; mean_out (and pairs_out, may be NULL): host.  Synchronises.
+ */
+pgsgd_status pgsgd_path_stress_exact(pgsgd_graph *g, const float *coords, double *mean_out, uint64_t *pairs_out,
+                                     void *stream);
 
 /* ------------------------------------------------------------------------- */
 /* Differentiable form: sampled stress as a loss                             */

@@ -21,7 +21,7 @@ import torch
 
 from ._lib import (GraphInfo, Params, PgsgdError, StressResult, Tune, check, lib)  # noqa: F401
 
-__all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "schedule", "zipf_table",
+__all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
            "sample_terms", "apply_terms", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
@@ -183,6 +183,16 @@ def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, grap
     check(lib().pgsgd_path_stress(g.handle, ctypes.c_void_p(coords.data_ptr()), int(pairs_per_step), int(seed),
                                   int(graph_id), ctypes.byref(r), _stream(torch, coords.device)))
     return {f[0]: getattr(r, f[0]) for f in StressResult._fields_}
+
+
+def path_stress_exact(g: Graph, coords):
+    """Path stress (Eq. 1) over all same-path step pairs; returns (mean, pairs). Synchronises."""
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    mean = ctypes.c_double()
+    pairs = ctypes.c_uint64()
+    check(lib().pgsgd_path_stress_exact(g.handle, ctypes.c_void_p(coords.data_ptr()), ctypes.byref(mean),
+                                        ctypes.byref(pairs), _stream(torch, coords.device)))
+    return mean.value, int(pairs.value)
 
 
 def sample_terms(g: Graph, iter: int, t_begin: int, count: int, params: LayoutParams | None = None, **kw):

@@ -98,6 +98,7 @@ SIGNATURES = {
     "pgsgd_layout": ([_P, _P, _P, _P], _i32),
     "pgsgd_layout_timed": ([_P, _P, _P, _P, _P, _P, _P], _i32),
     "pgsgd_path_stress": ([_P, _P, _u32, _u64, _u32, _P, _P], _i32),
+    "pgsgd_path_stress_exact": ([_P, _P, _P, _P, _P], _i32),
     "pgsgd_stress_forward": ([_P, _P, _P, _u64, _u32, _P, _P, _P], _i32),
     "pgsgd_stress_backward": ([_P, _P, _P, _u64, _u32, _P, _P, _P, _P], _i32),
     "pgsgd_adam_step": ([_P, _P, _P, _P, _u64, _f32, _f32, _f32, _f32, _u32, _P], _i32),

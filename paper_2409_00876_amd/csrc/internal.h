@@ -152,6 +152,7 @@ hipError_t launch_sps_pass(const StressLaunch& P, int pass, const double* mean_d
 hipError_t launch_reduce_parts(const double* part_f, const uint64_t* part_n, const uint64_t* part_skip,
                                uint32_t n_parts, double* out_f, uint64_t* out_n, double* mean_out,
                                float* loss_out, uint64_t* n_valid_out, hipStream_t s);
+hipError_t launch_path_stress_exact(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,
                              hipStream_t s);

@@ -112,6 +112,59 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, const dou
   }
 }
 
+// ---------------------------------------------------------------------------
+// Path stress, Eq. 1: for every path and every step pair i < j of it, the mean
+// of the stress over the endpoint combinations with d > 0; averaged over all
+// pairs.  Thread-strided over rows i; a row visits j = i+1 .. end of the path.
+// O(sum |p|^2) work: for small graphs and for validating the sampled metric.
+// part_f: per-block sum of the pair means; part_n: per-block pair count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_path_stress_exact(StressLaunch P, double* __restrict__ part_f,
+                                                           uint64_t* __restrict__ part_n) {
+  extern __shared__ __align__(16) char lds[];
+  uint64_t* off = reinterpret_cast<uint64_t*>(lds);
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  fill_offsets(off, P);
+  __syncthreads();
+  const float* __restrict__ X = P.coords;
+  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
+  double acc = 0.0;
+  uint64_t np = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.S; i += stride) {
+    const uint32_t p = find_path(off, P.path_top, i);
+    const uint64_t end = off[p + 1];
+    const StepRec si = load_rec(P.rec, i);
+    for (uint64_t j = i + 1; j < end; ++j) {
+      const StepRec sj = load_rec(P.rec, j);
+      double sum = 0.0;
+      uint32_t nv = 0;
+      for (uint32_t e = 0; e < 4; ++e) {
+        const uint32_t ei = e & 1u, ej = e >> 1;
+        const int64_t dd = endpoint_pos(si, ei) - endpoint_pos(sj, ej);
+        if (dd == 0) continue;
+        const uint64_t a = 2ull * (si.node_rev & kNodeMask) + ei;
+        const uint64_t b = 2ull * (sj.node_rev & kNodeMask) + ej;
+        double dx, dy, mag;
+        sum += stress_fp64(X, Y, a, b, (double)(dd < 0 ? -dd : dd), dx, dy, mag);
+        ++nv;
+      }
+      if (nv) {
+#pragma clang fp contract(off)
+        acc += sum / (double)nv;
+        ++np;
+      }
+    }
+  }
+  acc = block_sum(acc, red_f);
+  np = block_sum(np, red_n);
+  if (threadIdx.x == 0) {
+    part_f[blockIdx.x] = acc;
+    part_n[blockIdx.x] = np;
+  }
+}
+
 // One block sums the partials in a fixed order.
 __global__ __launch_bounds__(1024) void k_reduce_parts(const double* __restrict__ part_f,
                                                        const uint64_t* __restrict__ part_n,
@@ -307,6 +360,12 @@ hipError_t launch_sps_pass(const StressLaunch& P, int pass, const double* mean_d
                            uint64_t* part_n, uint64_t* part_skip, hipStream_t s) {
   hipLaunchKernelGGL(k_sps, dim3(kStressBlocks), dim3(kStressThreads), (size_t)P.path_slots * 8, s, P, pass,
                      mean_dev, part_f, part_n, part_skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_path_stress_exact(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s) {
+  hipLaunchKernelGGL(k_path_stress_exact, dim3(kStressBlocks), dim3(kStressThreads), (size_t)P.path_slots * 8, s, P,
+                     part_f, part_n);
   return hipGetLastError();
 }
 

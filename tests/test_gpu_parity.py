@@ -256,6 +256,43 @@ def test_sps_equals_oracle_on_same_layout(P, which, m, request):
 
 
 # ---------------------------------------------------------------------------
+# Path stress (Eq. 1) and its relation to the sampled metric
+# ---------------------------------------------------------------------------
+def test_exact_path_stress_equals_oracle(P, tiny):
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    c1 = c0.copy()
+    O.layout(og, c1)
+    for c in (c0, c1):
+        ps, pairs = P.path_stress_exact(g, torch.from_numpy(c).cuda())
+        ref, ref_pairs = O.path_stress_exact(og, c)
+        assert pairs == ref_pairs
+        assert abs(ps - ref) <= 1e-9 * abs(ref)
+
+
+def test_exact_path_stress_edge_graph(P):
+    import torch
+    sg = _edge_synth()
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    c = (O.init_coords(og) + np.random.default_rng(2).normal(scale=3, size=4 * og.n_nodes)).astype(np.float32)
+    ps, pairs = P.path_stress_exact(g, torch.from_numpy(c).cuda())
+    ref, ref_pairs = O.path_stress_exact(og, c)
+    assert pairs == ref_pairs and abs(ps - ref) <= 1e-9 * abs(ref)
+
+
+def test_sampled_path_stress_tracks_exact_path_stress(P):
+    import math
+    import bench
+    rows = bench.sps_vs_ps_layouts(n_graphs=6, stages=(0, 2, 7, 30))
+    xs = [math.log(r["sps"]) for r in rows]
+    ys = [math.log(r["ps"]) for r in rows]
+    r = np.corrcoef(xs, ys)[0, 1]
+    print(f"log-space correlation of SPS and PS over {len(rows)} layouts: {r:.4f}")
+    assert r > 0.95
+
+
+# ---------------------------------------------------------------------------
 # T7 + T10: full layouts
 # ---------------------------------------------------------------------------
 def test_linear_path_converges_on_gpu(P):
