@@ -38,7 +38,8 @@ PROFILE_COMMANDS = """rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof
 rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o fetch -- python3 bench.py --profile
 rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o write -- python3 bench.py --profile
 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d gpurun_out/prof_tcc -o tcc -- python3 bench.py --profile
-python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv"""
+rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d gpurun_out/prof_rdreq -o rdreq -- python3 bench.py --profile
+python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv gpurun_out/prof_rdreq/rdreq_counter_collection.csv"""
 KERNEL_SOURCES = ["paper_2409_00876_amd/csrc/layout_kernels.hip", "paper_2409_00876_amd/csrc/binned_kernels.hip",
                   "paper_2409_00876_amd/csrc/device.h", "paper_2409_00876_amd/csrc/internal.h"]
 
@@ -73,7 +74,8 @@ def _read_counters(path):
     return rows
 
 
-def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: str, command: str) -> None:
+def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: str, command: str,
+                       rdreq_csv: str = None) -> None:
     """Turns the rocprofv3 outputs of one --profile sequence into the committed
     summaries: profiles/layout_iter_chromosome_counters.json (read by this
     benchmark) and profiles/layout_iter_chromosome_counters.md."""
@@ -126,6 +128,20 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
            "iteration_traffic_bytes": it_traffic, "iteration_traffic_bytes_per_term": it_traffic / T,
            "l2_hit_rate": sum(hits) / (sum(hits) + sum(miss)),
            "l2_misses_per_term": sum(miss) / len(miss) / (T / launches)}
+    if rdreq_csv and os.path.exists(rdreq_csv):
+        rq = _read_counters(rdreq_csv)
+        by = {}
+        for name in ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum"):
+            vals = [v for k, c, v in rq if c == name and k.startswith(dom)]
+            cp = [v for k, c, v in rq if c == name and "copyBuffer" in k]
+            by[name] = (sum(vals) / max(1, len(vals)), max(cp) if cp else 0.0)
+        rd_bytes = 32 * by["TCC_EA0_RDREQ_32B_sum"][0] + 64 * by["TCC_EA0_RDREQ_64B_sum"][0] + \
+            128 * by["TCC_EA0_RDREQ_128B_sum"][0]
+        copy_rd = 32 * by["TCC_EA0_RDREQ_32B_sum"][1] + 64 * by["TCC_EA0_RDREQ_64B_sum"][1] + \
+            128 * by["TCC_EA0_RDREQ_128B_sum"][1]
+        rec["read_requests_per_launch"] = {k: v[0] for k, v in by.items()}
+        rec["read_bytes_from_request_sizes"] = rd_bytes
+        rec["copy_read_bytes_from_request_sizes"] = copy_rd
     out = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
@@ -146,6 +162,16 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
                 f"({rec['traffic_gbs_at_trace_duration'] / HBM_PEAK_GBS:.1%} of 8 TB/s) |\n")
         f.write(f"| L2 (TCC) hit rate | {rec['l2_hit_rate']:.1%} |\n")
         f.write(f"| L2 misses per term | {rec['l2_misses_per_term']:.2f} |\n")
+        if "read_bytes_from_request_sizes" in rec:
+            rq = rec["read_requests_per_launch"]
+            f.write(f"| read requests per launch: 32 B / 64 B / 128 B | {rq['TCC_EA0_RDREQ_32B_sum']:.3g} / "
+                    f"{rq['TCC_EA0_RDREQ_64B_sum']:.3g} / {rq['TCC_EA0_RDREQ_128B_sum']:.3g} |\n")
+            f.write(f"| read bytes from request sizes (cross-check of the calibrated FETCH_SIZE) | "
+                    f"{rec['read_bytes_from_request_sizes'] / 1e9:.1f} GB (1 GiB copy: "
+                    f"{rec['copy_read_bytes_from_request_sizes'] / 2**30:.3f} GiB) |\n")
+        f.write("\nFETCH_SIZE is computed from the TCC request counters assuming 64-byte requests unless "
+                "TCC_BUBBLE counts 128-byte ones; on gfx950 TCC_BUBBLE reads 0 while these kernels issue 128-byte "
+                "read requests, hence the copy calibration factor of 2.\n")
         f.write(f"\nkernel source sha256[:16]: `{rec['kernel_source_sha']}`\n")
     print(json.dumps(rec, indent=1))
 
@@ -331,6 +357,40 @@ def form_metric() -> dict:
             "tiny_seconds": {"sps_m100": t_sps, "ps_exact": t_ps}}
 
 
+def form_reuse(workload: str = "chromosome", schemes=((1, 1), (2, 1), (2, 2), (4, 2), (4, 4))) -> dict:
+    """Data-reuse variant: run time, updates/s and sampled path stress of full
+    layouts for several (DRF, SRF) schemes, against the plain loop (1, 1)."""
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    sg = synth.config_graph(workload)
+    g = P.Graph.from_synth(sg)
+    c = g.new_coords()
+    T = 10 * g.n_steps
+    rows = []
+    base = None
+    for drf, srf in schemes:
+        P.init_coords(g, c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it_ms, mk_ms, _ = P.layout_timed(g, c, reuse_factor=drf, step_reduction=srf)
+        wall = time.perf_counter() - t0
+        sps = P.path_stress(g, c, 10, 7)
+        sampled = 30 * ((T + srf - 1) // srf)
+        row = {"drf": drf, "srf": srf, "seconds": wall, "sampled_terms": sampled,
+               "updates_upper_bound": sampled * drf, "sampled_terms_per_s": sampled / wall,
+               "sps": sps["mean"], "sps_ci": [sps["ci_lo"], sps["ci_hi"]], "avg_iteration_ms": float(sum(it_ms) / 30)}
+        if base is None:
+            base = row
+        row["speedup_vs_plain"] = base["seconds"] / wall
+        row["sps_ratio_vs_plain"] = sps["mean"] / base["sps"]
+        row["quality"] = "good" if row["sps_ratio_vs_plain"] < 2 else (
+            "satisfying" if row["sps_ratio_vs_plain"] < 10 else "poor")
+        rows.append(row)
+        print(f"[reuse] {drf},{srf}: {wall:.2f} s, SPS {sps['mean']:.4g}", file=sys.stderr, flush=True)
+    return {"workload": workload, "schemes": rows}
+
+
 def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:
     import oracle as O
     og = O.Graph.from_synth(sg)
@@ -358,14 +418,16 @@ def main():
     ap.add_argument("--workload", default="chromosome", choices=["tiny", "mid", "chromosome"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
-    ap.add_argument("--form", choices=["batched", "autograd", "metric"], default=None,
+    ap.add_argument("--form", choices=["batched", "autograd", "metric", "reuse"], default=None,
                     help="measure one of the two forms against the plain loop instead (separate JSON line)")
     ap.add_argument("--batched-scale", type=float, default=1.0)
-    ap.add_argument("--summarize", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "TCC_CSV"),
-                    help="write the committed counter summaries from rocprofv3 outputs (no GPU)")
+    ap.add_argument("--summarize", nargs="+", metavar="PATH",
+                    help="TRACE_DIR FETCH_CSV WRITE_CSV TCC_CSV [RDREQ_CSV]: write the committed counter summaries "
+                         "from rocprofv3 outputs (no GPU)")
     a = ap.parse_args()
     if a.summarize:
-        summarize_counters(*a.summarize, command=PROFILE_COMMANDS)
+        summarize_counters(*a.summarize[:4], command=PROFILE_COMMANDS,
+                           rdreq_csv=a.summarize[4] if len(a.summarize) > 4 else None)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU (the layout of one graph is not "
@@ -380,6 +442,9 @@ def main():
         return
     if a.form == "metric":
         print(json.dumps({"form": "metric", **form_metric()}))
+        return
+    if a.form == "reuse":
+        print(json.dumps({"form": "reuse", **form_reuse()}))
         return
 
     import torch

@@ -122,8 +122,25 @@ typedef struct {
   uint32_t max_inflight_waves;/* plain schedule: cap on concurrently running 64-term groups; 0 = automatic */
   uint32_t flags;             /* reserved, must be 0 */
   uint32_t schedule;          /* processing order of an iteration's terms: PGSGD_SCHEDULE_* */
-  uint32_t reserved;          /* must be 0 */
+  uint16_t reuse_factor;      /* data reuse: updates per sampled term (DRF), 0 or 1 = off, at most 16 */
+  uint16_t step_reduction;    /* data reuse: sampled terms per iteration divided by this (SRF), 0 or 1 = off */
 } pgsgd_params;
+
+/* Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
+ * Trade-off with Sampled Path Stress"), active when reuse_factor > 1 or
+ * step_reduction > 1 (plain schedule only):
+ *   - an iteration samples ceil(terms_per_step * S / step_reduction) terms in
+ *     aligned groups of 64; a group's path is the path of the global step
+ *     drawn by its first term (paths stay chosen with probability ∝ |p|), and
+ *     each term draws its own step uniformly in that path (partner, coins,
+ *     cooling and skips as in pgsgd_layout);
+ *   - after the group's primary updates, reuse_factor - 1 rounds pair the
+ *     i-endpoint of lane l with the j-endpoint of lane (l + o_k) mod 64,
+ *     o_k = 1 + (byte k-1 of Philox stream 4 at counter (group, 0, iter)) mod
+ *     63, using the values already loaded (cross-lane shuffles, no new loads);
+ *     d_ref is the path distance of the two endpoints; same-slot or d = 0
+ *     pairs are skipped.  Each endpoint is stored once at the end.
+ * Updates per iteration: up to reuse_factor x the sampled terms. */
 
 /* Processing order of the terms of an iteration.  The sampled terms are the
  * same in every schedule; only the order (and so the Hogwild interleaving)
@@ -342,11 +359,24 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph *const *graphs, uint32_t n, co
  * PGSGD_SCHEDULE_BINNED, in which case the binning kernels and the binned
  * layout kernel process the whole iteration (without updating coordinates)
  * and record the terms of the range, which must lie in [0, terms_per_step * S).
- * Async.
+ * With the data-reuse variant active it records that variant's terms
+ * (see pgsgd_sample_terms_reuse).  Async.
  */
 pgsgd_status pgsgd_sample_terms(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,
                                 uint64_t count, uint64_t *i_out, uint64_t *j_out, uint8_t *flags_out,
                                 void *stream);
+/*
+ * The data-reuse variant's terms and reuse offsets, recorded by its layout
+ * kernel with the layout's launch shape: terms t in [t_begin, t_begin + count)
+ * as in pgsgd_sample_terms (t_begin a multiple of 64), and, when offsets_out
+ * (device, may be NULL) is given, the offsets o_1..o_{reuse_factor-1} of every
+ * 64-term group of the range (reuse_factor - 1 bytes per group, in group
+ * order).  Async.
+ */
+pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,
+                                      uint64_t count, uint64_t *i_out, uint64_t *j_out, uint8_t *flags_out,
+                                      uint8_t *offsets_out, void *stream);
+
 /*
  * Applies count given terms (device arrays as written by pgsgd_sample_terms)
  * with learning rate eta, one thread per term, with the update of

@@ -58,6 +58,9 @@ def _load():
         "or_layout": ([P, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_layout_threaded": ([P, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P, u32, u64], u64),
         "or_apply_terms_f64": ([P, f64, P, P, P, u64, P], u64),
+        "or_sample_terms_reuse": ([P, u32, f64, u32, u64, u32, u32, u64, u64, P, P, P], None),
+        "or_reuse_offsets": ([u64, u32, u32, u64, u32, P], None),
+        "or_layout_reuse": ([P, u32, u32, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_apply_terms_f32": ([P, f64, P, P, P, u64, P], u64),
         "or_sampled_path_stress": ([P, P, u32, u64, u32, P, P], None),
         "or_sps_expectation": ([P, P, P], None),
@@ -176,6 +179,32 @@ def layout(g: Graph, coords: np.ndarray, n_iters=30, terms_per_step=10, eta_max=
     return int(L.or_layout_threaded(g._h, int(n_iters), int(terms_per_step), float(eta_max), float(eta_min),
                                     float(theta), int(window), int(seed), int(graph_id), int(first_iter),
                                     int(last_iter), _p(coords), int(threads), int(term_limit)))
+
+
+def sample_terms_reuse(g: Graph, iter: int, t_begin: int, count: int, n_iters=30, theta=0.99, window=1000,
+                       seed=24301, graph_id=0):
+    """Terms of the data-reuse variant: group-shared paths (see oracle.c)."""
+    i = np.zeros(count, dtype=np.uint64)
+    j = np.zeros(count, dtype=np.uint64)
+    f = np.zeros(count, dtype=np.uint8)
+    _load().or_sample_terms_reuse(g._h, int(n_iters), float(theta), int(window), int(seed), int(graph_id),
+                                  int(iter), int(t_begin), int(count), _p(i), _p(j), _p(f))
+    return i, j, f
+
+
+def reuse_offsets(iter: int, group: int, drf: int, seed=24301, graph_id=0) -> list:
+    o = np.zeros(17, dtype=np.uint32)
+    _load().or_reuse_offsets(int(seed), int(graph_id), int(iter), int(group), int(drf), _p(o))
+    return [int(x) for x in o[1:drf]]
+
+
+def layout_reuse(g: Graph, coords: np.ndarray, drf: int, srf: int, n_iters=30, terms_per_step=10, eta_max=0.0,
+                 eta_min=0.01, theta=0.99, window=1000, seed=24301, graph_id=0, first_iter=0, last_iter=0) -> int:
+    """The data-reuse variant of the layout loop, sequentially (see oracle.c)."""
+    assert coords.dtype == np.float32 and coords.flags.c_contiguous and coords.size == 4 * g.n_nodes
+    return int(_load().or_layout_reuse(g._h, int(n_iters), int(terms_per_step), int(drf), int(srf), float(eta_max),
+                                       float(eta_min), float(theta), int(window), int(seed), int(graph_id),
+                                       int(first_iter), int(last_iter), _p(coords)))
 
 
 def apply_terms_f64(g: Graph, eta: float, i, j, flags, coords64: np.ndarray) -> int:

@@ -452,6 +452,129 @@ uint64_t or_apply_terms_f32(const or_graph *g, double eta, const uint64_t *i, co
 }
 
 /* ---------------------------------------------------------------------------
+ * Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
+ * Trade-off with Sampled Path Stress"): each sampled step yields DRF updates
+ * and the number of sampled steps per iteration is divided by SRF.  Reading
+ * R10 (the paper gives no formula):
+ *   - an iteration has ceil(terms_per_step * S / SRF) sampled terms, in aligned
+ *     groups of 64; the group's path is the path of the global step drawn by
+ *     its first term (so paths are still chosen with probability ∝ |p|), and
+ *     every term t of the group draws its own step uniformly in that path:
+ *     i = start + floor(u64(t) * |p| / 2^64); its partner, endpoint coins,
+ *     cooling and skips are those of the plain definition;
+ *   - after the group's primary updates (terms in order), reuse rounds
+ *     k = 1..DRF-1 pair, for every lane l in order, the i-endpoint of lane l
+ *     with the j-endpoint of lane (l + o_k) mod 64, o_k = 1 + (byte k-1 of the
+ *     words of Philox stream 4 at counter (group, 0, iter)) mod 63, when both
+ *     terms exist and are not skipped; d_ref is the path distance of those two
+ *     endpoints; pairs with the same slot or d = 0 are skipped.
+ * With DRF = 1 and SRF = 1 the loop is or_layout's with group-shared paths.
+ * ------------------------------------------------------------------------- */
+enum { STREAM_REUSE = 4 };
+
+static void sample_group_term(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t t, uint32_t p,
+                              uint32_t group_coin, uint64_t *i_out, uint64_t *j_out, uint32_t *flags) {
+  uint32_t r[4];
+  draw(sp->seed, t, iter, STREAM_LAYOUT, sp->graph_id, r);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+  uint64_t i = start + mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), len);
+  uint32_t cooling = (iter >= sp->n_iters / 2) || group_coin;
+  uint32_t e_i = r[3] & 1u, e_j = (r[3] >> 1) & 1u;
+  uint64_t j;
+  int skip = 0;
+  if (cooling) partner_power_law(g, sp, i, start, len, r[2], r[3], &j, &skip);
+  else j = start + mulhi32(r[2], (uint32_t)len);
+  if (!skip) {
+    uint64_t a = 2ull * step_node_id(g, i) + e_i, b = 2ull * step_node_id(g, j) + e_j;
+    int64_t d = or_endpoint_pos(g, i, e_i) - or_endpoint_pos(g, j, e_j);
+    if (a == b || d == 0) skip = 1;
+  }
+  *i_out = i; *j_out = j;
+  *flags = e_i | (e_j << 1) | (cooling << 2) | ((uint32_t)skip << 3);
+}
+
+/* The group's path and the reuse offsets o_1..o_{DRF-1}. */
+static uint32_t group_path(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t t0, uint32_t *coin) {
+  uint32_t r[4];
+  draw(sp->seed, t0, iter, STREAM_LAYOUT, sp->graph_id, r);
+  *coin = (r[3] >> 3) & 1u;
+  return path_of_step(g, mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), g->S));
+}
+
+static void reuse_offsets(const sampler *sp, uint32_t iter, uint64_t group, uint32_t drf, uint32_t *o) {
+  uint32_t r[4];
+  draw(sp->seed, group, iter, STREAM_REUSE, sp->graph_id, r);
+  for (uint32_t k = 1; k < drf; ++k) {
+    uint32_t byte = (r[(k - 1) / 4] >> (8 * ((k - 1) % 4))) & 0xFFu;
+    o[k] = 1 + byte % 63;
+  }
+}
+
+void or_sample_terms_reuse(const or_graph *g, uint32_t n_iters, double theta, uint32_t W, uint64_t seed,
+                           uint32_t graph_id, uint32_t iter, uint64_t t_begin, uint64_t count, uint64_t *i_out,
+                           uint64_t *j_out, uint8_t *flags_out) {
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  for (uint64_t k = 0; k < count; ++k) {
+    uint64_t t = t_begin + k;
+    uint32_t coin, fl;
+    uint32_t p = group_path(g, &sp, iter, t - (t % 64), &coin);
+    sample_group_term(g, &sp, iter, t, p, coin, &i_out[k], &j_out[k], &fl);
+    flags_out[k] = (uint8_t)fl;
+  }
+  free((void *)sp.zipf);
+}
+
+void or_reuse_offsets(uint64_t seed, uint32_t graph_id, uint32_t iter, uint64_t group, uint32_t drf, uint32_t *o) {
+  sampler sp;
+  sp.seed = seed; sp.graph_id = graph_id;
+  reuse_offsets(&sp, iter, group, drf, o);
+}
+
+uint64_t or_layout_reuse(const or_graph *g, uint32_t n_iters, uint32_t terms_per_step, uint32_t drf, uint32_t srf,
+                         double eta_max, double eta_min, double theta, uint32_t W, uint64_t seed, uint32_t graph_id,
+                         uint32_t first, uint32_t last, float *coords) {
+  if (g->S == 0 || n_iters == 0 || drf < 1 || drf > 16 || srf < 1) return 0;
+  if (eta_max <= 0.0) eta_max = (double)g->d_max * (double)g->d_max;
+  double *eta = (double *)malloc(sizeof(double) * n_iters);
+  or_schedule(n_iters, eta_max, eta_min, eta);
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  uint64_t T = ((uint64_t)terms_per_step * g->S + srf - 1) / srf, applied = 0;
+  if (last == 0 || last > n_iters) last = n_iters;
+  uint64_t ti[64], tj[64];
+  uint32_t tf[64], o[17];
+  for (uint32_t it = first; it < last; ++it) {
+    for (uint64_t t0 = 0; t0 < T; t0 += 64) {
+      uint32_t n = (uint32_t)(T - t0 < 64 ? T - t0 : 64), coin;
+      uint32_t p = group_path(g, &sp, it, t0, &coin);
+      for (uint32_t l = 0; l < n; ++l) {
+        sample_group_term(g, &sp, it, t0 + l, p, coin, &ti[l], &tj[l], &tf[l]);
+        if (tf[l] & 8u) continue;
+        uint64_t a = 2ull * step_node_id(g, ti[l]) + (tf[l] & 1u), b = 2ull * step_node_id(g, tj[l]) + ((tf[l] >> 1) & 1u);
+        applied += update_f32(X, Y, a, b, term_distance(g, ti[l], tj[l], tf[l]), eta[it]);
+      }
+      reuse_offsets(&sp, it, t0 / 64, drf, o);
+      for (uint32_t k = 1; k < drf; ++k) {
+        for (uint32_t l = 0; l < n; ++l) {
+          uint32_t m = (l + o[k]) % 64;
+          if (m >= n || (tf[l] & 8u) || (tf[m] & 8u)) continue;
+          uint32_t ei = tf[l] & 1u, ej = (tf[m] >> 1) & 1u;
+          uint64_t a = 2ull * step_node_id(g, ti[l]) + ei, b = 2ull * step_node_id(g, tj[m]) + ej;
+          int64_t d = or_endpoint_pos(g, ti[l], ei) - or_endpoint_pos(g, tj[m], ej);
+          if (a == b || d == 0) continue;
+          applied += update_f32(X, Y, a, b, d < 0 ? -d : d, eta[it]);
+        }
+      }
+    }
+  }
+  free((void *)sp.zipf);
+  free(eta);
+  return applied;
+}
+
+/* ---------------------------------------------------------------------------
  * Sampled path stress, Eq. 2, with the two-pass CI95 (reading R9).  Pair q of
  * path p, q in [m*off[p], m*off[p+1]), draws Philox stream 1 at counter q:
  * i = start + floor(u64 * |p| / 2^64), j = start + floor(r2 * |p| / 2^32),

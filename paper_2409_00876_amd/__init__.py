@@ -22,7 +22,7 @@ import torch
 from ._lib import (GraphInfo, Params, PgsgdError, StressResult, Tune, check, lib)  # noqa: F401
 
 __all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
-           "sample_terms", "apply_terms", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
+           "sample_terms", "sample_terms_reuse", "apply_terms", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
 
@@ -64,7 +64,8 @@ class LayoutParams:
     max_inflight_waves: int = 0
     flags: int = 0
     schedule: int = 0           # 0 auto, 1 plain, 2 binned
-    reserved: int = 0
+    reuse_factor: int = 1       # data-reuse variant: updates per sampled term (DRF)
+    step_reduction: int = 1     # data-reuse variant: sampled terms divided by SRF
 
     def to_c(self) -> Params:
         p = Params()
@@ -207,6 +208,23 @@ def sample_terms(g: Graph, iter: int, t_begin: int, count: int, params: LayoutPa
                                    ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
                                    ctypes.c_void_p(f.data_ptr()), _stream(torch, dev)))
     return i, j, f
+
+
+def sample_terms_reuse(g: Graph, iter: int, t_begin: int, count: int, params: LayoutParams | None = None, **kw):
+    """The data-reuse variant's terms (i, j, flags) and reuse offsets (uint8,
+    reuse_factor - 1 per 64-term group), recorded by its kernel."""
+    p = _params(params, kw)
+    dev = f"cuda:{g.device}"
+    i = torch.empty(count, dtype=torch.int64, device=dev)
+    j = torch.empty(count, dtype=torch.int64, device=dev)
+    f = torch.full((count,), 255, dtype=torch.uint8, device=dev)
+    n_groups = (t_begin + count + 63) // 64 - t_begin // 64
+    o = torch.zeros(max(1, n_groups * max(0, p.reuse_factor - 1)), dtype=torch.uint8, device=dev)
+    check(lib().pgsgd_sample_terms_reuse(g.handle, ctypes.byref(p), int(iter), int(t_begin), int(count),
+                                         ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
+                                         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(o.data_ptr()),
+                                         _stream(torch, dev)))
+    return i, j, f, o
 
 
 def apply_terms(g: Graph, coords, eta: float, i, j, f):

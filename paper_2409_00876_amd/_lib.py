@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
         ("max_inflight_waves", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
         ("schedule", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("reuse_factor", ctypes.c_uint16),
+        ("step_reduction", ctypes.c_uint16),
     ]
 
 
@@ -109,6 +110,7 @@ SIGNATURES = {
     "pgsgd_autotune_batched": ([_P, _u32, _P, _P, _P, _P, _P], _i32),
     "pgsgd_batch_sample_terms": ([_P, _u32, _P, _u32, _P, _P, _P, _P, _P], _i32),
     "pgsgd_sample_terms": ([_P, _P, _u32, _u64, _u64, _P, _P, _P, _P], _i32),
+    "pgsgd_sample_terms_reuse": ([_P, _P, _u32, _u64, _u64, _P, _P, _P, _P, _P], _i32),
     "pgsgd_apply_terms": ([_P, _f32, _P, _P, _P, _u64, _P, _P], _i32),
 }
 

@@ -197,7 +197,10 @@ pgsgd_status ensure_zipf(pgsgd_graph* g, double theta, uint32_t W, hipStream_t s
 
 pgsgd_status check_params(const pgsgd_params* p) {
   if (!p) return fail(PGSGD_ERR_INVALID_ARG, "params is NULL");
-  if (p->flags != 0 || p->reserved != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags and reserved must be 0");
+  if (p->flags != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags must be 0");
+  if (p->reuse_factor > 16) return fail(PGSGD_ERR_INVALID_ARG, "reuse_factor must be at most 16");
+  if ((p->reuse_factor > 1 || p->step_reduction > 1) && p->schedule == PGSGD_SCHEDULE_BINNED)
+    return fail(PGSGD_ERR_INVALID_ARG, "the data-reuse variant runs with the plain schedule only");
   if (p->schedule > PGSGD_SCHEDULE_BINNED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
   if (p->zipf_window < 1 || p->zipf_window > 65535)
     return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", p->zipf_window);
@@ -229,8 +232,10 @@ LayoutLaunch make_layout_launch(const pgsgd_graph* g, const pgsgd_params* p) {
   L.guide = g->d_guide;
   L.n_nodes = g->n_nodes;
   L.S = g->S;
-  L.n_terms = (uint64_t)p->terms_per_step * g->S;
+  const uint64_t srf = p->step_reduction > 1 ? p->step_reduction : 1;
+  L.n_terms = ((uint64_t)p->terms_per_step * g->S + srf - 1) / srf;
   L.n_groups = (L.n_terms + 63) / 64;
+  L.drf = p->reuse_factor > 1 ? p->reuse_factor : 1;
   L.n_paths = g->n_paths;
   L.path_slots = g->path_slots;
   L.path_top = g->path_top;
@@ -293,7 +298,8 @@ void pgsgd_params_default(pgsgd_params* p) {
   p->max_inflight_waves = 0;
   p->flags = 0;
   p->schedule = PGSGD_SCHEDULE_AUTO;
-  p->reserved = 0;
+  p->reuse_factor = 1;
+  p->step_reduction = 1;
 }
 
 pgsgd_status pgsgd_schedule(const pgsgd_params* p, int64_t d_max, float* eta_out) {
@@ -627,6 +633,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   L.t_end = L.n_terms;
   L.g_begin = 0;
   L.g_end = L.n_groups;
+  const bool reuse = p->reuse_factor > 1 || p->step_reduction > 1;
   const bool binned = tracing || use_binned(g, p);
   uint32_t blocks = 0, threads = 256;
   BinLaunch B{};
@@ -689,7 +696,8 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
       }
     } else {
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1], s));
-      HIP_TRY(launch_layout_iter(L, blocks, threads, s));
+      if (reuse) HIP_TRY(launch_layout_reuse(L, blocks, threads, s));
+      else HIP_TRY(launch_layout_iter(L, blocks, threads, s));
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
     }
     if (tracing) break;
@@ -713,9 +721,49 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   return ok();
 }
 
+// The data-reuse kernel in recording mode over the terms of [t_begin, t_begin
+// + count) (t_begin a multiple of 64), with the layout's launch shape.
+hipError_t sample_reuse(pgsgd_graph* g, const pgsgd_params* p, hipStream_t s, size_t lds, uint32_t iter,
+                        uint64_t t_begin, uint64_t count, uint64_t* i_out, uint64_t* j_out, uint8_t* f_out,
+                        uint8_t* o_out) {
+  LayoutLaunch L = make_layout_launch(g, p);
+  uint32_t blocks, threads;
+  if (layout_grid(g, p, lds, L.n_groups, &blocks, &threads) != PGSGD_OK) return hipErrorUnknown;
+  L.wave_stride = (uint64_t)blocks * (threads / 64);
+  L.iter = iter;
+  L.cool_all = iter >= p->n_iters / 2 ? 1u : 0u;
+  L.t_begin = t_begin;
+  L.t_end = t_begin + count;
+  L.g_begin = t_begin >> 6;
+  L.g_end = (t_begin + count + 63) >> 6;
+  L.trace_i = i_out;
+  L.trace_j = j_out;
+  L.trace_f = f_out;
+  L.trace_o = o_out;
+  return launch_layout_reuse(L, blocks, threads, s);
+}
+
 }  // namespace
 
 extern "C" {
+
+pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph* g, const pgsgd_params* p, uint32_t iter, uint64_t t_begin,
+                                      uint64_t count, uint64_t* i_out, uint64_t* j_out, uint8_t* flags_out,
+                                      uint8_t* offsets_out, void* stream) {
+  if (!g || !i_out || !j_out || !flags_out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
+  if (t_begin % 64) return fail(PGSGD_ERR_INVALID_ARG, "t_begin must be a multiple of 64");
+  if (t_begin + count < t_begin || t_begin + count >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term range too large");
+  if (count == 0 || g->S == 0) return ok();
+  DeviceGuard guard(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  size_t lds;
+  if ((st = layout_prepare(g, p, s, &lds))) return st;
+  HIP_TRY(sample_reuse(g, p, s, lds, iter, t_begin, count, i_out, j_out, flags_out, offsets_out));
+  return ok();
+}
 
 pgsgd_status pgsgd_layout(pgsgd_graph* g, const pgsgd_params* p, float* coords, void* stream) {
   return layout_impl(g, p, coords, nullptr, nullptr, nullptr, stream);
@@ -750,6 +798,11 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t 
   hipStream_t s = (hipStream_t)stream;
   size_t lds;
   if ((st = layout_prepare(g, p, s, &lds))) return st;
+  if (p->reuse_factor > 1 || p->step_reduction > 1) {
+    hipError_t e = sample_reuse(g, p, s, lds, iter, t_begin, count, i_out, j_out, flags_out, nullptr);
+    HIP_TRY(e);
+    return ok();
+  }
   // the layout kernel itself, in recording mode, with the layout's launch shape
   LayoutLaunch L = make_layout_launch(g, p);
   uint32_t blocks, threads;

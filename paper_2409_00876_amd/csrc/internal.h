@@ -29,7 +29,7 @@ struct LayoutLaunch {
   uint32_t c3;             // stream << 24 | graph_id
   uint32_t k0, k1;         // Philox key
   float eta;
-  uint32_t pad_;
+  uint32_t drf;            // data reuse: updates per sampled term (1 = off)
   // term range [t_begin, t_end) of this launch, as 64-term groups [g_begin, g_end)
   uint64_t t_begin, t_end;
   uint64_t g_begin, g_end;
@@ -38,6 +38,7 @@ struct LayoutLaunch {
   uint64_t* trace_i;
   uint64_t* trace_j;
   uint8_t* trace_f;
+  uint8_t* trace_o;        // data reuse: offsets o_1..o_{drf-1} per group
 };
 
 // Binned processing of one iteration (binned_kernels.hip): terms are binned by
@@ -129,6 +130,7 @@ struct StressLaunch {
 size_t layout_lds_bytes(uint32_t path_slots, uint32_t W);
 size_t batch_lds_bytes(uint32_t n_graphs, uint32_t path_slots_total, uint32_t W);
 hipError_t launch_layout_iter(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
+hipError_t launch_layout_reuse(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const uint64_t* i, const uint64_t* j,
                               const uint8_t* f, uint64_t count, hipStream_t s);
 // boundary layout [2][n][2] <-> interleaved working copy [n][2](x, y)

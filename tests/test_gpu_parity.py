@@ -171,6 +171,55 @@ def test_binned_sampling_bitexact_chromosome(P, chromosome, it):
 
 
 # ---------------------------------------------------------------------------
+# Data-reuse variant (DRF, SRF)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("it", [0, 20])
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+def test_reuse_sampling_bitexact(P, which, it, request):
+    sg, og, g = request.getfixturevalue(which)
+    n = 1 << 16
+    i, j, f, o = P.sample_terms_reuse(g, it, 64 * 37, n, reuse_factor=4, step_reduction=2, graph_id=3)
+    oi, oj, of = O.sample_terms_reuse(og, it, 64 * 37, n, graph_id=3)
+    assert np.array_equal(_to_np_u64(i), oi) and np.array_equal(_to_np_u64(j), oj)
+    assert np.array_equal(f.cpu().numpy(), of)
+    go = o.cpu().numpy().reshape(-1, 3)
+    for k in range(0, go.shape[0], 97):
+        assert list(go[k]) == O.reuse_offsets(it, 37 + k, 4, graph_id=3)
+    # a group shares one path
+    path = np.searchsorted(og.path_off, oi, side="right") - 1
+    assert np.all(path.reshape(-1, 64) == path.reshape(-1, 64)[:, :1])
+
+
+def test_reuse_off_is_the_plain_layout(P, tiny):
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    a = torch.from_numpy(c0).cuda()
+    b = torch.from_numpy(c0).cuda()
+    P.layout(g, a, max_inflight_waves=1, first_iter=0, last_iter=3)
+    P.layout(g, b, max_inflight_waves=1, first_iter=0, last_iter=3, reuse_factor=1, step_reduction=1)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("drf,srf", [(2, 1), (2, 2), (4, 4)])
+def test_reuse_layout_quality_matches_oracle_variant(P, tiny, drf, srf):
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    gpu, ora = [], []
+    for sd in (101, 102, 103, 104):
+        c = torch.from_numpy(c0).cuda()
+        P.layout(g, c, seed=sd, max_inflight_waves=1, reuse_factor=drf, step_reduction=srf)
+        gpu.append(O.sps_expectation(og, c.cpu().numpy())[0])
+        co = c0.copy()
+        O.layout_reuse(og, co, drf, srf, seed=sd)
+        ora.append(O.sps_expectation(og, co)[0])
+    ratio = np.mean(gpu) / np.mean(ora)
+    print(f"reuse ({drf},{srf}): GPU {np.mean(gpu):.6f} oracle {np.mean(ora):.6f} ratio {ratio:.4f}")
+    assert abs(ratio - 1) <= 0.03
+
+
+# ---------------------------------------------------------------------------
 # T6b: one collision-free deterministic batch
 # ---------------------------------------------------------------------------
 def _collision_free(og, i, j, f, limit):
