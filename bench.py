@@ -322,7 +322,7 @@ def sps_vs_ps_layouts(n_graphs: int = 24, stages=(0, 1, 2, 4, 7, 11, 16, 30), m:
 def form_metric() -> dict:
     """Sampled path stress against exact path stress over graded layouts (the
     analogue of the paper's correlation study), plus the run time of both
-    metrics on the mid graph's final layout."""
+    metrics on the tiny graph's final layout."""
     import math
     import torch
     import synth

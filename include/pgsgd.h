@@ -302,19 +302,22 @@ typedef struct {
   uint32_t groups_per_item; /* consecutive 64-term groups a wave takes per work item, >= 1 */
   uint32_t blocks_per_cu;   /* persistent blocks per compute unit, >= 1 */
   uint32_t max_blocks;      /* cap on the grid (0 = none): bounds concurrent updates for small graphs */
+  uint32_t phases;          /* work-item order, 1..64: 1 = graph after graph (fastest on MI355X: the
+                               coordinates of the graph in progress stay in the Infinity Cache);
+                               R > 1 interleaves the graphs in R phases (updates spread over graphs) */
 } pgsgd_tune;
 
 typedef struct pgsgd_batch pgsgd_batch;
 
 /*
- * Prepares a batched layout of n graphs (all on the same device); work items
- * are interleaved over the graphs in 32 phases so that concurrent updates are
- * spread over all graphs in proportion to their size.  Graph k uses
+ * Prepares a batched layout of n graphs (all on the same device) in the work
+ * order of tune->phases.  Graph k uses
  * p->graph_id + k as its graph_id (so its terms equal those of a plain
  * pgsgd_layout with that graph_id) and its own schedule from its own d_max
  * when p->eta_max <= 0.  coords[k] is graph k's coordinate buffer (device).
  * The n_iters launches are captured once in a HIP graph.  tune = NULL picks
- * defaults.  The sampled terms do not depend on tune.  max_inflight_waves is
+ * defaults (256 threads, 1 group per item, 2 blocks per CU, 1 phase).  The
+ * sampled terms do not depend on tune.  max_inflight_waves is
  * ignored (the persistent grid sets the concurrency).
  */
 pgsgd_status pgsgd_batch_create(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,

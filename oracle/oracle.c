@@ -455,7 +455,7 @@ uint64_t or_apply_terms_f32(const or_graph *g, double eta, const uint64_t *i, co
  * Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
  * Trade-off with Sampled Path Stress"): each sampled step yields DRF updates
  * and the number of sampled steps per iteration is divided by SRF.  Reading
- * R10 (the paper gives no formula):
+ * R17 (the paper gives no formula):
  *   - an iteration has ceil(terms_per_step * S / SRF) sampled terms, in aligned
  *     groups of 64; the group's path is the path of the global step drawn by
  *     its first term (so paths are still chosen with probability ∝ |p|), and

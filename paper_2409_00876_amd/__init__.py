@@ -316,7 +316,7 @@ def _tune_c(tune) -> Tune | None:
     if isinstance(tune, Tune):
         return tune
     return Tune(int(tune["block_threads"]), int(tune["groups_per_item"]), int(tune["blocks_per_cu"]),
-                int(tune.get("max_blocks", 0)))
+                int(tune.get("max_blocks", 0)), int(tune.get("phases", 1)))
 
 
 def _graph_arrays(graphs, coords_list):
@@ -417,12 +417,13 @@ def autotune(graphs, coords_list, params: LayoutParams | None = None, use_cache:
         if sig in cache:
             return dict(cache[sig], cached=True)
     gh, ch = _graph_arrays(graphs, coords_list)
-    best = Tune(0, 0, 0, int(max_blocks))
+    best = Tune(0, 0, 0, int(max_blocks), 1)
     ms = ctypes.c_float()
     check(lib().pgsgd_autotune_batched(gh, len(graphs), ctypes.byref(p), ch, ctypes.byref(best), ctypes.byref(ms),
                                        _stream(torch, f"cuda:{graphs[0].device}")))
     res = {"block_threads": best.block_threads, "groups_per_item": best.groups_per_item,
-           "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks, "ms": ms.value}
+           "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks, "phases": best.phases,
+           "ms": ms.value}
     if use_cache:
         cache[sig] = res
         try:

@@ -79,6 +79,7 @@ class Tune(ctypes.Structure):
         ("groups_per_item", ctypes.c_uint32),
         ("blocks_per_cu", ctypes.c_uint32),
         ("max_blocks", ctypes.c_uint32),
+        ("phases", ctypes.c_uint32),
     ]
 
 

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/pgsgd.h"
+#include "batch.h"
 #include "device.h"
 #include "internal.h"
 
@@ -993,14 +994,18 @@ pgsgd_status check_tune(const pgsgd_tune* t) {
     return fail(PGSGD_ERR_INVALID_ARG, "tune.block_threads must be a multiple of 64 in [64, 1024]");
   if (t->groups_per_item < 1) return fail(PGSGD_ERR_INVALID_ARG, "tune.groups_per_item must be >= 1");
   if (t->blocks_per_cu < 1) return fail(PGSGD_ERR_INVALID_ARG, "tune.blocks_per_cu must be >= 1");
+  if (t->phases < 1 || t->phases > 64) return fail(PGSGD_ERR_INVALID_ARG, "tune.phases must be in [1, 64]");
   return PGSGD_OK;
 }
 
+// Measured on MI355X (24 chromosome-like graphs): 256 threads, one group per
+// item, 2 blocks per CU and graph-major order are the fastest.
 pgsgd_tune default_tune() {
   pgsgd_tune t{};
-  t.block_threads = 512;
-  t.groups_per_item = 4;
-  t.blocks_per_cu = 4;
+  t.block_threads = 256;
+  t.groups_per_item = 1;
+  t.blocks_per_cu = 2;
+  t.phases = 1;
   return t;
 }
 
@@ -1028,7 +1033,7 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
     if ((uint64_t)p->terms_per_step * graphs[k]->S >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term count >= 2^48");
     slots_total += graphs[k]->path_slots;
   }
-  const size_t lds = batch_lds_bytes(n, slots_total, p->zipf_window);
+  const size_t lds = batch_lds_bytes(n, t.phases, slots_total, p->zipf_window);
   if (lds > graphs[0]->lds_limit)
     return fail(PGSGD_ERR_UNSUPPORTED, "batched LDS image of %zu bytes exceeds the %zu-byte block limit", lds,
                 graphs[0]->lds_limit);
@@ -1040,7 +1045,7 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
   b->tune = t;
   b->params = *p;
   std::vector<BatchGraph> hdr(n);
-  std::vector<uint64_t> seg_off((size_t)kBatchPhases * n + 1, 0), blob;
+  std::vector<uint64_t> seg_off((size_t)t.phases * n + 1, 0), blob;
   std::vector<float> eta_all;
   blob.reserve(slots_total);
   for (uint32_t k = 0; k < n; ++k) {
@@ -1068,10 +1073,11 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
     eta_all.insert(eta_all.end(), eta.begin(), eta.end());
   }
   // segment (phase r, graph k) holds items [floor(r I_k / R), floor((r+1) I_k / R)) of graph k
-  for (uint32_t r = 0; r < kBatchPhases; ++r)
+  const uint32_t R = t.phases;
+  for (uint32_t r = 0; r < R; ++r)
     for (uint32_t k = 0; k < n; ++k) {
       const uint64_t I = hdr[k].n_items;
-      const uint64_t sz = ((r + 1) * I) / kBatchPhases - (r * I) / kBatchPhases;
+      const uint64_t sz = ((r + 1) * I) / R - (r * I) / R;
       const size_t sidx = (size_t)r * n + k;
       seg_off[sidx + 1] = seg_off[sidx] + sz;
     }
@@ -1122,6 +1128,7 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
   L.n_iters = p->n_iters;
   L.k0 = (uint32_t)p->seed;
   L.k1 = (uint32_t)(p->seed >> 32);
+  L.phases = t.phases;
   if (capture) {
     hipStream_t cs;
     if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) {
@@ -1235,18 +1242,20 @@ pgsgd_status pgsgd_autotune_batched(pgsgd_graph* const* graphs, uint32_t n, cons
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const uint32_t threads_c[] = {256, 512, 1024};
-  const uint32_t gpi_c[] = {1, 4, 16, 64};
-  const uint32_t bpc_c[] = {1, 2, 4, 8};
+  const uint32_t threads_c[] = {256, 512};
+  const uint32_t gpi_c[] = {1, 4, 16};
+  const uint32_t bpc_c[] = {1, 2, 4};
+  const uint32_t phase_c[] = {1, 4};
   float best_ms = 1e30f;
   pgsgd_tune best_t = default_tune();
   best_t.max_blocks = tune_cap;
   bool any = false;
+  for (uint32_t ph : phase_c)
   for (uint32_t th : threads_c)
     for (uint32_t gpi : gpi_c)
       for (uint32_t bpc : bpc_c) {
         if (bpc * th / 64 > 32) continue;  // more waves than a CU holds
-        pgsgd_tune t{th, gpi, bpc, tune_cap};
+        pgsgd_tune t{th, gpi, bpc, tune_cap, ph};
         pgsgd_batch* b = nullptr;
         if (batch_build(graphs, n, &pt, coords, &t, 16, false, &b) != PGSGD_OK) continue;
         BatchLaunch L = b->launch;

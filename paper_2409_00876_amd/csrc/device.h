@@ -167,4 +167,46 @@ __device__ __forceinline__ void apply_update(float2* __restrict__ W, uint64_t a,
   W[b] = make_float2(pb.x + r * dx, pb.y + r * dy);
 }
 
+// LDS image shared by the layout kernels: padded path offsets, then the
+// power-law table C[0..W], then its guide (kGuideSize+1 entries).
+struct LdsView {
+  uint64_t* off;
+  uint32_t* zipf;
+  uint16_t* guide;
+};
+
+__device__ __forceinline__ LdsView lds_view(char* base, uint32_t path_slots, uint32_t W) {
+  LdsView v;
+  v.off = reinterpret_cast<uint64_t*>(base);
+  v.zipf = reinterpret_cast<uint32_t*>(base + (size_t)path_slots * 8);
+  v.guide = reinterpret_cast<uint16_t*>(base + (size_t)path_slots * 8 + (size_t)(W + 1) * 4);
+  return v;
+}
+
+__device__ __forceinline__ void lds_fill(const LdsView& v, const uint64_t* __restrict__ path_off, uint32_t n_paths,
+                                         uint32_t path_slots, const uint32_t* __restrict__ zipf,
+                                         const uint16_t* __restrict__ guide, uint32_t W) {
+  for (uint32_t k = threadIdx.x; k < path_slots; k += blockDim.x) v.off[k] = k <= n_paths ? path_off[k] : ~0ull;
+  for (uint32_t k = threadIdx.x; k <= W; k += blockDim.x) v.zipf[k] = zipf[k];
+  for (uint32_t k = threadIdx.x; k <= kGuideSize; k += blockDim.x) v.guide[k] = guide[k];
+}
+
+// Sampling of one term from its draw (all integer): step i, partner j, flags.
+__device__ __forceinline__ Term sample_term(const Rand4& r, bool cooling, uint64_t S, const LdsView& L,
+                                            uint32_t path_top, uint32_t W) {
+  Term T;
+  T.i = mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), S);
+  const uint32_t p = find_path(L.off, path_top, T.i);
+  const uint64_t start = L.off[p];
+  const uint64_t len = L.off[p + 1] - start;
+  bool ok = true;
+  if (cooling) {
+    ok = partner_power_law(T.i, start, len, r.r2, r.r3, L.zipf, L.guide, W, T.j);
+  } else {
+    T.j = start + mulhi32(r.r2, (uint32_t)len);
+  }
+  T.flags = (r.r3 & 3u) | ((cooling ? 1u : 0u) << 2) | ((ok ? 0u : 1u) << 3);
+  return T;
+}
+
 }  // namespace pgsgd

@@ -63,50 +63,6 @@ struct BinLaunch {
   uint32_t* xitem;         // [kXcds][xstride] prefix of 64-term items over the windows of each XCD
 };
 
-// Per-graph header of the batched launch.
-struct BatchGraph {
-  const StepRec* rec;
-  float2* work;            // interleaved coordinates of this graph
-  uint64_t n_nodes;
-  uint64_t S;
-  uint64_t n_terms;
-  uint64_t n_groups_run;   // groups processed (all, except in tuning runs)
-  uint64_t n_items;        // ceil(n_groups_run / groups_per_item)
-  uint32_t path_base;      // index of this graph's offsets in the path blob
-  uint32_t path_top;
-  uint32_t c3;
-  float eta;               // filled per iteration from eta_all
-  // parity hook: when trace_f is set the terms are recorded (index t) instead
-  // of applied
-  uint64_t* trace_i;
-  uint64_t* trace_j;
-  uint8_t* trace_f;
-};
-
-// Work items of the batched launch are ordered in kBatchPhases phases: phase r
-// holds, graph after graph, the r-th 1/kBatchPhases share of every graph's
-// items, so the waves running at any moment spread over all graphs in
-// proportion to their size (few concurrent updates per node in every graph).
-constexpr uint32_t kBatchPhases = 32;
-
-struct BatchLaunch {
-  const BatchGraph* graphs;
-  const uint64_t* seg_off;     // kBatchPhases * n_graphs + 1 segment prefix (segment = phase * n + graph)
-  const uint64_t* path_blob;   // padded offsets of all graphs
-  const float* eta_all;        // [n_graphs][n_iters]
-  const uint32_t* zipf;
-  const uint16_t* guide;
-  uint64_t wave_stride;
-  uint64_t groups_per_item;
-  uint32_t n_graphs;
-  uint32_t path_slots_total;
-  uint32_t W;
-  uint32_t n_iters;
-  uint32_t iter;
-  uint32_t cool_all;
-  uint32_t k0, k1;
-};
-
 // Stress kernels (sampled path stress, differentiable loss).
 struct StressLaunch {
   const StepRec* rec;
@@ -128,7 +84,6 @@ struct StressLaunch {
 };
 
 size_t layout_lds_bytes(uint32_t path_slots, uint32_t W);
-size_t batch_lds_bytes(uint32_t n_graphs, uint32_t path_slots_total, uint32_t W);
 hipError_t launch_layout_iter(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 hipError_t launch_layout_reuse(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const uint64_t* i, const uint64_t* j,
@@ -136,12 +91,10 @@ hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const
 // boundary layout [2][n][2] <-> interleaved working copy [n][2](x, y)
 hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s);
 hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s);
-hipError_t launch_layout_batch(const BatchLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 const void* layout_iter_kernel();
 hipError_t launch_bin_count_scan_scatter(const BinLaunch& B, hipStream_t s);
 hipError_t launch_bin_layout(const BinLaunch& B, uint32_t blocks, hipStream_t s);
 const void* bin_layout_kernel();
-const void* layout_batch_kernel();
 
 // SPS: pass 1 writes per-block (sum, n_valid, n_skipped); pass 2 per-block sum
 // of squared deviations from mean_dev.  Final reductions write to out.

@@ -518,8 +518,10 @@ def small_batch(P):
 @pytest.mark.parametrize("it", [0, 15])
 def test_batched_sampling_bitexact(P, small_batch, it):
     sgs, ogs, gs = small_batch
+    # default order, graph-major with small items, 7 interleaved phases with large items and a capped grid
     tunes = [None, {"block_threads": 256, "groups_per_item": 1, "blocks_per_cu": 1},
-             {"block_threads": 1024, "groups_per_item": 16, "blocks_per_cu": 2, "max_blocks": 3}]
+             {"block_threads": 1024, "groups_per_item": 16, "blocks_per_cu": 2, "max_blocks": 3, "phases": 7},
+             {"block_threads": 512, "groups_per_item": 4, "blocks_per_cu": 1, "phases": 64}]
     outs = [P.batch_sample_terms(gs, it, tune=t, graph_id=5) for t in tunes]
     for k, og in enumerate(ogs):
         oi, oj, of = O.sample_terms(og, it, 0, 10 * og.S, graph_id=5 + k)
@@ -558,6 +560,7 @@ def test_batch_handle_runs_and_autotune_keeps_coords(P, small_batch):
     before = [c.clone() for c in cs]
     res = P.autotune(gs, cs, use_cache=False, max_blocks=4)
     assert res["block_threads"] % 64 == 0 and res["groups_per_item"] >= 1 and res["max_blocks"] == 4
+    assert res["phases"] in (1, 4)
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(before, cs))
     b = P.Batch(gs, cs, tune=res, first_iter=0, last_iter=2)
