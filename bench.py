@@ -31,36 +31,50 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-DOMINANT = {False: "k_layout_iter", True: "k_bin_layout"}  # by schedule: plain, binned
+SCHEDULES = {"plain": 1, "binned": 2, "windowed": 3}
+DOMINANT = {1: "k_layout_iter", 2: "k_bin_layout", 3: "k_layout_local"}  # the layout kernel of each schedule
 ALG_BYTES_PER_TERM = 64  # 2 step records (16 B each) + 2 endpoints read (8 B each) + written (8 B each)
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
-PROFILE_COMMANDS = """rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline
-rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o fetch -- python3 bench.py --profile
-rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o write -- python3 bench.py --profile
-rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d gpurun_out/prof_tcc -o tcc -- python3 bench.py --profile
-rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d gpurun_out/prof_rdreq -o rdreq -- python3 bench.py --profile
-python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv gpurun_out/prof_rdreq/rdreq_counter_collection.csv"""
-KERNEL_SOURCES = ["paper_2409_00876_amd/csrc/layout_kernels.hip", "paper_2409_00876_amd/csrc/binned_kernels.hip",
-                  "paper_2409_00876_amd/csrc/device.h", "paper_2409_00876_amd/csrc/internal.h"]
+CSRC = "paper_2409_00876_amd/csrc/"
+# the sources each layout kernel is compiled from (a counter summary is valid for this hash only)
+KERNEL_SOURCES = {
+    "k_layout_iter": [CSRC + "layout_kernels.hip", CSRC + "binned_kernels.hip", CSRC + "device.h", CSRC + "internal.h"],
+    "k_bin_layout": [CSRC + "layout_kernels.hip", CSRC + "binned_kernels.hip", CSRC + "device.h", CSRC + "internal.h"],
+    "k_layout_local": [CSRC + "local_kernels.hip", CSRC + "local.h", CSRC + "device.h", CSRC + "internal.h"],
+}
+COUNTERS_NAME = {"k_layout_iter": "layout_iter", "k_bin_layout": "bin_layout", "k_layout_local": "layout_local"}
 
 
-def kernel_source_hash() -> str:
+def counters_file(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{COUNTERS_NAME[kernel]}_chromosome_counters.json")
+
+
+def profile_commands(schedule: str) -> str:
+    opt = "" if schedule == "windowed" else f" --schedule {schedule}"
+    return f"""rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline{opt}
+rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o fetch -- python3 bench.py --profile{opt}
+rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o write -- python3 bench.py --profile{opt}
+rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d gpurun_out/prof_tcc -o tcc -- python3 bench.py --profile{opt}
+rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d gpurun_out/prof_rdreq -o rdreq -- python3 bench.py --profile{opt}
+python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv gpurun_out/prof_rdreq/rdreq_counter_collection.csv{opt}"""
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(terms_per_launch: int):
-    """Measured HBM traffic per launch from the committed counter summary, if it
-    was taken on the current kernel source and workload."""
+def stored_traffic(kernel: str, terms_per_launch: int):
+    """Measured HBM traffic per launch from the committed counter summary of
+    `kernel`, if it was taken on the current kernel source and workload."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(counters_file(kernel)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None, None
-    if rec.get("kernel_source_sha") != kernel_source_hash() or rec.get("terms_per_iteration") != terms_per_launch:
+    if rec.get("kernel_source_sha") != kernel_source_hash(kernel) or rec.get("terms_per_iteration") != terms_per_launch:
         return None, rec
     return rec.get("traffic_bytes_per_launch"), rec
 
@@ -74,18 +88,19 @@ def _read_counters(path):
     return rows
 
 
-def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: str, command: str,
+def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: str, schedule: str,
                        rdreq_csv: str = None) -> None:
     """Turns the rocprofv3 outputs of one --profile sequence into the committed
-    summaries: profiles/layout_iter_chromosome_counters.json (read by this
-    benchmark) and profiles/layout_iter_chromosome_counters.md."""
+    summaries profiles/<kernel>_chromosome_counters.json (read by this
+    benchmark) and .md, for the layout kernel of `schedule`."""
     import csv
     copy_bytes = 1 << 30
+    command = profile_commands(schedule)
+    kernel = DOMINANT[SCHEDULES[schedule]]
 
     fetch_rows = _read_counters(fetch_csv)
-    names = {k for k, c, v in fetch_rows}
-    dom = "pgsgd::k_bin_layout" if any(k.startswith("pgsgd::k_bin_layout") for k in names) else "pgsgd::k_layout_iter"
-    iter_kernels = ("pgsgd::k_bin_", "pgsgd::k_layout_iter")
+    dom = "pgsgd::" + kernel
+    iter_kernels = ("pgsgd::k_bin_", "pgsgd::k_layout_iter", "pgsgd::k_local_", "pgsgd::k_layout_local")
 
     def per_kernel(rows, counter):
         lay = [v for k, c, v in rows if c == counter and k.startswith(dom)]
@@ -119,7 +134,7 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
     it_traffic = (f_it * 1024 * f_factor + w_it * 1024 * w_factor) / n_iter_profiled
     rec = {"kernel": dom.split("::")[1], "workload": "chromosome", "terms_per_launch": T / launches,
            "launches_per_iteration": launches, "terms_per_iteration": T,
-           "kernel_source_sha": kernel_source_hash(), "command": command,
+           "kernel_source_sha": kernel_source_hash(kernel), "command": command,
            "trace_avg_launch_ms": avg_ns / 1e6, "trace_calls": int(stats["Calls"]),
            "fetch_calibration_factor": f_factor, "write_calibration_factor": w_factor,
            "fetch_bytes_per_launch": sum(fetch_b) / len(fetch_b), "write_bytes_per_launch": sum(write_b) / len(write_b),
@@ -142,7 +157,7 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
         rec["read_requests_per_launch"] = {k: v[0] for k, v in by.items()}
         rec["read_bytes_from_request_sizes"] = rd_bytes
         rec["copy_read_bytes_from_request_sizes"] = copy_rd
-    out = os.path.join(ROOT, "profiles", "layout_iter_chromosome_counters.json")
+    out = counters_file(kernel)
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
     md = out[:-5] + ".md"
@@ -151,6 +166,7 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
         f.write(f"Commands (from the repository root, with TMPDIR=/tmp):\n\n```\n{command}\n```\n\n")
         f.write("| quantity | value |\n|---|---|\n")
         f.write(f"| kernel-trace calls / average duration | {rec['trace_calls']} / {rec['trace_avg_launch_ms']:.2f} ms |\n")
+        f.write(f"| schedule | {schedule} |\n")
         f.write(f"| terms per launch / launches per iteration | {T / launches:,.0f} / {launches} |\n")
         f.write(f"| all kernels of an iteration: traffic per term | {it_traffic / T:.1f} B |\n")
         f.write(f"| FETCH_SIZE calibration (1 GiB copy) | x{f_factor:.4f} |\n")
@@ -416,6 +432,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chromosome", choices=["tiny", "mid", "chromosome"])
+    ap.add_argument("--schedule", default="windowed", choices=list(SCHEDULES),
+                    help="processing order of the layout loop (the library's automatic choice is windowed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--form", choices=["batched", "autograd", "metric", "reuse"], default=None,
@@ -426,7 +444,7 @@ def main():
                          "from rocprofv3 outputs (no GPU)")
     a = ap.parse_args()
     if a.summarize:
-        summarize_counters(*a.summarize[:4], command=PROFILE_COMMANDS,
+        summarize_counters(*a.summarize[:4], schedule=a.schedule,
                            rdreq_csv=a.summarize[4] if len(a.summarize) > 4 else None)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -455,13 +473,14 @@ def main():
     sg = synth.config_graph(a.workload)
     g = P.Graph.from_synth(sg, device=0)
     coords = g.new_coords()
-    params = P.LayoutParams()
+    params = P.LayoutParams(schedule=SCHEDULES[a.schedule])
     T = params.terms_per_step * g.n_steps
+    kernel = DOMINANT[params.schedule]
 
     if a.profile:
         P.init_coords(g, coords)
-        P.layout(g, coords, first_iter=0, last_iter=1)
-        P.layout(g, coords, first_iter=15, last_iter=16)
+        P.layout(g, coords, params, first_iter=0, last_iter=1)
+        P.layout(g, coords, params, first_iter=15, last_iter=16)
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         y = torch.empty_like(x)
         y.copy_(x)
@@ -472,7 +491,7 @@ def main():
     # warm-up (not timed)
     for _ in range(a.warmup):
         P.init_coords(g, coords)
-        P.layout(g, coords, seed=params.seed + 1)
+        P.layout(g, coords, params, seed=params.seed + 1)
     torch.cuda.synchronize()
 
     iter_ms, main_ms = [], []
@@ -493,10 +512,9 @@ def main():
     avg_ms = sum(main_ms) / (len(main_ms) * launches)  # one launch of the dominant kernel
     terms_per_launch = T / launches
     achieved = ALG_BYTES_PER_TERM * terms_per_launch / (avg_ms * 1e-3) / 1e9
-    binned = params.schedule == 2
-    traffic, counters = stored_traffic(T)
+    traffic, counters = stored_traffic(kernel, T)
     if traffic is not None and (counters.get("launches_per_iteration") != launches
-                                or counters.get("kernel") != DOMINANT[binned]):
+                                or counters.get("kernel") != kernel):
         traffic = None
 
     sps = P.path_stress(g, coords, pairs_per_step=10, seed=7)
@@ -529,7 +547,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": DOMINANT[binned], "avg_launch_ms": avg_ms,
+                     "kernel": kernel, "schedule": a.schedule, "avg_launch_ms": avg_ms,
                      "launches_per_iteration": launches, "terms_per_launch": terms_per_launch,
                      "bytes_per_term_algorithmic": ALG_BYTES_PER_TERM,
                      "iteration_ms": avg_iter_ms,

@@ -119,7 +119,7 @@ typedef struct {
   uint64_t seed;              /* Philox key */
   uint32_t first_iter;        /* run iterations [first_iter, last_iter) ... */
   uint32_t last_iter;         /* ... ; last_iter = 0 means n_iters */
-  uint32_t max_inflight_waves;/* plain schedule: cap on concurrently running 64-term groups; 0 = automatic */
+  uint32_t max_inflight_waves;/* cap on concurrently running 64-term groups (waves); 0 = automatic */
   uint32_t flags;             /* reserved, must be 0 */
   uint32_t schedule;          /* processing order of an iteration's terms: PGSGD_SCHEDULE_* */
   uint16_t reuse_factor;      /* data reuse: updates per sampled term (DRF), 0 or 1 = off, at most 16 */
@@ -128,7 +128,7 @@ typedef struct {
 
 /* Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
  * Trade-off with Sampled Path Stress"), active when reuse_factor > 1 or
- * step_reduction > 1 (plain schedule only):
+ * step_reduction > 1 (PLAIN or AUTO schedule only):
  *   - an iteration samples ceil(terms_per_step * S / step_reduction) terms in
  *     aligned groups of 64; a group's path is the path of the global step
  *     drawn by its first term (paths stay chosen with probability ∝ |p|), and
@@ -142,17 +142,39 @@ typedef struct {
  *     pairs are skipped.  Each endpoint is stored once at the end.
  * Updates per iteration: up to reuse_factor x the sampled terms. */
 
-/* Processing order of the terms of an iteration.  The sampled terms are the
- * same in every schedule; only the order (and so the Hogwild interleaving)
- * differs.
- *   PLAIN   term groups in index order over a grid capped by max_inflight_waves
- *   BINNED  terms binned by the window of consecutive path steps holding their
- *           step i, windows processed XCD by XCD for L2 locality of the step
- *           records and coordinates (uses scratch of 6 bytes per term of a
- *           chunk of up to 2^30 terms, allocated on first use)
- *   AUTO    PLAIN (on MI355X the binned order raises the layout kernel's L2
- *           hit rate but not its speed, and adds the binning passes) */
-enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_BINNED = 2 };
+/* Processing order of the terms of an iteration.
+ *   PLAIN    term groups in index order over a grid capped by
+ *            max_inflight_waves
+ *   BINNED   the PLAIN terms, binned by the window of consecutive path steps
+ *            holding their step i and processed window by window, XCD by XCD
+ *            (scratch of 6 bytes per term of a chunk of up to 2^30 terms,
+ *            allocated on first use); the same terms as PLAIN
+ *   WINDOWED window-major enumeration: the steps are cut into windows of
+ *            2^h consecutive global steps (h = 14, decreased while there
+ *            would be fewer than 64 windows but not below 6, increased while
+ *            there would be more than 32768); window w receives n_w slots,
+ *            n_w = the number of the iteration's PLAIN step draws that fall
+ *            in it (so (n_w) is multinomial(T, |w| / S)); slot s (windows in
+ *            order, s < T) draws Philox stream 5 at counter (s mod 2^32,
+ *            s >> 32, iter, 5 << 24 | graph_id), takes its step uniformly in
+ *            its window, i = start_w + floor(u64 * |w| / 2^64), and its
+ *            partner, endpoint coins and skips as a PLAIN term does from
+ *            words 2 and 3; its cooling coin is bit 3 of word 3 of the first
+ *            slot of its aligned 64-slot group within the window.  A
+ *            multinomial count of uniform draws per window is T i.i.d.
+ *            uniform steps: the distribution of terms of Alg. 1, in another
+ *            order.  Windows are processed in runs (each path cut into 8
+ *            pieces, XCD x takes piece x of every path), a window at a time
+ *            per XCD, so its step records and the coordinates of the nodes
+ *            it visits stay in the XCD's L2.  max_inflight_waves caps the
+ *            waves (automatic: about nodes_w / 40, nodes_w = 2^h * n_nodes *
+ *            n_paths / S the nodes a window visits, at most the PLAIN cap,
+ *            so that an XCD's in-flight terms stay below a fifth of its
+ *            window's nodes).  Scratch: a few
+ *            words per window, allocated on first use.  pgsgd_sample_terms
+ *            records slots [t_begin, t_begin + count) in slot order.
+ *   AUTO     WINDOWED, or PLAIN for the data-reuse variant */
+enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_BINNED = 2, PGSGD_SCHEDULE_WINDOWED = 3 };
 
 /* Fills the defaults listed above (seed 24301, graph_id 0). */
 void pgsgd_params_default(pgsgd_params *p);
@@ -357,12 +379,12 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph *const *graphs, uint32_t n, co
  * Writes the terms t in [t_begin, t_begin + count) of iteration iter, sampled
  * exactly as pgsgd_layout samples them: i_out, j_out (device uint64) and
  * flags_out (device uint8: bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped).
- * The terms are recorded by the layout kernel itself, with the launch shape
- * pgsgd_layout uses: the plain kernel unless p->schedule is
- * PGSGD_SCHEDULE_BINNED, in which case the binning kernels and the binned
- * layout kernel process the whole iteration (without updating coordinates)
- * and record the terms of the range, which must lie in [0, terms_per_step * S).
- * With the data-reuse variant active it records that variant's terms
+ * The terms are recorded by the layout kernels of the schedule p->schedule
+ * resolves to, with the launch shape pgsgd_layout uses: PLAIN records with the
+ * plain kernel; BINNED and WINDOWED run their counting and layout kernels over
+ * the whole iteration (without updating coordinates) and record the terms
+ * (WINDOWED: the slots) of the range, which must lie in [0, terms_per_step *
+ * S).  With the data-reuse variant active it records that variant's terms
  * (see pgsgd_sample_terms_reuse).  Async.
  */
 pgsgd_status pgsgd_sample_terms(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,

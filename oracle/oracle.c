@@ -217,11 +217,10 @@ static void partner_power_law(const or_graph *g, const sampler *sp, uint64_t i, 
   (void)g;
 }
 
-static void sample_term(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t t, uint32_t group_coin,
-                        uint64_t *i_out, uint64_t *j_out, uint32_t *flags) {
-  uint32_t r[4];
-  draw(sp->seed, t, iter, STREAM_LAYOUT, sp->graph_id, r);
-  uint64_t i = mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), g->S);
+/* Everything of a term after its step i: partner, endpoint coins, skips;
+ * r is the term's draw (words 2 and 3 are used). */
+static void term_from_step(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t i, const uint32_t r[4],
+                           uint32_t group_coin, uint64_t *i_out, uint64_t *j_out, uint32_t *flags) {
   uint32_t p = path_of_step(g, i);
   uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
   uint32_t cooling = (iter >= sp->n_iters / 2) || group_coin;
@@ -237,6 +236,14 @@ static void sample_term(const or_graph *g, const sampler *sp, uint32_t iter, uin
   }
   *i_out = i; *j_out = j;
   *flags = e_i | (e_j << 1) | (cooling << 2) | ((uint32_t)skip << 3);
+}
+
+static void sample_term(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t t, uint32_t group_coin,
+                        uint64_t *i_out, uint64_t *j_out, uint32_t *flags) {
+  uint32_t r[4];
+  draw(sp->seed, t, iter, STREAM_LAYOUT, sp->graph_id, r);
+  uint64_t i = mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), g->S);
+  term_from_step(g, sp, iter, i, r, group_coin, i_out, j_out, flags);
 }
 
 /* The fair coin of R2 for the 64-term group containing t: bit 3 of word 3 of
@@ -568,6 +575,147 @@ uint64_t or_layout_reuse(const or_graph *g, uint32_t n_iters, uint32_t terms_per
         }
       }
     }
+  }
+  free((void *)sp.zipf);
+  free(eta);
+  return applied;
+}
+
+/* ---------------------------------------------------------------------------
+ * Window-major enumeration of an iteration's terms (reading R18).  The steps
+ * are cut into windows of 2^shift consecutive global steps, shift =
+ * or_window_shift(S).  The iteration's T = terms_per_step * S terms are
+ *   - counted per window: n_w = #{t < T : floor(i_t / 2^shift) = w}, i_t the
+ *     step of term t of the plain definition (sample_term), so (n_w) is
+ *     multinomial(T, |w| / S);
+ *   - enumerated as slots, window after window: slot s = off_w + k (off_w the
+ *     prefix of the counts, k < n_w) draws Philox stream 5 at counter s; its
+ *     step is uniform in the window, i = start_w + floor(u64 * |w| / 2^64), and
+ *     the rest follows term_from_step with the draw's words 2 and 3; the
+ *     cooling coin is bit 3 of word 3 of slot off_w + 64 * floor(k / 64).
+ * A multinomial count of uniform draws per window is T i.i.d. uniform steps,
+ * so the terms have the distribution of Alg. 1; only their order differs.
+ * ------------------------------------------------------------------------- */
+enum { STREAM_WINDOW = 5 };
+
+uint32_t or_window_shift(uint64_t S) {
+  uint32_t sh = 14;
+  while (sh > 6 && ((S + (1ull << sh) - 1) >> sh) < 64) --sh;
+  while (((S + (1ull << sh) - 1) >> sh) > 32768) ++sh;
+  return sh;
+}
+
+typedef struct {
+  const or_graph *g; uint64_t seed; uint32_t graph_id, iter, sh; uint64_t t0, t1, n_win; uint64_t *counts;
+} count_job;
+
+static void *count_worker(void *arg) {
+  count_job *jb = (count_job *)arg;
+  for (uint64_t w = 0; w < jb->n_win; ++w) jb->counts[w] = 0;
+  for (uint64_t t = jb->t0; t < jb->t1; ++t) {
+    uint32_t r[4];
+    draw(jb->seed, t, jb->iter, STREAM_LAYOUT, jb->graph_id, r);
+    jb->counts[mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), jb->g->S) >> jb->sh]++;
+  }
+  return NULL;
+}
+
+/* The counts n_w; `threads` threads count contiguous term ranges into their
+ * own histograms, which are then summed (the same integers for any count). */
+void or_window_counts(const or_graph *g, uint64_t seed, uint32_t graph_id, uint32_t iter, uint32_t terms_per_step,
+                      uint64_t *counts, uint32_t threads) {
+  uint32_t sh = or_window_shift(g->S);
+  uint64_t n_win = (g->S + (1ull << sh) - 1) >> sh, T = (uint64_t)terms_per_step * g->S;
+  if (threads < 1) threads = 1;
+  count_job *jobs = (count_job *)calloc(threads, sizeof(count_job));
+  pthread_t *tid = (pthread_t *)calloc(threads, sizeof(pthread_t));
+  for (uint32_t k = 0; k < threads; ++k) {
+    jobs[k].g = g; jobs[k].seed = seed; jobs[k].graph_id = graph_id; jobs[k].iter = iter; jobs[k].sh = sh;
+    jobs[k].t0 = T * k / threads; jobs[k].t1 = T * (k + 1) / threads; jobs[k].n_win = n_win;
+    jobs[k].counts = (uint64_t *)malloc(sizeof(uint64_t) * (n_win ? n_win : 1));
+    pthread_create(&tid[k], NULL, count_worker, &jobs[k]);
+  }
+  for (uint64_t w = 0; w < n_win; ++w) counts[w] = 0;
+  for (uint32_t k = 0; k < threads; ++k) {
+    pthread_join(tid[k], NULL);
+    for (uint64_t w = 0; w < n_win; ++w) counts[w] += jobs[k].counts[w];
+    free(jobs[k].counts);
+  }
+  free(jobs);
+  free(tid);
+}
+
+/* Slot k of window w (first slot off_w). */
+static void sample_slot(const or_graph *g, const sampler *sp, uint32_t iter, uint32_t sh, uint64_t w, uint64_t off_w,
+                        uint64_t k, uint64_t *i_out, uint64_t *j_out, uint32_t *flags) {
+  uint32_t r[4], lead[4];
+  draw(sp->seed, off_w + k, iter, STREAM_WINDOW, sp->graph_id, r);
+  draw(sp->seed, off_w + k - (k % 64), iter, STREAM_WINDOW, sp->graph_id, lead);
+  uint64_t start = w << sh, len = g->S - start < (1ull << sh) ? g->S - start : (1ull << sh);
+  uint64_t i = start + mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), len);
+  term_from_step(g, sp, iter, i, r, (lead[3] >> 3) & 1u, i_out, j_out, flags);
+}
+
+static uint64_t *window_offsets(const or_graph *g, const sampler *sp, uint32_t iter, uint32_t terms_per_step,
+                                uint64_t *n_win_out) {
+  uint32_t sh = or_window_shift(g->S);
+  uint64_t n_win = (g->S + (1ull << sh) - 1) >> sh;
+  uint64_t *off = (uint64_t *)malloc(sizeof(uint64_t) * (n_win + 1));
+  or_window_counts(g, sp->seed, sp->graph_id, iter, terms_per_step, off + 1, 1);
+  off[0] = 0;
+  for (uint64_t w = 0; w < n_win; ++w) off[w + 1] += off[w];
+  *n_win_out = n_win;
+  return off;
+}
+
+/* Slots [s_begin, s_begin + count) (all below T) given the window offsets
+ * off[0..n_win] (the prefix of or_window_counts for the same iteration). */
+void or_sample_terms_windowed(const or_graph *g, uint32_t n_iters, double theta, uint32_t W, uint64_t seed,
+                              uint32_t graph_id, uint32_t iter, const uint64_t *off, uint64_t s_begin,
+                              uint64_t count, uint64_t *i_out, uint64_t *j_out, uint8_t *flags_out) {
+  if (g->S == 0) return;
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  uint32_t sh = or_window_shift(g->S);
+  uint64_t n_win = (g->S + (1ull << sh) - 1) >> sh, w = 0;
+  for (uint64_t k = 0; k < count; ++k) {
+    uint64_t s = s_begin + k;
+    while (w + 1 < n_win && off[w + 1] <= s) ++w;
+    uint32_t fl;
+    sample_slot(g, &sp, iter, sh, w, off[w], s - off[w], &i_out[k], &j_out[k], &fl);
+    flags_out[k] = (uint8_t)fl;
+  }
+  free((void *)sp.zipf);
+}
+
+/* The layout loop of Alg. 1 with the window-major enumeration, one thread,
+ * slots in order. */
+uint64_t or_layout_windowed(const or_graph *g, uint32_t n_iters, uint32_t terms_per_step, double eta_max,
+                            double eta_min, double theta, uint32_t W, uint64_t seed, uint32_t graph_id, uint32_t first,
+                            uint32_t last, float *coords) {
+  if (g->S == 0 || n_iters == 0) return 0;
+  if (eta_max <= 0.0) eta_max = (double)g->d_max * (double)g->d_max;
+  double *eta = (double *)malloc(sizeof(double) * n_iters);
+  or_schedule(n_iters, eta_max, eta_min, eta);
+  sampler sp;
+  make_sampler(&sp, n_iters, theta, W, seed, graph_id);
+  float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  uint32_t sh = or_window_shift(g->S);
+  uint64_t applied = 0;
+  if (last == 0 || last > n_iters) last = n_iters;
+  for (uint32_t it = first; it < last; ++it) {
+    uint64_t n_win;
+    uint64_t *off = window_offsets(g, &sp, it, terms_per_step, &n_win);
+    for (uint64_t w = 0; w < n_win; ++w)
+      for (uint64_t k = 0; k < off[w + 1] - off[w]; ++k) {
+        uint64_t i, j;
+        uint32_t fl;
+        sample_slot(g, &sp, it, sh, w, off[w], k, &i, &j, &fl);
+        if (fl & 8u) continue;
+        uint64_t a = 2ull * step_node_id(g, i) + (fl & 1u), b = 2ull * step_node_id(g, j) + ((fl >> 1) & 1u);
+        applied += update_f32(X, Y, a, b, term_distance(g, i, j, fl), eta[it]);
+      }
+    free(off);
   }
   free((void *)sp.zipf);
   free(eta);

@@ -18,7 +18,7 @@ ERR_RANGE = -2
 ERR_OOM = -3
 ERR_DEVICE = -4
 ERR_UNSUPPORTED = -5
-SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_BINNED = 0, 1, 2
+SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_BINNED, SCHEDULE_WINDOWED = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "RANGE", -3: "OOM", -4: "DEVICE", -5: "UNSUPPORTED"}
 
 

@@ -23,6 +23,7 @@
 #include "batch.h"
 #include "device.h"
 #include "internal.h"
+#include "local.h"
 
 using namespace pgsgd;
 
@@ -147,13 +148,23 @@ struct pgsgd_graph {
   uint32_t* d_woff = nullptr;
   uint32_t* d_cursor = nullptr;
   uint32_t* d_xitem = nullptr;
+  // window-major scratch (allocated on first use)
+  uint32_t loc_nwin = 0, loc_shift = 0, loc_xstride = 0, loc_streams = 0;
+  uint32_t* d_lcount = nullptr;
+  uint64_t* d_loff = nullptr;
+  uint64_t* d_lxitem = nullptr;
+  uint64_t* d_lqueue = nullptr;
+  uint32_t* d_lorder = nullptr;
+  uint32_t* d_lsbeg = nullptr;
 
   ~pgsgd_graph() {
     DeviceGuard g(device);
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
                     (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_tag,
-                    (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem})
+                    (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem,
+                    (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
+                    (void*)d_lsbeg})
       if (p) (void)hipFree(p);
   }
 };
@@ -200,9 +211,10 @@ pgsgd_status check_params(const pgsgd_params* p) {
   if (!p) return fail(PGSGD_ERR_INVALID_ARG, "params is NULL");
   if (p->flags != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags must be 0");
   if (p->reuse_factor > 16) return fail(PGSGD_ERR_INVALID_ARG, "reuse_factor must be at most 16");
-  if ((p->reuse_factor > 1 || p->step_reduction > 1) && p->schedule == PGSGD_SCHEDULE_BINNED)
+  if (p->schedule > PGSGD_SCHEDULE_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
+  if ((p->reuse_factor > 1 || p->step_reduction > 1) &&
+      (p->schedule == PGSGD_SCHEDULE_BINNED || p->schedule == PGSGD_SCHEDULE_WINDOWED))
     return fail(PGSGD_ERR_INVALID_ARG, "the data-reuse variant runs with the plain schedule only");
-  if (p->schedule > PGSGD_SCHEDULE_BINNED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
   if (p->zipf_window < 1 || p->zipf_window > 65535)
     return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", p->zipf_window);
   if (!(p->zipf_theta >= 0.0) || !std::isfinite(p->zipf_theta))
@@ -552,12 +564,14 @@ extern "C" {
 
 namespace {
 
-// AUTO selects PLAIN: on MI355X the binned order raises the L2 hit rate of the
-// layout kernel (9% -> 28% at 2^16-step windows) without making it faster, and
-// the binning passes cost about a quarter of an iteration.
-bool use_binned(const pgsgd_graph* g, const pgsgd_params* p) {
-  (void)g;
-  return p->schedule == PGSGD_SCHEDULE_BINNED;
+// AUTO selects WINDOWED (PLAIN for the data-reuse variant, which needs the
+// plain enumeration): on MI355X the window-major order keeps a window's
+// records and coordinates in the L2 and is 2-3x faster than PLAIN at the same
+// layout quality.  BINNED orders the plain terms by window but its binning
+// passes cost more than they save.
+uint32_t resolve_schedule(const pgsgd_params* p) {
+  if (p->schedule != PGSGD_SCHEDULE_AUTO) return p->schedule;
+  return (p->reuse_factor > 1 || p->step_reduction > 1) ? PGSGD_SCHEDULE_PLAIN : PGSGD_SCHEDULE_WINDOWED;
 }
 
 // Binning scratch for chunks of up to min(T, kBinChunk) terms: windows of
@@ -587,6 +601,89 @@ pgsgd_status ensure_bins(pgsgd_graph* g, uint64_t n_terms, hipStream_t s) {
   if ((st = dev_alloc(g, &g->d_cursor, nwin))) return st;
   if ((st = dev_alloc(g, &g->d_xitem, (size_t)kXcds * g->bin_xstride))) return st;
   HIP_TRY(launch_fill_u32(g->d_wcount, nwin, 0u, s));  // the histogram must start at zero
+  return PGSGD_OK;
+}
+
+// Window-major scratch: windows of 2^window_shift(S) steps, grouped into
+// kXcds * streams runs by the piece of their path they lie in.
+pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
+  const uint32_t shift = window_shift(g->S);
+  const uint32_t nwin = (uint32_t)((g->S + (1ull << shift) - 1) >> shift);
+  if ((size_t)nwin * 4 > g->lds_limit)
+    return fail(PGSGD_ERR_UNSUPPORTED, "the window histogram (%u windows) exceeds the %zu-byte LDS of a block", nwin,
+                g->lds_limit);
+  if (g->d_lcount && g->loc_nwin == nwin && g->loc_shift == shift && g->loc_streams == streams) return PGSGD_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  for (void** q : {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
+                   (void**)&g->d_lorder, (void**)&g->d_lsbeg})
+    if (*q) {
+      (void)hipFree(*q);
+      *q = nullptr;
+    }
+  g->loc_nwin = nwin;
+  g->loc_shift = shift;
+  g->loc_streams = streams;
+  const uint32_t runs = kXcds * streams;
+  // run of a window: the piece of its path it starts in (each path cut into
+  // `runs` equal pieces); windows keep their id order inside a run
+  std::vector<uint32_t> order(nwin), sbeg(runs + 1, 0), run_of(nwin);
+  {
+    uint32_t p = 0;
+    for (uint32_t w = 0; w < nwin; ++w) {
+      const uint64_t st0 = (uint64_t)w << shift;
+      while (p + 1 < g->n_paths && g->h_path_off[p + 1] <= st0) ++p;
+      const uint64_t b = g->h_path_off[p], len = g->h_path_off[p + 1] - b;
+      const uint64_t r = len ? ((st0 - b) * runs) / len : 0;
+      run_of[w] = (uint32_t)std::min<uint64_t>(r, runs - 1);
+      ++sbeg[run_of[w] + 1];
+    }
+    for (uint32_t r = 0; r < runs; ++r) sbeg[r + 1] += sbeg[r];
+    std::vector<uint32_t> cur(sbeg.begin(), sbeg.end() - 1);
+    for (uint32_t w = 0; w < nwin; ++w) order[cur[run_of[w]]++] = w;
+  }
+  // a row of xitem holds the prefix over the windows of one run and its total
+  uint32_t longest = 0;
+  for (uint32_t r = 0; r < runs; ++r) longest = std::max(longest, sbeg[r + 1] - sbeg[r]);
+  g->loc_xstride = longest + 1;
+  pgsgd_status st;
+  if ((st = dev_alloc(g, &g->d_lcount, nwin))) return st;
+  if ((st = dev_alloc(g, &g->d_loff, nwin + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_lxitem, (size_t)runs * g->loc_xstride))) return st;
+  if ((st = dev_alloc(g, &g->d_lqueue, (size_t)runs * 16))) return st;
+  if ((st = dev_alloc(g, &g->d_lorder, nwin))) return st;
+  if ((st = dev_alloc(g, &g->d_lsbeg, runs + 1))) return st;
+  HIP_TRY(hipMemcpy(g->d_lorder, order.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->d_lsbeg, sbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
+  HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histogram must start at zero
+  return PGSGD_OK;
+}
+
+// Automatic wave cap of the windowed schedule (see kLocalNodesPerWave).
+uint64_t auto_local_waves(const pgsgd_graph* g) {
+  const uint32_t sh = window_shift(g->S);
+  const double nodes_w = std::min<double>((double)g->n_nodes,
+                                          std::ldexp(1.0, (int)sh) * (double)g->n_nodes * g->n_paths / (double)g->S);
+  const uint64_t w = (uint64_t)(nodes_w / (double)kLocalNodesPerWave);
+  return std::max<uint64_t>(1, std::min(w, auto_inflight_waves(g)));
+}
+
+// Grid of k_layout_local: the in-flight wave cap (params.max_inflight_waves,
+// automatic: auto_local_waves) and occupancy give the waves; 256-thread
+// blocks in a multiple of 8 (one share per XCD), or 64-thread blocks below 32
+// waves.
+pgsgd_status local_grid(pgsgd_graph* g, const pgsgd_params* p, size_t lds, uint32_t* blocks, uint32_t* threads) {
+  int nb = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, layout_local_kernel(), 256, lds));
+  uint64_t waves = (uint64_t)g->n_cu * (uint64_t)std::max(nb, 1) * 4;
+  const uint64_t cap = p->max_inflight_waves ? p->max_inflight_waves : auto_local_waves(g);
+  waves = std::max<uint64_t>(1, std::min(waves, cap));
+  if (waves >= 4ull * kXcds) {
+    *threads = 256;
+    *blocks = (uint32_t)((waves / 4) / kXcds * kXcds);
+  } else {
+    *threads = 64;
+    *blocks = (uint32_t)waves;
+  }
   return PGSGD_OK;
 }
 
@@ -635,11 +732,37 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   L.g_begin = 0;
   L.g_end = L.n_groups;
   const bool reuse = p->reuse_factor > 1 || p->step_reduction > 1;
-  const bool binned = tracing || use_binned(g, p);
+  const uint32_t sched = resolve_schedule(p);
+  const bool windowed = sched == PGSGD_SCHEDULE_WINDOWED;
+  const bool binned = !windowed && (tracing || sched == PGSGD_SCHEDULE_BINNED);
   uint32_t blocks = 0, threads = 256;
   BinLaunch B{};
+  LocalLaunch W{};
   uint64_t n_chunks = 1;
-  if (binned) {
+  if (windowed) {
+    const uint32_t streams = kLocalStreams, grab = kLocalGrab;
+    if ((st = ensure_local(g, streams, s))) return st;
+    if ((st = local_grid(g, p, lds, &blocks, &threads))) return st;
+    W.n_win = g->loc_nwin;
+    W.win_shift = g->loc_shift;
+    W.count_blocks = (uint32_t)g->n_cu * 2;
+    W.xstride = g->loc_xstride;
+    W.wcount = g->d_lcount;
+    W.woff = g->d_loff;
+    W.xitem = g->d_lxitem;
+    W.queue = g->d_lqueue;
+    W.worder = g->d_lorder;
+    W.sbeg = g->d_lsbeg;
+    W.streams = streams;
+    W.grab = grab;
+    L.trace_i = trace_i;
+    L.trace_j = trace_j;
+    L.trace_f = trace_f;
+    if (tracing) {
+      L.t_begin = trace_begin;
+      L.t_end = trace_begin + trace_count;
+    }
+  } else if (binned) {
     if ((st = ensure_bins(g, L.n_terms, s))) return st;
     if ((st = bin_blocks(g, lds, &blocks))) return st;
     B.n_win = g->bin_nwin;
@@ -685,7 +808,14 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
     L.eta = eta[it];
     if (iter_ms) HIP_TRY(hipEventRecord(ev[e0], s));
-    if (binned) {
+    if (windowed) {
+      W.L = L;
+      HIP_TRY(launch_local_count_scan(W, s));
+      HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(W.queue), 2ull * kXcds * W.streams * 16, 0u, s));
+      if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1], s));
+      HIP_TRY(launch_layout_local(W, blocks, threads, s));
+      if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
+    } else if (binned) {
       for (uint64_t c = 0; c < n_chunks; ++c) {
         B.L = L;
         B.c0 = c * g->bin_chunk;
@@ -785,14 +915,17 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t 
   if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
   if (t_begin + count < t_begin || t_begin + count >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term range too large");
   if (count == 0 || g->S == 0) return ok();
-  if (p->schedule == PGSGD_SCHEDULE_BINNED) {
-    // the binning kernels and the binned layout kernel process the whole
-    // iteration; the terms of [t_begin, t_begin + count) are recorded
+  const uint32_t sched = resolve_schedule(p);
+  if (sched == PGSGD_SCHEDULE_BINNED || sched == PGSGD_SCHEDULE_WINDOWED) {
+    // the binning (window count) kernels and the layout kernel process the
+    // whole iteration; the terms (window-major slots) of [t_begin, t_begin +
+    // count) are recorded
     if (t_begin + count > (uint64_t)p->terms_per_step * g->S)
-      return fail(PGSGD_ERR_INVALID_ARG, "the binned schedule records terms of the iteration only (t < T)");
+      return fail(PGSGD_ERR_INVALID_ARG, "this schedule records terms of the iteration only (t < T)");
     pgsgd_params q = *p;
     q.first_iter = iter;
     q.last_iter = iter + 1;
+    q.schedule = sched;
     return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, i_out, j_out, flags_out, t_begin, count);
   }
   DeviceGuard guard(g->device);

@@ -1,0 +1,194 @@
+// Window-major schedule of one PG-SGD iteration for gfx950.
+//
+// The steps are cut into windows of 2^win_shift consecutive global steps.  An
+// iteration of T terms is enumerated window by window:
+//   1. counts: n_w = the number of the iteration's plain step draws (term t:
+//      i_t = floor(u64(t) * S / 2^64), the same draw as the plain schedule)
+//      that fall in window w, so (n_w) is exactly multinomial(T, |w| / S);
+//   2. slot k of window w (global slot s = sum_{v<w} n_v + k) draws its step
+//      uniformly inside the window from Philox stream 5 at counter s, and its
+//      partner, endpoint coins and cooling exactly as a plain term does; the
+//      cooling coin belongs to aligned groups of 64 slots of a window.
+// A multinomial number of uniform draws per window is an i.i.d. uniform draw
+// over all steps, so an iteration samples the same distribution of terms as
+// Alg. 1; only the processing order differs (Hogwild leaves it free).
+//
+// Every path is cut into 8 * streams equal pieces and the windows are grouped
+// into runs by the piece they start in (run sigma: piece sigma of path 0, then
+// of path 1, ...).  XCD x (blocks b with b mod 8 = x) works on its `streams`
+// runs at the same time, each run window after window.  So a window's step
+// records and the coordinates of the nodes its steps visit (close ids in a
+// locality-ordered graph) stay in the XCD's 4 MB L2, cooling partners (within W
+// steps) fall into the same window, uniform partners stay inside the one or
+// two paths in progress (few address translation misses), and the concurrent
+// updates are spread over 8 * streams far-apart stretches of the graph (few
+// lost Hogwild updates).
+//   k_local_count  plain draw i_t, window histogram (LDS, then global)
+//   k_local_scan   window offsets, per-run group prefixes; clears the histogram
+//   k_layout_local slot draw, sample, gather, update
+#include "device.h"
+#include "local.h"
+
+namespace pgsgd {
+
+__global__ __launch_bounds__(1024) void k_local_count(LocalLaunch P) {
+  extern __shared__ __align__(16) char lds[];
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds);
+  for (uint32_t k = threadIdx.x; k < P.n_win; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  const LayoutLaunch& L = P.L;
+  const uint64_t lane_stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L.n_terms; t += lane_stride) {
+    const Rand4 r = philox10((uint32_t)t, (uint32_t)(t >> 32), L.iter, L.c3, L.k0, L.k1);
+    const uint64_t i = mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), L.S);
+    atomicAdd(&hist[(uint32_t)(i >> P.win_shift)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < P.n_win; k += blockDim.x)
+    if (hist[k]) atomicAdd(&P.wcount[k], hist[k]);
+}
+
+// One block.  woff = exclusive prefix of wcount; per run the prefix of
+// ceil(n_w / 64) over its windows; then wcount = 0.
+__global__ __launch_bounds__(1024) void k_local_scan(LocalLaunch P) {
+  __shared__ uint64_t part[1024];
+  const uint32_t n = P.n_win;
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t k0 = min(n, threadIdx.x * per);
+  const uint32_t k1 = min(n, k0 + per);
+  uint64_t s = 0;
+  for (uint32_t k = k0; k < k1; ++k) s += P.wcount[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t acc = 0;
+    for (uint32_t k = 0; k < blockDim.x; ++k) {
+      const uint64_t v = part[k];
+      part[k] = acc;
+      acc += v;
+    }
+    P.woff[n] = acc;
+  }
+  __syncthreads();
+  uint64_t acc = part[threadIdx.x];
+  for (uint32_t k = k0; k < k1; ++k) {
+    P.woff[k] = acc;
+    acc += P.wcount[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kXcds * P.streams) {
+    const uint32_t run = threadIdx.x;
+    uint64_t* xi = P.xitem + (size_t)run * P.xstride;
+    uint64_t items = 0;
+    const uint32_t b = P.sbeg[run], e = P.sbeg[run + 1];
+    for (uint32_t q = b; q < e; ++q) {
+      xi[q - b] = items;
+      items += (P.wcount[P.worder[q]] + 63) >> 6;
+    }
+    xi[e - b] = items;
+  }
+  __syncthreads();
+  for (uint32_t k = k0; k < k1; ++k) P.wcount[k] = 0;
+}
+
+// The 64 slots of item m of a run (windows worder[wb], worder[wb + 1], ...);
+// q is the calling wave's window cursor in the run (items only grow).
+__device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
+                                           const uint64_t* __restrict__ xi, uint64_t m, uint32_t& q) {
+  const LayoutLaunch& L = P.L;
+  const uint32_t lane = threadIdx.x & 63u;
+  while (q + 1 < nq && xi[q + 1] <= m) ++q;
+  const uint32_t w = P.worder[wb + q];
+  const uint64_t wbeg = P.woff[w];
+  const uint64_t nw = P.woff[w + 1] - wbeg;
+  const uint64_t k = (m - xi[q]) * 64 + lane;
+  const uint64_t s = wbeg + k;  // global slot
+  const uint32_t slot_c3 = (kStreamWindow << 24) | (L.c3 & 0xFFFFFFu);
+  const Rand4 r = philox10((uint32_t)s, (uint32_t)(s >> 32), L.iter, slot_c3, L.k0, L.k1);
+  const uint32_t lead = uniform_u32(r.r3);  // lane 0: slot 64 * group, always inside the window
+  const bool cooling = L.cool_all || ((lead >> 3) & 1u);
+  if (k >= nw) return;
+  const uint64_t wstart = (uint64_t)w << P.win_shift;
+  const uint64_t wlen = min((uint64_t)1 << P.win_shift, L.S - wstart);
+  Term T;
+  T.i = wstart + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), wlen);
+  const uint32_t p = find_path(V.off, L.path_top, T.i);
+  const uint64_t start = V.off[p];
+  const uint64_t len = V.off[p + 1] - start;
+  bool ok = true;
+  if (cooling) ok = partner_power_law(T.i, start, len, r.r2, r.r3, V.zipf, V.guide, L.W, T.j);
+  else T.j = start + mulhi32(r.r2, (uint32_t)len);
+  T.flags = (r.r3 & 3u) | ((cooling ? 1u : 0u) << 2) | ((ok ? 0u : 1u) << 3);
+  if (L.trace_f) {  // parity hook: record the slots of [t_begin, t_end) instead of applying them
+    if (s < L.t_begin || s >= L.t_end) return;
+    if (!(T.flags & 8u)) {
+      uint64_t a, b;
+      float d;
+      if (!resolve_term(L.rec, T, a, b, d)) T.flags |= 8u;
+    }
+    const uint64_t o = s - L.t_begin;
+    L.trace_i[o] = T.i;
+    L.trace_j[o] = T.j;
+    L.trace_f[o] = (uint8_t)T.flags;
+    return;
+  }
+  if (T.flags & 8u) return;
+  uint64_t a, b;
+  float d;
+  if (!resolve_term(L.rec, T, a, b, d)) return;
+  apply_update(L.work, a, b, d, L.eta);
+}
+
+__global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
+  extern __shared__ __align__(16) char lds[];
+  const LayoutLaunch& L = P.L;
+  const LdsView V = lds_view(lds, L.path_slots, L.W);
+  lds_fill(V, L.path_off, L.n_paths, L.path_slots, L.zipf, L.guide, L.W);
+  __syncthreads();
+
+  // blocks are dispatched to the XCDs round-robin: block b runs on XCD b % 8
+  // and takes the runs of XCD share b % 8 (with fewer than 8 blocks, block b
+  // takes the shares b, b + blocks, ...); wave v of a share starts on stream
+  // v mod streams and, when that run is exhausted, helps the share's other
+  // runs in turn
+  const uint32_t nx = min(gridDim.x, kXcds);
+  const uint32_t v = (blockIdx.x / nx) * (blockDim.x >> 6) + uniform_u32(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint32_t x = blockIdx.x % nx; x < kXcds; x += nx)
+  for (uint32_t h = 0; h < P.streams; ++h) {
+    const uint32_t run = x * P.streams + (v + h) % P.streams;
+    const uint32_t wb = P.sbeg[run];
+    const uint32_t nq = P.sbeg[run + 1] - wb;
+    const uint64_t* __restrict__ xi = P.xitem + (size_t)run * P.xstride;
+    const uint64_t n_items = xi[nq];
+    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(P.queue + (size_t)run * 16);
+    uint32_t q = 0;
+    for (uint64_t m = 0, m_end = 0;; ++m) {
+      if (m >= m_end) {
+        uint64_t base = 0;
+        if (lane == 0) base = atomicAdd(ctr, (unsigned long long)P.grab);
+        m = ((uint64_t)uniform_u32((uint32_t)(base >> 32)) << 32) | uniform_u32((uint32_t)base);
+        if (m >= n_items) break;
+        m_end = min(m + P.grab, n_items);
+      }
+      local_item(P, V, wb, nq, xi, m, q);
+    }
+  }
+}
+
+hipError_t launch_local_count_scan(const LocalLaunch& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_local_count, dim3(P.count_blocks), dim3(1024), (size_t)P.n_win * 4, s, P);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_local_scan, dim3(1), dim3(1024), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout_local(const LocalLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s) {
+  hipLaunchKernelGGL(k_layout_local, dim3(blocks), dim3(threads), layout_lds_bytes(P.L.path_slots, P.L.W), s, P);
+  return hipGetLastError();
+}
+
+const void* layout_local_kernel() { return reinterpret_cast<const void*>(&k_layout_local); }
+
+}  // namespace pgsgd

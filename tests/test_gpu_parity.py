@@ -69,6 +69,7 @@ def _to_np_u64(t):
 
 
 def _compare_terms(P, g, og, it, t0, count, **kw):
+    kw.setdefault("schedule", 1)  # the plain enumeration (the others have their own checks)
     i, j, f = P.sample_terms(g, it, t0, count, **kw)
     oi, oj, of = O.sample_terms(og, it, t0, count, **{k: v for k, v in kw.items() if k in ("seed", "graph_id")})
     gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
@@ -171,6 +172,55 @@ def test_binned_sampling_bitexact_chromosome(P, chromosome, it):
 
 
 # ---------------------------------------------------------------------------
+# The windowed schedule: window-major slots (reading R18), recorded by its kernels
+# ---------------------------------------------------------------------------
+def _compare_windowed(P, g, og, it, s0, count, offsets=None, **kw):
+    i, j, f = P.sample_terms(g, it, s0, count, schedule=3, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("seed", "graph_id")}
+    oi, oj, of = O.sample_terms_windowed(og, it, s0, count, offsets=offsets, threads=16, **okw)
+    gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
+    assert not np.any(gf == 255), "a slot was not processed"
+    bad = np.nonzero((gi != oi) | (gj != oj) | (gf != of))[0]
+    assert bad.size == 0, f"iter {it} s0 {s0}: {bad.size} mismatches, first at s={s0 + bad[0]}: " \
+                          f"gpu ({gi[bad[0]]},{gj[bad[0]]},{gf[bad[0]]}) oracle ({oi[bad[0]]},{oj[bad[0]]},{of[bad[0]]})"
+
+
+@pytest.mark.parametrize("it", [0, 14, 15, 29])
+def test_windowed_sampling_bitexact_tiny(P, tiny, it):
+    sg, og, g = tiny
+    T = 10 * og.S  # whole iteration
+    for waves in (0, 1, 37, 4096):  # the terms do not depend on the launch shape
+        _compare_windowed(P, g, og, it, 0, T, max_inflight_waves=waves)
+    _compare_windowed(P, g, og, it, 1000 + 7, 1 << 16, graph_id=5, seed=99)
+
+
+def test_windowed_sampling_edge_graph(P):
+    sg = _edge_synth()
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    for it in (0, 15, 29):
+        _compare_windowed(P, g, og, it, 0, 10 * og.S)
+
+
+@pytest.mark.parametrize("it", [0, 15])
+def test_windowed_sampling_bitexact_mid(P, mid, it):
+    sg, og, g = mid
+    T = 10 * og.S
+    off = O.window_offsets(og, it, threads=16)
+    for s0, n in ((0, 1 << 20), (T // 3 + 17, 1 << 18), (T - (1 << 18) - 3, (1 << 18) + 3)):
+        _compare_windowed(P, g, og, it, s0, n, offsets=off)
+
+
+@pytest.mark.parametrize("it", [0, 29])
+def test_windowed_sampling_bitexact_chromosome(P, chromosome, it):
+    # full size, in the launch shape the benchmark times: start, middle and ragged end of the slots
+    sg, og, g = chromosome
+    T = 10 * og.S
+    off = O.window_offsets(og, it, threads=16)
+    for s0, n in ((0, 1 << 20), (T // 2 + 12345, 1 << 20), (T - (1 << 20) - 5, (1 << 20) + 5)):
+        _compare_windowed(P, g, og, it, s0, n, offsets=off)
+
+
+# ---------------------------------------------------------------------------
 # Data-reuse variant (DRF, SRF)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("it", [0, 20])
@@ -196,8 +246,8 @@ def test_reuse_off_is_the_plain_layout(P, tiny):
     c0 = O.init_coords(og)
     a = torch.from_numpy(c0).cuda()
     b = torch.from_numpy(c0).cuda()
-    P.layout(g, a, max_inflight_waves=1, first_iter=0, last_iter=3)
-    P.layout(g, b, max_inflight_waves=1, first_iter=0, last_iter=3, reuse_factor=1, step_reduction=1)
+    P.layout(g, a, max_inflight_waves=1, first_iter=0, last_iter=3, schedule=1)
+    P.layout(g, b, max_inflight_waves=1, first_iter=0, last_iter=3, reuse_factor=1, step_reduction=1, schedule=1)
     assert torch.equal(a, b)
 
 
@@ -247,7 +297,7 @@ def test_collision_free_batch_matches_fp64(P, which, it, request):
     import torch
     sg, og, g = request.getfixturevalue(which)
     K = 65536
-    i, j, f = P.sample_terms(g, it, 0, K)
+    i, j, f = P.sample_terms(g, it, 0, K, schedule=1)
     gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
     keep = _collision_free(og, gi, gj, gf, K)
     assert keep.size > 1000
@@ -344,13 +394,14 @@ def test_sampled_path_stress_tracks_exact_path_stress(P):
 # ---------------------------------------------------------------------------
 # T7 + T10: full layouts
 # ---------------------------------------------------------------------------
-def test_linear_path_converges_on_gpu(P):
+@pytest.mark.parametrize("schedule", [1, 3])
+def test_linear_path_converges_on_gpu(P, schedule):
     import torch
     sg = synth.linear_path(2000)
     og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
     c0 = O.init_coords(og)
     c = torch.from_numpy(c0).cuda()
-    P.layout(g, c)
+    P.layout(g, c, schedule=schedule)
     s_gpu = P.path_stress(g, c, 100, 7)["mean"]
     co = c0.copy()
     O.layout(og, co)
@@ -358,7 +409,8 @@ def test_linear_path_converges_on_gpu(P):
     assert s_gpu < 1e-3 and s_gpu <= max(1.5 * s_ora, 1e-3)
 
 
-def test_full_layout_sps_parity_tiny(P, tiny):
+@pytest.mark.parametrize("schedule", [1, 3])
+def test_full_layout_sps_parity_tiny(P, tiny, schedule):
     import torch
     sg, og, g = tiny
     c0 = O.init_coords(og)
@@ -366,7 +418,7 @@ def test_full_layout_sps_parity_tiny(P, tiny):
     gpu, ora, gpu_sps = [], [], []
     for sd in seeds:
         c = torch.from_numpy(c0).cuda()
-        P.layout(g, c, seed=sd)
+        P.layout(g, c, seed=sd, schedule=schedule)
         cg = c.cpu().numpy()
         gpu.append(O.sps_expectation(og, cg)[0])
         gpu_sps.append(P.path_stress(g, c, 100, 7)["mean"])
@@ -374,7 +426,7 @@ def test_full_layout_sps_parity_tiny(P, tiny):
         O.layout(og, co, seed=sd)
         ora.append(O.sps_expectation(og, co)[0])
     ratio = np.mean(gpu) / np.mean(ora)
-    print(f"tiny: GPU {np.mean(gpu):.6f} oracle {np.mean(ora):.6f} ratio {ratio:.4f} "
+    print(f"tiny schedule {schedule}: GPU {np.mean(gpu):.6f} oracle {np.mean(ora):.6f} ratio {ratio:.4f} "
           f"(oracle seed spread {np.std(ora) / np.mean(ora):.4f}); GPU SPS(m=100) {np.mean(gpu_sps):.6f}")
     assert abs(ratio - 1) <= 0.03
 
@@ -387,7 +439,7 @@ def _mid_goldens():
     return out
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_full_layout_sps_parity_mid(P, mid, schedule):
     import torch
     goldens = _mid_goldens()

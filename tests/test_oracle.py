@@ -236,6 +236,125 @@ def test_power_law_partner_boundaries():
 
 
 # ---------------------------------------------------------------------------
+# T5b: the window-major enumeration (reading R18) against the plain definition
+# and the uniform law it must reproduce
+# ---------------------------------------------------------------------------
+def _windows(S):
+    sh = O.window_shift(S)
+    return sh, (S + (1 << sh) - 1) >> sh
+
+
+@pytest.mark.parametrize("S", [0, 1, 63, 64, 1000, 14416, 64 << 14, (64 << 14) - 1, 10 ** 8, 408037251, 10 ** 12])
+def test_window_shift_bounds(S):
+    sh, n = _windows(S)
+    assert 6 <= sh
+    assert n <= 32768
+    assert n >= 64 or sh == 6           # small graphs: windows down to 64 steps
+    assert sh <= 14 or _windows(S)[1] > 16384  # longer than 2^14 only when 2^14 would exceed the window cap
+
+
+def test_window_counts_are_the_histogram_of_plain_draws(tiny_oracle):
+    g = tiny_oracle
+    sh = O.window_shift(g.S)
+    T = 10 * g.S
+    for it in (0, 17):
+        i, _, _ = O.sample_terms(g, it, 0, T)
+        brute = np.bincount((i >> np.uint64(sh)).astype(np.int64), minlength=_windows(g.S)[1])
+        assert np.array_equal(O.window_counts(g, it).astype(np.int64), brute)
+        assert np.array_equal(O.window_counts(g, it, threads=3), O.window_counts(g, it))
+
+
+def test_windowed_slots_follow_their_window(tiny_synth, tiny_oracle):
+    g, sg = tiny_oracle, tiny_synth
+    sh = O.window_shift(g.S)
+    T = 10 * g.S
+    for it in (0, 15):
+        counts = O.window_counts(g, it).astype(np.int64)
+        i, j, f = O.sample_terms_windowed(g, it, 0, T)
+        w_of_slot = np.repeat(np.arange(len(counts)), counts)
+        assert np.array_equal(i.astype(np.int64) >> sh, w_of_slot), "slot step outside its window"
+        assert np.all(j < g.S)
+        assert np.all(_path_of(sg.path_off, i) == _path_of(sg.path_off, j)), "partner must lie on the same path"
+        cool = (f >> 2) & 1
+        hop = np.abs(i.astype(np.int64) - j.astype(np.int64))
+        assert np.all(hop[cool == 1] <= 1000)
+        if it >= 15:
+            assert np.all(cool == 1)
+        else:
+            assert 0.3 < cool.mean() < 0.7
+            off = np.concatenate([[0], np.cumsum(counts)])
+            for w in range(len(counts)):  # one coin per aligned 64-slot group of a window
+                cw = cool[off[w]:off[w + 1]]
+                for b in range(0, len(cw), 64):
+                    assert np.all(cw[b:b + 64] == cw[b])
+        assert abs((f & 1).mean() - 0.5) < 0.02 and abs(((f >> 1) & 1).mean() - 0.5) < 0.02
+
+
+def test_windowed_steps_are_uniform_chi_square(tiny_oracle):
+    # pooled over three iterations: 3 * 10 * S slots over S steps
+    g = tiny_oracle
+    T = 10 * g.S
+    i = np.concatenate([O.sample_terms_windowed(g, it, 0, T)[0] for it in (0, 1, 2)])
+    counts = np.bincount(i.astype(np.int64), minlength=g.S)
+    e = len(i) / g.S
+    chi2 = float(np.sum((counts - e) ** 2 / e))
+    dof = g.S - 1
+    assert abs(chi2 - dof) < 5 * math.sqrt(2 * dof)
+    # and uniform inside the windows (offsets in the full-length windows)
+    sh = O.window_shift(g.S)
+    full = i < ((g.S >> sh) << sh)
+    pos = (i[full] & np.uint64((1 << sh) - 1)).astype(np.int64)
+    c2 = np.bincount(pos, minlength=1 << sh)
+    e2 = len(pos) / (1 << sh)
+    chi2b = float(np.sum((c2 - e2) ** 2 / e2))
+    assert abs(chi2b - ((1 << sh) - 1)) < 5 * math.sqrt(2 * ((1 << sh) - 1))
+
+
+def test_windowed_slot_draw_and_counter(tiny_oracle):
+    # slot s draws Philox stream 5 at counter (s mod 2^32, s >> 32, iteration, 5 << 24 | graph_id)
+    g = tiny_oracle
+    sh = O.window_shift(g.S)
+    counts = O.window_counts(g, 4, graph_id=3).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    s0 = int(off[7]) + 60
+    i, j, f = O.sample_terms_windowed(g, 4, s0, 10, graph_id=3)
+    for k in range(10):
+        s = s0 + k
+        w = int(np.searchsorted(off, s, side="right") - 1)
+        r = O.philox([s & 0xFFFFFFFF, s >> 32, 4, (5 << 24) | 3], [24301, 0])
+        start = w << sh
+        ln = min(1 << sh, g.S - start)
+        assert int(i[k]) == start + ((int(r[0]) | (int(r[1]) << 32)) * ln >> 64)
+        lead_slot = int(off[w]) + ((s - int(off[w])) // 64) * 64
+        lead = O.philox([lead_slot & 0xFFFFFFFF, lead_slot >> 32, 4, (5 << 24) | 3], [24301, 0])
+        assert ((int(f[k]) >> 2) & 1) == ((int(lead[3]) >> 3) & 1)
+
+
+def test_windowed_layout_quality_equals_plain_on_tiny(tiny_oracle):
+    # same term distribution, another sequential order: the exact expectation of the
+    # sampled path stress after full layouts agrees within 3% (mean of 3 seeds each)
+    g = tiny_oracle
+    c0 = O.init_coords(g)
+    plain, win = [], []
+    for seed in (0, 1, 2):
+        a = c0.copy()
+        O.layout(g, a, seed=seed)
+        plain.append(O.sps_expectation(g, a)[0])
+        b = c0.copy()
+        O.layout_windowed(g, b, seed=seed)
+        win.append(O.sps_expectation(g, b)[0])
+    assert abs(np.mean(win) / np.mean(plain) - 1) < 0.03
+
+
+def test_windowed_layout_converges_on_a_linear_path():
+    n = 400
+    g = O.Graph(np.full(n, 5, np.uint32), np.array([0, n], np.uint64), np.arange(n, dtype=np.uint32))
+    c = O.init_coords(g)
+    O.layout_windowed(g, c)
+    assert O.sps_expectation(g, c)[0] < 1e-3
+
+
+# ---------------------------------------------------------------------------
 # T6: one update against the closed form (two-node example) and the gradient
 # ---------------------------------------------------------------------------
 def _two_node():
