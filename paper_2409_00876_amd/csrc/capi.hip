@@ -156,6 +156,7 @@ struct pgsgd_graph {
   uint64_t* d_lqueue = nullptr;
   uint32_t* d_lorder = nullptr;
   uint32_t* d_lsbeg = nullptr;
+  uint32_t* d_lwpath = nullptr;
 
   ~pgsgd_graph() {
     DeviceGuard g(device);
@@ -164,7 +165,7 @@ struct pgsgd_graph {
                     (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_tag,
                     (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem,
                     (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
-                    (void*)d_lsbeg})
+                    (void*)d_lsbeg, (void*)d_lwpath})
       if (p) (void)hipFree(p);
   }
 };
@@ -615,7 +616,7 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   if (g->d_lcount && g->loc_nwin == nwin && g->loc_shift == shift && g->loc_streams == streams) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
   for (void** q : {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
-                   (void**)&g->d_lorder, (void**)&g->d_lsbeg})
+                   (void**)&g->d_lorder, (void**)&g->d_lsbeg, (void**)&g->d_lwpath})
     if (*q) {
       (void)hipFree(*q);
       *q = nullptr;
@@ -626,13 +627,15 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   const uint32_t runs = kXcds * streams;
   // run of a window: the piece of its path it starts in (each path cut into
   // `runs` equal pieces); windows keep their id order inside a run
-  std::vector<uint32_t> order(nwin), sbeg(runs + 1, 0), run_of(nwin);
+  std::vector<uint32_t> order(nwin), sbeg(runs + 1, 0), run_of(nwin), wpath(nwin);
   {
     uint32_t p = 0;
     for (uint32_t w = 0; w < nwin; ++w) {
       const uint64_t st0 = (uint64_t)w << shift;
       while (p + 1 < g->n_paths && g->h_path_off[p + 1] <= st0) ++p;
       const uint64_t b = g->h_path_off[p], len = g->h_path_off[p + 1] - b;
+      const uint64_t st1 = std::min<uint64_t>(g->S, st0 + (1ull << shift));  // window [st0, st1)
+      wpath[w] = st1 <= g->h_path_off[p + 1] ? p : (p | 0x80000000u);
       const uint64_t r = len ? ((st0 - b) * runs) / len : 0;
       run_of[w] = (uint32_t)std::min<uint64_t>(r, runs - 1);
       ++sbeg[run_of[w] + 1];
@@ -652,8 +655,10 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   if ((st = dev_alloc(g, &g->d_lqueue, (size_t)runs * 16))) return st;
   if ((st = dev_alloc(g, &g->d_lorder, nwin))) return st;
   if ((st = dev_alloc(g, &g->d_lsbeg, runs + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_lwpath, nwin))) return st;
   HIP_TRY(hipMemcpy(g->d_lorder, order.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(g->d_lsbeg, sbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->d_lwpath, wpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
   HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histogram must start at zero
   return PGSGD_OK;
 }
@@ -753,6 +758,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     W.queue = g->d_lqueue;
     W.worder = g->d_lorder;
     W.sbeg = g->d_lsbeg;
+    W.wpath = g->d_lwpath;
     W.streams = streams;
     W.grab = grab;
     L.trace_i = trace_i;

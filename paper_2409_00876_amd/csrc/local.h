@@ -48,6 +48,7 @@ struct LocalLaunch {
   uint64_t* woff;          // [n_win + 1] first slot of every window (window-id order)
   const uint32_t* worder;  // [n_win] windows in region order
   const uint32_t* sbeg;    // [kXcds * streams + 1] first position in worder of every run
+  const uint32_t* wpath;   // [n_win] path holding the whole window, or bit 31 set if it spans paths
   uint64_t* xitem;         // [kXcds * streams][xstride] prefix of 64-slot groups over the windows of each run
   uint64_t* queue;         // [kXcds * streams * 16] item counters, one per run on its own 128-byte line
 };

@@ -31,6 +31,18 @@
 
 namespace pgsgd {
 
+// Loads of the read-only run metadata at wave-uniform addresses: through the
+// constant address space, so they become scalar loads (scalar cache) instead
+// of vector loads with a full memory round trip each.
+template <typename T>
+__device__ __forceinline__ T uload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  return ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32) | uniform_u32((uint32_t)v);
+}
+
 __global__ __launch_bounds__(1024) void k_local_count(LocalLaunch P) {
   extern __shared__ __align__(16) char lds[];
   uint32_t* hist = reinterpret_cast<uint32_t*>(lds);
@@ -97,11 +109,11 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
                                            const uint64_t* __restrict__ xi, uint64_t m, uint32_t& q) {
   const LayoutLaunch& L = P.L;
   const uint32_t lane = threadIdx.x & 63u;
-  while (q + 1 < nq && xi[q + 1] <= m) ++q;
-  const uint32_t w = P.worder[wb + q];
-  const uint64_t wbeg = P.woff[w];
-  const uint64_t nw = P.woff[w + 1] - wbeg;
-  const uint64_t k = (m - xi[q]) * 64 + lane;
+  while (q + 1 < nq && uniform_u64(uload(xi + q + 1)) <= m) q = uniform_u32(q + 1);
+  const uint32_t w = uniform_u32(uload(P.worder + wb + q));
+  const uint64_t wbeg = uniform_u64(uload(P.woff + w));
+  const uint64_t nw = uniform_u64(uload(P.woff + w + 1)) - wbeg;
+  const uint64_t k = (m - uniform_u64(uload(xi + q))) * 64 + lane;
   const uint64_t s = wbeg + k;  // global slot
   const uint32_t slot_c3 = (kStreamWindow << 24) | (L.c3 & 0xFFFFFFu);
   const Rand4 r = philox10((uint32_t)s, (uint32_t)(s >> 32), L.iter, slot_c3, L.k0, L.k1);
@@ -112,7 +124,9 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
   const uint64_t wlen = min((uint64_t)1 << P.win_shift, L.S - wstart);
   Term T;
   T.i = wstart + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), wlen);
-  const uint32_t p = find_path(V.off, L.path_top, T.i);
+  // the path of a window inside one path is known; a window across paths searches
+  const uint32_t wp = uniform_u32(uload(P.wpath + w));
+  const uint32_t p = (wp >> 31) ? find_path(V.off, L.path_top, T.i) : wp;
   const uint64_t start = V.off[p];
   const uint64_t len = V.off[p + 1] - start;
   bool ok = true;
@@ -157,10 +171,10 @@ __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
   for (uint32_t x = blockIdx.x % nx; x < kXcds; x += nx)
   for (uint32_t h = 0; h < P.streams; ++h) {
     const uint32_t run = x * P.streams + (v + h) % P.streams;
-    const uint32_t wb = P.sbeg[run];
-    const uint32_t nq = P.sbeg[run + 1] - wb;
+    const uint32_t wb = uniform_u32(uload(P.sbeg + run));
+    const uint32_t nq = uniform_u32(uload(P.sbeg + run + 1)) - wb;
     const uint64_t* __restrict__ xi = P.xitem + (size_t)run * P.xstride;
-    const uint64_t n_items = xi[nq];
+    const uint64_t n_items = uniform_u64(uload(xi + nq));
     unsigned long long* ctr = reinterpret_cast<unsigned long long*>(P.queue + (size_t)run * 16);
     uint32_t q = 0;
     for (uint64_t m = 0, m_end = 0;; ++m) {
