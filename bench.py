@@ -194,8 +194,10 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
 
 def form_batched(n_graphs: int = 24, scale: float = 1.0) -> dict:
     """Batched form: the uneven chromosome-like graphs laid out by one captured
-    HIP graph of persistent launches, against sequential plain runs of the same
-    graphs on the same GPU, compared at equal sampled path stress (per graph)."""
+    HIP graph (default schedule: every graph's windowed kernels, spread over
+    the autotuned number of concurrent branches), against sequential
+    single-graph layouts of the same graphs on the same GPU, compared at equal
+    sampled path stress (per graph)."""
     import torch
     import synth
     import paper_2409_00876_amd as P
@@ -223,7 +225,7 @@ def form_batched(n_graphs: int = 24, scale: float = 1.0) -> dict:
     tune = P.autotune(gs, cs, use_cache=False)
     note(f"tune {tune}")
     terms = 30 * 10 * sum(g.n_steps for g in gs)
-    # sequential plain runs
+    # sequential single-graph runs
     for g, c in zip(gs, cs):
         P.init_coords(g, c)
     torch.cuda.synchronize()

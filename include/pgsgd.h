@@ -316,8 +316,7 @@ pgsgd_status pgsgd_adam_step(float *x, const float *grad, float *m, float *v, ui
                              float beta2, float eps, uint32_t t, void *stream);
 
 /* ------------------------------------------------------------------------- */
-/* Batched form: many graphs in one persistent, graph-captured launch per    */
-/* iteration                                                                  */
+/* Batched form: many graphs laid out by one captured HIP graph              */
 /* ------------------------------------------------------------------------- */
 typedef struct {
   uint32_t block_threads;   /* 64..1024, multiple of 64 */
@@ -327,20 +326,31 @@ typedef struct {
   uint32_t phases;          /* work-item order, 1..64: 1 = graph after graph (fastest on MI355X: the
                                coordinates of the graph in progress stay in the Infinity Cache);
                                R > 1 interleaves the graphs in R phases (updates spread over graphs) */
+  uint32_t branches;        /* windowed batches: graphs laid out concurrently, 0..16 (0 = 4) */
 } pgsgd_tune;
 
 typedef struct pgsgd_batch pgsgd_batch;
 
 /*
- * Prepares a batched layout of n graphs (all on the same device) in the work
- * order of tune->phases.  Graph k uses
- * p->graph_id + k as its graph_id (so its terms equal those of a plain
- * pgsgd_layout with that graph_id) and its own schedule from its own d_max
- * when p->eta_max <= 0.  coords[k] is graph k's coordinate buffer (device).
- * The n_iters launches are captured once in a HIP graph.  tune = NULL picks
- * defaults (256 threads, 1 group per item, 2 blocks per CU, 1 phase).  The
- * sampled terms do not depend on tune.  max_inflight_waves is
- * ignored (the persistent grid sets the concurrency).
+ * Prepares a batched layout of n graphs (all on the same device).  Graph k
+ * uses p->graph_id + k as its graph_id (so its terms equal those of a
+ * pgsgd_layout of that graph with that graph_id and the same schedule) and
+ * its own learning-rate schedule from its own d_max when p->eta_max <= 0.
+ * coords[k] is graph k's coordinate buffer (device).  The iterations are
+ * captured once in a HIP graph.  p->schedule (resolved as for pgsgd_layout)
+ * selects the form:
+ *   WINDOWED  every graph runs its own windowed kernels, with its own wave cap
+ *             (max_inflight_waves or automatic); the graphs are spread over
+ *             tune->branches concurrent branches of the HIP graph (longest
+ *             first, each to the least loaded branch), a branch laying out
+ *             its graphs one after another.  Only tune->branches is used.
+ *   PLAIN     one persistent launch per iteration covers the terms of all
+ *             graphs, in the work order of tune->phases (block_threads,
+ *             groups_per_item, blocks_per_cu, max_blocks, phases are used;
+ *             max_inflight_waves is ignored).
+ * tune = NULL picks defaults (4 branches; 256 threads, 1 group per item, 2
+ * blocks per CU, 1 phase).  The sampled terms do not depend on tune.  The
+ * data-reuse variant and the BINNED schedule are rejected (INVALID_ARG).
  */
 pgsgd_status pgsgd_batch_create(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
                                 float *const *coords, const pgsgd_tune *tune, pgsgd_batch **out);
@@ -353,8 +363,10 @@ pgsgd_status pgsgd_layout_batched(pgsgd_graph *const *graphs, uint32_t n, const 
                                   float *const *coords, const pgsgd_tune *tune, void *stream);
 /*
  * Times candidate tunings on one iteration of the batch (on scratch copies of
- * the coordinates, which are left unchanged) and writes the fastest to *best.
- * On entry best->max_blocks is a grid cap kept in every candidate (0 = none).
+ * the coordinates, which are left unchanged) and writes the fastest to *best:
+ * for the windowed form 1, 2, 3, 4, 6 or 8 branches, for the plain form the
+ * persistent kernel's shape.  On entry best->max_blocks is a grid cap kept in
+ * every plain candidate (0 = none).
  * ms_out (host, may be NULL) receives the best time.  Synchronous.
  */
 pgsgd_status pgsgd_autotune_batched(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
@@ -365,8 +377,10 @@ pgsgd_status pgsgd_autotune_batched(pgsgd_graph *const *graphs, uint32_t n, cons
  * recording mode that writes every sampled term of graph k (t in [0,
  * terms_per_step * S_k)) to i_out[k], j_out[k], flags_out[k] (device arrays of
  * that length, flags as in pgsgd_sample_terms) instead of updating
- * coordinates.  Uses the same kernel, work mapping and tune as
- * pgsgd_batch_run.  Synchronises the stream.
+ * coordinates.  Uses the same kernels, work mapping and tune as
+ * pgsgd_batch_run (windowed form: each graph's windowed kernels; the slots
+ * of graph k in slot order).  Synchronises the stream (plain form; the
+ * windowed form records asynchronously on the stream).
  */
 pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p, uint32_t iter,
                                       const pgsgd_tune *tune, uint64_t *const *i_out, uint64_t *const *j_out,

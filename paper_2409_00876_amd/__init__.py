@@ -316,7 +316,7 @@ def _tune_c(tune) -> Tune | None:
     if isinstance(tune, Tune):
         return tune
     return Tune(int(tune["block_threads"]), int(tune["groups_per_item"]), int(tune["blocks_per_cu"]),
-                int(tune.get("max_blocks", 0)), int(tune.get("phases", 1)))
+                int(tune.get("max_blocks", 0)), int(tune.get("phases", 1)), int(tune.get("branches", 0)))
 
 
 def _graph_arrays(graphs, coords_list):
@@ -405,7 +405,7 @@ def autotune(graphs, coords_list, params: LayoutParams | None = None, use_cache:
     p = _params(params, kw)
     sig = "|".join([torch.cuda.get_device_name(graphs[0].device), str(len(graphs)),
                     str(sum(g.n_steps for g in graphs)), str(max(g.n_paths for g in graphs)),
-                    str(p.terms_per_step), str(p.zipf_window), str(max_blocks)])
+                    str(p.terms_per_step), str(p.zipf_window), str(max_blocks), str(p.schedule)])
     path = _tune_cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -417,12 +417,13 @@ def autotune(graphs, coords_list, params: LayoutParams | None = None, use_cache:
         if sig in cache:
             return dict(cache[sig], cached=True)
     gh, ch = _graph_arrays(graphs, coords_list)
-    best = Tune(0, 0, 0, int(max_blocks), 1)
+    best = Tune(0, 0, 0, int(max_blocks), 1, 0)
     ms = ctypes.c_float()
     check(lib().pgsgd_autotune_batched(gh, len(graphs), ctypes.byref(p), ch, ctypes.byref(best), ctypes.byref(ms),
                                        _stream(torch, f"cuda:{graphs[0].device}")))
     res = {"block_threads": best.block_threads, "groups_per_item": best.groups_per_item,
            "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks, "phases": best.phases,
+           "branches": best.branches,
            "ms": ms.value}
     if use_cache:
         cache[sig] = res

@@ -80,6 +80,7 @@ class Tune(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_uint32),
         ("max_blocks", ctypes.c_uint32),
         ("phases", ctypes.c_uint32),
+        ("branches", ctypes.c_uint32),
     ]
 
 

@@ -47,6 +47,9 @@ struct BatchLaunch {
   uint32_t phases;             // work-item phases (see batch_kernels.hip)
 };
 
+constexpr uint32_t kMaxBranches = 16;  // windowed batches: concurrent branches of the HIP graph
+constexpr uint32_t kAutoBranches = 4;
+
 size_t batch_lds_bytes(uint32_t n_graphs, uint32_t phases, uint32_t path_slots_total, uint32_t W);
 hipError_t launch_layout_batch(const BatchLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 const void* layout_batch_kernel();

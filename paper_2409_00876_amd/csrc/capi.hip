@@ -692,6 +692,43 @@ pgsgd_status local_grid(pgsgd_graph* g, const pgsgd_params* p, size_t lds, uint3
   return PGSGD_OK;
 }
 
+// Scratch, grid and launch arguments of the windowed schedule for graph g
+// (L: the sampling arguments of make_layout_launch).
+pgsgd_status local_plan(pgsgd_graph* g, const pgsgd_params* p, size_t lds, const LayoutLaunch& L, hipStream_t s,
+                        LocalLaunch* W, uint32_t* blocks, uint32_t* threads) {
+  pgsgd_status st;
+  if ((st = ensure_local(g, kLocalStreams, s))) return st;
+  if ((st = local_grid(g, p, lds, blocks, threads))) return st;
+  *W = LocalLaunch{};
+  W->L = L;
+  W->n_win = g->loc_nwin;
+  W->win_shift = g->loc_shift;
+  W->count_blocks = (uint32_t)g->n_cu * 2;
+  W->xstride = g->loc_xstride;
+  W->wcount = g->d_lcount;
+  W->woff = g->d_loff;
+  W->xitem = g->d_lxitem;
+  W->queue = g->d_lqueue;
+  W->worder = g->d_lorder;
+  W->sbeg = g->d_lsbeg;
+  W->wpath = g->d_lwpath;
+  W->streams = kLocalStreams;
+  W->grab = kLocalGrab;
+  return PGSGD_OK;
+}
+
+// One windowed iteration (W.L.iter, cool_all and eta set): counts and
+// offsets, run counters cleared, layout.  With e_mid set, an event is recorded
+// between the counting and the layout kernel.
+hipError_t local_iteration(const LocalLaunch& W, uint32_t blocks, uint32_t threads, hipStream_t s,
+                           hipEvent_t e_mid = nullptr) {
+  hipError_t e = launch_local_count_scan(W, s);
+  if (!e) e = launch_fill_u32(reinterpret_cast<uint32_t*>(W.queue), 2ull * kXcds * W.streams * 16, 0u, s);
+  if (!e && e_mid) e = hipEventRecord(e_mid, s);
+  if (!e) e = launch_layout_local(W, blocks, threads, s);
+  return e;
+}
+
 pgsgd_status bin_blocks(pgsgd_graph* g, size_t lds, uint32_t* blocks) {
   if (g->bin_blocks_per_cu <= 0) {
     int nb = 0;
@@ -745,22 +782,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   LocalLaunch W{};
   uint64_t n_chunks = 1;
   if (windowed) {
-    const uint32_t streams = kLocalStreams, grab = kLocalGrab;
-    if ((st = ensure_local(g, streams, s))) return st;
-    if ((st = local_grid(g, p, lds, &blocks, &threads))) return st;
-    W.n_win = g->loc_nwin;
-    W.win_shift = g->loc_shift;
-    W.count_blocks = (uint32_t)g->n_cu * 2;
-    W.xstride = g->loc_xstride;
-    W.wcount = g->d_lcount;
-    W.woff = g->d_loff;
-    W.xitem = g->d_lxitem;
-    W.queue = g->d_lqueue;
-    W.worder = g->d_lorder;
-    W.sbeg = g->d_lsbeg;
-    W.wpath = g->d_lwpath;
-    W.streams = streams;
-    W.grab = grab;
+    if ((st = local_plan(g, p, lds, L, s, &W, &blocks, &threads))) return st;
     L.trace_i = trace_i;
     L.trace_j = trace_j;
     L.trace_f = trace_f;
@@ -816,10 +838,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     if (iter_ms) HIP_TRY(hipEventRecord(ev[e0], s));
     if (windowed) {
       W.L = L;
-      HIP_TRY(launch_local_count_scan(W, s));
-      HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(W.queue), 2ull * kXcds * W.streams * 16, 0u, s));
-      if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1], s));
-      HIP_TRY(launch_layout_local(W, blocks, threads, s));
+      HIP_TRY(local_iteration(W, blocks, threads, s, iter_ms ? ev[e0 + 1] : nullptr));
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
     } else if (binned) {
       for (uint64_t c = 0; c < n_chunks; ++c) {
@@ -1114,6 +1133,14 @@ struct pgsgd_batch {
   std::vector<uint64_t> n_nodes;
   uint32_t blocks = 0;
   uint64_t total_terms = 0;
+  // windowed form: per graph its launch arguments, grid and schedule; the
+  // graphs run on `branches` concurrent branches of the captured HIP graph
+  bool windowed = false;
+  std::vector<pgsgd_graph*> graphs;
+  std::vector<LocalLaunch> wl;
+  std::vector<uint32_t> wblocks, wthreads;
+  std::vector<std::vector<float>> weta;
+  std::vector<std::vector<uint32_t>> branch_graphs;
 
   ~pgsgd_batch() {
     DeviceGuard g(device);
@@ -1134,6 +1161,130 @@ pgsgd_status check_tune(const pgsgd_tune* t) {
   if (t->groups_per_item < 1) return fail(PGSGD_ERR_INVALID_ARG, "tune.groups_per_item must be >= 1");
   if (t->blocks_per_cu < 1) return fail(PGSGD_ERR_INVALID_ARG, "tune.blocks_per_cu must be >= 1");
   if (t->phases < 1 || t->phases > 64) return fail(PGSGD_ERR_INVALID_ARG, "tune.phases must be in [1, 64]");
+  if (t->branches > kMaxBranches) return fail(PGSGD_ERR_INVALID_ARG, "tune.branches must be at most %u", kMaxBranches);
+  return PGSGD_OK;
+}
+
+// Graphs of a windowed batch per concurrent branch: longest first, each to
+// the branch with the fewest steps so far.
+std::vector<std::vector<uint32_t>> assign_branches(pgsgd_graph* const* graphs, uint32_t n, uint32_t nb) {
+  std::vector<uint32_t> order(n);
+  for (uint32_t k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return graphs[a]->S > graphs[b]->S; });
+  std::vector<std::vector<uint32_t>> out(nb);
+  std::vector<uint64_t> load(nb, 0);
+  for (uint32_t k : order) {
+    const uint32_t j = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    out[j].push_back(k);
+    load[j] += graphs[k]->S;
+  }
+  return out;
+}
+
+// The windowed batch: every graph keeps its own windowed plan (graph_id + k);
+// with capture, one HIP graph runs the branches concurrently, each branch its
+// graphs one after another (work copy in, all iterations, work copy out).
+pgsgd_status batch_build_windowed(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p,
+                                  float* const* coords, const pgsgd_tune& t, bool capture, pgsgd_batch** out) {
+  const int dev = graphs[0]->device;
+  DeviceGuard guard(dev);
+  pgsgd_batch* b = new (std::nothrow) pgsgd_batch();
+  if (!b) return fail(PGSGD_ERR_OOM, "host allocation failed");
+  b->device = dev;
+  b->n_graphs = n;
+  b->tune = t;
+  b->params = *p;
+  b->windowed = true;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e) {
+    delete b;
+    return fail(PGSGD_ERR_DEVICE, "stream create: %s", hipGetErrorString(e));
+  }
+  pgsgd_status st = PGSGD_OK;
+  for (uint32_t k = 0; k < n && !st; ++k) {
+    pgsgd_graph* g = graphs[k];
+    pgsgd_params q = *p;
+    q.graph_id = p->graph_id + k;
+    q.schedule = PGSGD_SCHEDULE_WINDOWED;
+    size_t lds = 0;
+    if ((st = layout_prepare(g, &q, cs, &lds))) break;
+    LayoutLaunch L = make_layout_launch(g, &q);
+    L.t_begin = 0;
+    L.t_end = L.n_terms;
+    L.g_begin = 0;
+    L.g_end = L.n_groups;
+    LocalLaunch W;
+    uint32_t blk = 0, thr = 0;
+    if ((st = local_plan(g, &q, lds, L, cs, &W, &blk, &thr))) break;
+    std::vector<float> eta;
+    build_schedule(q.n_iters, eta_max_of(&q, g->d_max), q.eta_min, eta);
+    b->graphs.push_back(g);
+    b->wl.push_back(W);
+    b->wblocks.push_back(blk);
+    b->wthreads.push_back(thr);
+    b->weta.push_back(eta);
+    b->coords.push_back(coords[k]);
+    b->total_terms += L.n_terms;
+  }
+  if (st) {
+    (void)hipStreamDestroy(cs);
+    delete b;
+    return st;
+  }
+  const uint32_t nb = std::min<uint32_t>(t.branches ? t.branches : kAutoBranches, n);
+  b->branch_graphs = assign_branches(graphs, n, nb);
+  if (capture) {
+    const uint32_t last = p->last_iter == 0 ? p->n_iters : p->last_iter;
+    std::vector<hipStream_t> bs(nb, nullptr);
+    std::vector<hipEvent_t> join(nb, nullptr);
+    hipEvent_t fork = nullptr;
+    e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (uint32_t j = 0; j < nb && !e; ++j) {
+      e = hipStreamCreateWithFlags(&bs[j], hipStreamNonBlocking);
+      if (!e) e = hipEventCreateWithFlags(&join[j], hipEventDisableTiming);
+    }
+    bool capturing = false;
+    if (!e) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (!e) {
+      capturing = true;
+      e = hipEventRecord(fork, cs);
+    }
+    for (uint32_t j = 0; j < nb && !e; ++j) {
+      e = hipStreamWaitEvent(bs[j], fork, 0);
+      for (uint32_t k : b->branch_graphs[j]) {
+        pgsgd_graph* g = graphs[k];
+        if (!e) e = launch_to_work(coords[k], g->d_work, g->n_nodes, bs[j]);
+        for (uint32_t it = p->first_iter; it < last && !e; ++it) {
+          LocalLaunch W = b->wl[k];
+          W.L.iter = it;
+          W.L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
+          W.L.eta = b->weta[k][it];
+          e = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
+        }
+        if (!e) e = launch_from_work(g->d_work, coords[k], g->n_nodes, bs[j]);
+      }
+      if (!e) e = hipEventRecord(join[j], bs[j]);
+      if (!e) e = hipStreamWaitEvent(cs, join[j], 0);
+    }
+    if (capturing) {
+      hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+      if (!e) e = e2;
+    }
+    if (!e) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    for (uint32_t j = 0; j < nb; ++j) {
+      if (bs[j]) (void)hipStreamDestroy(bs[j]);
+      if (join[j]) (void)hipEventDestroy(join[j]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+  }
+  (void)hipStreamDestroy(cs);
+  if (e) {
+    (void)hipGetLastError();
+    delete b;
+    return fail(PGSGD_ERR_DEVICE, "windowed batch setup: %s", hipGetErrorString(e));
+  }
+  *out = b;
   return PGSGD_OK;
 }
 
@@ -1172,6 +1323,14 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
     if ((uint64_t)p->terms_per_step * graphs[k]->S >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term count >= 2^48");
     slots_total += graphs[k]->path_slots;
   }
+  if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
+    if (trace_f) return fail(PGSGD_ERR_INVALID_ARG, "internal: windowed batches record through the graph path");
+    return batch_build_windowed(graphs, n, p, coords, t, capture, out);
+  }
+  if (resolve_schedule(p) != PGSGD_SCHEDULE_PLAIN)
+    return fail(PGSGD_ERR_INVALID_ARG, "the batched form runs the windowed or the plain schedule");
+  if (p->reuse_factor > 1 || p->step_reduction > 1)
+    return fail(PGSGD_ERR_INVALID_ARG, "the batched form does not run the data-reuse variant");
   const size_t lds = batch_lds_bytes(n, t.phases, slots_total, p->zipf_window);
   if (lds > graphs[0]->lds_limit)
     return fail(PGSGD_ERR_UNSUPPORTED, "batched LDS image of %zu bytes exceeds the %zu-byte block limit", lds,
@@ -1344,6 +1503,24 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph* const* graphs, uint32_t n, co
   if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
   for (uint32_t k = 0; k < n; ++k)
     if (!i_out[k] || !j_out[k] || !flags_out[k]) return fail(PGSGD_ERR_INVALID_ARG, "trace buffer %u is NULL", k);
+  if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
+    // a windowed batch runs every graph's own windowed kernels (graph_id + k):
+    // record each graph's slots with them
+    for (uint32_t k = 0; k < n; ++k) {
+      if (!graphs[k]) return fail(PGSGD_ERR_INVALID_ARG, "graph %u is NULL", k);
+      pgsgd_params q = *p;
+      q.graph_id = p->graph_id + k;
+      q.schedule = PGSGD_SCHEDULE_WINDOWED;
+      q.first_iter = iter;
+      q.last_iter = iter + 1;
+      const uint64_t T = (uint64_t)p->terms_per_step * graphs[k]->S;
+      if (T == 0) continue;
+      if ((st = layout_impl(graphs[k], &q, nullptr, nullptr, nullptr, nullptr, stream, i_out[k], j_out[k],
+                            flags_out[k], 0, T)))
+        return st;
+    }
+    return ok();
+  }
   // the coordinates are never touched in trace mode; any aligned pointer will do
   std::vector<float*> dummy(n, reinterpret_cast<float*>(16));
   pgsgd_batch* b = nullptr;
@@ -1362,6 +1539,87 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph* const* graphs, uint32_t n, co
   return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Windowed batches: times one iteration of all graphs for 1, 2, 3, 4, 6 and 8
+// concurrent branches (launched directly, not captured) and keeps the fastest.
+pgsgd_status autotune_windowed(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p, float* const* coords,
+                               pgsgd_tune* best, float* ms_out, hipStream_t s) {
+  pgsgd_params pt = *p;
+  pt.first_iter = 0;
+  pt.last_iter = 1;
+  pgsgd_tune t0 = default_tune();
+  t0.max_blocks = best->max_blocks;
+  pgsgd_batch* b = nullptr;
+  pgsgd_status st = batch_build(graphs, n, &pt, coords, &t0, 1, false, &b);
+  if (st) return st;
+  std::vector<hipStream_t> bs(kMaxBranches, nullptr);
+  std::vector<hipEvent_t> join(kMaxBranches, nullptr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (!e) e = hipEventCreate(&e1);
+  for (uint32_t j = 0; j < kMaxBranches && !e; ++j) {
+    e = hipStreamCreateWithFlags(&bs[j], hipStreamNonBlocking);
+    if (!e) e = hipEventCreateWithFlags(&join[j], hipEventDisableTiming);
+  }
+  // the caller's coordinates are loaded into the working copies and never written back
+  for (uint32_t k = 0; k < n && !e; ++k) e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, s);
+  auto run = [&](uint32_t nb, float* ms) -> hipError_t {
+    const auto br = assign_branches(graphs, n, nb);
+    hipError_t r = hipEventRecord(e0, s);
+    for (uint32_t j = 0; j < nb && !r; ++j) {
+      r = hipStreamWaitEvent(bs[j], e0, 0);
+      for (uint32_t k : br[j]) {
+        LocalLaunch W = b->wl[k];
+        W.L.iter = 0;
+        W.L.cool_all = 0;
+        W.L.eta = b->weta[k][0];
+        if (!r) r = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
+      }
+      if (!r) r = hipEventRecord(join[j], bs[j]);
+      if (!r) r = hipStreamWaitEvent(s, join[j], 0);
+    }
+    if (!r) r = hipEventRecord(e1, s);
+    if (!r) r = hipEventSynchronize(e1);
+    if (!r && ms) r = hipEventElapsedTime(ms, e0, e1);
+    return r;
+  };
+  float best_ms = 1e30f;
+  uint32_t best_nb = 0;
+  if (!e) e = run(1, nullptr);  // warm-up
+  for (uint32_t nb : {1u, 2u, 3u, 4u, 6u, 8u}) {
+    if (e || nb > n) break;
+    float ms = 0.0f;
+    e = run(nb, &ms);
+    if (!e && ms < best_ms) {
+      best_ms = ms;
+      best_nb = nb;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  for (uint32_t j = 0; j < kMaxBranches; ++j) {
+    if (bs[j]) (void)hipStreamDestroy(bs[j]);
+    if (join[j]) (void)hipEventDestroy(join[j]);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  delete b;
+  if (e) {
+    (void)hipGetLastError();
+    return fail(PGSGD_ERR_DEVICE, "windowed tuning: %s", hipGetErrorString(e));
+  }
+  *best = t0;
+  best->branches = best_nb;
+  if (ms_out) *ms_out = best_ms;
+  return PGSGD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 pgsgd_status pgsgd_autotune_batched(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_params* p,
                                     float* const* coords, pgsgd_tune* best, float* ms_out, void* stream) {
   if (!best || !graphs || !coords || n == 0) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
@@ -1375,6 +1633,10 @@ pgsgd_status pgsgd_autotune_batched(pgsgd_graph* const* graphs, uint32_t n, cons
   // and never write them back, so the caller's buffers are left unchanged.
   for (uint32_t k = 0; k < n; ++k)
     if (!graphs[k] || !coords[k]) return fail(PGSGD_ERR_INVALID_ARG, "graph or coords %u is NULL", k);
+  if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
+    st = autotune_windowed(graphs, n, p, coords, best, ms_out, s);
+    return st ? st : ok();
+  }
   pgsgd_params pt = *p;
   pt.first_iter = 0;
   pt.last_iter = 1;

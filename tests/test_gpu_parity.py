@@ -569,12 +569,13 @@ def small_batch(P):
 
 @pytest.mark.parametrize("it", [0, 15])
 def test_batched_sampling_bitexact(P, small_batch, it):
+    # the persistent plain-order kernel
     sgs, ogs, gs = small_batch
     # default order, graph-major with small items, 7 interleaved phases with large items and a capped grid
     tunes = [None, {"block_threads": 256, "groups_per_item": 1, "blocks_per_cu": 1},
              {"block_threads": 1024, "groups_per_item": 16, "blocks_per_cu": 2, "max_blocks": 3, "phases": 7},
              {"block_threads": 512, "groups_per_item": 4, "blocks_per_cu": 1, "phases": 64}]
-    outs = [P.batch_sample_terms(gs, it, tune=t, graph_id=5) for t in tunes]
+    outs = [P.batch_sample_terms(gs, it, tune=t, graph_id=5, schedule=1) for t in tunes]
     for k, og in enumerate(ogs):
         oi, oj, of = O.sample_terms(og, it, 0, 10 * og.S, graph_id=5 + k)
         for out in outs:
@@ -591,7 +592,7 @@ def test_batched_layout_matches_plain_quality(P, small_batch):
     cb = [torch.from_numpy(c).cuda() for c in init]
     # one wave: these graphs have only 1.6K-3.9K nodes (see the automatic cap of layout())
     tune = {"block_threads": 64, "groups_per_item": 1, "blocks_per_cu": 1, "max_blocks": 1}
-    P.layout_batched(gs, cb, tune=tune, graph_id=0)
+    P.layout_batched(gs, cb, tune=tune, graph_id=0, schedule=1)
     ratios = []
     for k, (og, g) in enumerate(zip(ogs, gs)):
         co = init[k].copy()
@@ -603,6 +604,35 @@ def test_batched_layout_matches_plain_quality(P, small_batch):
     assert abs(np.mean(ratios) - 1) <= 0.03
 
 
+@pytest.mark.parametrize("it", [0, 15])
+def test_windowed_batch_sampling_bitexact(P, small_batch, it):
+    sgs, ogs, gs = small_batch
+    for t in (None, {"block_threads": 256, "groups_per_item": 1, "blocks_per_cu": 1, "branches": 3}):
+        out = P.batch_sample_terms(gs, it, tune=t, graph_id=5)
+        for k, og in enumerate(ogs):
+            oi, oj, of = O.sample_terms_windowed(og, it, 0, 10 * og.S, graph_id=5 + k)
+            i, j, f = out[k]
+            assert np.array_equal(_to_np_u64(i), oi), f"graph {k}: i differs"
+            assert np.array_equal(_to_np_u64(j), oj), f"graph {k}: j differs"
+            assert np.array_equal(f.cpu().numpy(), of), f"graph {k}: flags differ"
+
+
+@pytest.mark.parametrize("branches", [1, 3])
+def test_windowed_batch_equals_single_layouts(P, small_batch, branches):
+    # these graphs run one wave each (automatic cap), so every graph's layout is
+    # deterministic: the batch must reproduce the single-graph layouts exactly
+    import torch
+    sgs, ogs, gs = small_batch
+    init = [O.init_coords(og) for og in ogs]
+    cb = [torch.from_numpy(c).cuda() for c in init]
+    P.layout_batched(gs, cb, tune={"block_threads": 256, "groups_per_item": 1, "blocks_per_cu": 1,
+                                   "branches": branches}, graph_id=3)
+    for k, g in enumerate(gs):
+        c = torch.from_numpy(init[k]).cuda()
+        P.layout(g, c, graph_id=3 + k)
+        assert torch.equal(c, cb[k]), f"graph {k} differs from its single layout"
+
+
 def test_batch_handle_runs_and_autotune_keeps_coords(P, small_batch):
     import torch
     sgs, ogs, gs = small_batch
@@ -610,12 +640,21 @@ def test_batch_handle_runs_and_autotune_keeps_coords(P, small_batch):
     for g, c in zip(gs, cs):
         P.init_coords(g, c)
     before = [c.clone() for c in cs]
-    res = P.autotune(gs, cs, use_cache=False, max_blocks=4)
+    res = P.autotune(gs, cs, use_cache=False, max_blocks=4, schedule=1)
     assert res["block_threads"] % 64 == 0 and res["groups_per_item"] >= 1 and res["max_blocks"] == 4
     assert res["phases"] in (1, 4)
+    resw = P.autotune(gs, cs, use_cache=False)
+    assert resw["branches"] in (1, 2, 3, 4)
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(before, cs))
-    b = P.Batch(gs, cs, tune=res, first_iter=0, last_iter=2)
+    bw = P.Batch(gs, cs, tune=resw, first_iter=0, last_iter=2)
+    bw.run()
+    torch.cuda.synchronize()
+    assert any(not torch.equal(a, c) for a, c in zip(before, cs))
+    bw.close()
+    for g, c in zip(gs, cs):
+        P.init_coords(g, c)
+    b = P.Batch(gs, cs, tune=res, first_iter=0, last_iter=2, schedule=1)
     b.run()
     torch.cuda.synchronize()
     assert any(not torch.equal(a, c) for a, c in zip(before, cs))
