@@ -167,10 +167,11 @@ typedef struct {
  *            pieces, XCD x takes piece x of every path), a window at a time
  *            per XCD, so its step records and the coordinates of the nodes
  *            it visits stay in the XCD's L2.  max_inflight_waves caps the
- *            waves (automatic: about nodes_w / 40, nodes_w = 2^h * n_nodes *
- *            n_paths / S the nodes a window visits, at most the PLAIN cap,
- *            so that an XCD's in-flight terms stay below a fifth of its
- *            window's nodes).  Scratch: a few
+ *            waves (automatic: about nodes_w / 12, nodes_w = 2^h * n_nodes *
+ *            n_paths / S the nodes a window visits, at most the PLAIN cap).
+ *            Uniform-partner updates read the partner first and the window-
+ *            local endpoint after it arrived, which keeps the window in which
+ *            a concurrent update of a local node can be lost short.  Scratch: a few
  *            words per window, allocated on first use.  pgsgd_sample_terms
  *            records slots [t_begin, t_begin + count) in slot order.
  *   AUTO     WINDOWED, or PLAIN for the data-reuse variant */

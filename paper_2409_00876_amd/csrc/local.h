@@ -16,11 +16,12 @@ constexpr uint32_t kLocalMaxWindows = 32768;
 constexpr uint32_t kLocalStreams = 1;       // runs per XCD worked on at the same time
 constexpr uint32_t kLocalMaxStreams = 16;
 constexpr uint32_t kLocalGrab = 4;          // items a wave takes from its run's counter at once
-// Automatic wave cap: the in-flight terms of an XCD (waves / 8 * 64) stay
-// below about a fifth of the nodes its active window visits (more lose
-// measurably many Hogwild updates), i.e. waves <= 8 * nodes_w / 320 with
-// nodes_w ~ 2^shift * n_nodes * n_paths / S; never above the plain cap.
-constexpr uint64_t kLocalNodesPerWave = 40;  // 320 / 8
+// Automatic wave cap: waves <= nodes_w / 12, nodes_w ~ 2^shift * n_nodes *
+// n_paths / S the nodes a window visits (an XCD's in-flight terms then stay
+// below about two thirds of its window's nodes), never above the plain cap.
+// With the far-first update order of uniform-partner terms, layout quality on
+// locality-ordered graphs is flat up to this cap.
+constexpr uint64_t kLocalNodesPerWave = 12;
 
 // log2 of the window length for S steps: 2^14, halved while there would be
 // fewer than 64 windows (not below 2^6), doubled while there would be more

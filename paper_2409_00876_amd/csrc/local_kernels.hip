@@ -103,6 +103,29 @@ __global__ __launch_bounds__(1024) void k_local_scan(LocalLaunch P) {
   for (uint32_t k = k0; k < k1; ++k) P.wcount[k] = 0;
 }
 
+// The update of apply_update with the loads ordered for a window-local i
+// endpoint a and a partner b that may lie anywhere in the path (uniform
+// partners): b is read first and a only once b has arrived, so the span in
+// which a concurrent update of a (a node of the active window, where the
+// in-flight terms concentrate) can be lost is one L2 round trip instead of a
+// far memory access.  The empty asm makes the address of a depend on the
+// loaded b (no instruction is emitted).  Same arithmetic as apply_update.
+__device__ __forceinline__ void apply_update_far_first(float2* __restrict__ W, uint64_t a, uint64_t b, float d,
+                                                       float eta) {
+  const float2 pb = W[b];
+  uint32_t lo = (uint32_t)a;
+  asm volatile("" : "+v"(lo) : "v"(pb.x), "v"(pb.y));
+  a = (a & ~0xFFFFFFFFull) | lo;
+  const float2 pa = W[a];
+  const float dx = pa.x - pb.x, dy = pa.y - pb.y;
+  const float mag = sqrtf(dx * dx + dy * dy);
+  if (mag == 0.0f) return;
+  const float mu = fminf(eta / (d * d), 1.0f);
+  const float r = mu * (mag - d) / (2.0f * mag);
+  W[a] = make_float2(pa.x - r * dx, pa.y - r * dy);
+  W[b] = make_float2(pb.x + r * dx, pb.y + r * dy);
+}
+
 // The 64 slots of item m of a run (windows worder[wb], worder[wb + 1], ...);
 // q is the calling wave's window cursor in the run (items only grow).
 __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
@@ -150,7 +173,8 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
   uint64_t a, b;
   float d;
   if (!resolve_term(L.rec, T, a, b, d)) return;
-  apply_update(L.work, a, b, d, L.eta);
+  if (cooling) apply_update(L.work, a, b, d, L.eta);  // both endpoints in or next to the window
+  else apply_update_far_first(L.work, a, b, d, L.eta);
 }
 
 __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
