@@ -273,6 +273,24 @@ typedef struct {
 pgsgd_status pgsgd_path_stress(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
                                uint32_t graph_id, pgsgd_stress_result *out, void *stream);
 
+/* Pair modes of pgsgd_path_stress_pairs. */
+enum { PGSGD_PAIRS_UNIFORM = 0, PGSGD_PAIRS_POWER_LAW = 1 };
+
+/*
+ * pgsgd_path_stress with a choice of partner: PGSGD_PAIRS_UNIFORM is Eq. 2
+ * (pgsgd_path_stress); PGSGD_PAIRS_POWER_LAW gives pair q the same step i and
+ * draw words, and as j the power-law partner of the layout's cooling phase
+ * (direction bit 2 of word 3, hop z ~ Zipf(zipf_theta) on [1, min(zipf_window,
+ * room)] from word 2; a single-step path has none and the pair counts as
+ * skipped).  The power-law mode measures how well the layout keeps short path
+ * distances.  zipf_theta, zipf_window are read in that mode only (same limits
+ * as in pgsgd_params).  Synchronises the stream.  Errors: INVALID_ARG (unknown
+ * mode, bad Zipf parameters), UNSUPPORTED (LDS), DEVICE.
+ */
+pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
+                                     uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
+                                     pgsgd_stress_result *out, void *stream);
+
 /*
  * Path stress, Eq. 1 (Section "Path Stress"): over every path and every pair of
  * its steps i < j, the stress averaged over the endpoint combinations with

@@ -67,6 +67,7 @@ def _load():
         "or_sample_terms_windowed": ([P, u32, f64, u32, u64, u32, u32, P, u64, u64, P, P, P], None),
         "or_layout_windowed": ([P, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_sampled_path_stress": ([P, P, u32, u64, u32, P, P], None),
+        "or_sampled_path_stress_pairs": ([P, P, u32, u64, u32, u32, f64, u32, P, P], None),
         "or_sps_expectation": ([P, P, P], None),
         "or_path_stress_exact": ([P, P, P], None),
         "or_init_coords": ([P, u64, u32, f32, P], None),
@@ -275,11 +276,19 @@ def apply_terms_f32(g: Graph, eta: float, i, j, flags, coords: np.ndarray) -> in
 # ---------------------------------------------------------------------------
 # Metrics (Eq. 1, Eq. 2)
 # ---------------------------------------------------------------------------
-def sampled_path_stress(g: Graph, coords: np.ndarray, m: int = 100, seed: int = 7, graph_id: int = 0) -> dict:
+def sampled_path_stress(g: Graph, coords: np.ndarray, m: int = 100, seed: int = 7, graph_id: int = 0,
+                        pairs: str = "uniform", theta: float = 0.99, window: int = 1000) -> dict:
+    """Eq. 2 with its CI95; pairs="power_law" takes the cooling phase's partner (reading R19)."""
     coords = np.ascontiguousarray(coords, dtype=np.float32)
     out = np.zeros(6, dtype=np.float64)
     cnt = np.zeros(2, dtype=np.uint64)
-    _load().or_sampled_path_stress(g._h, _p(coords), int(m), int(seed), int(graph_id), _p(out), _p(cnt))
+    if pairs == "uniform":
+        _load().or_sampled_path_stress(g._h, _p(coords), int(m), int(seed), int(graph_id), _p(out), _p(cnt))
+    elif pairs == "power_law":
+        _load().or_sampled_path_stress_pairs(g._h, _p(coords), int(m), int(seed), int(graph_id), 1, float(theta),
+                                             int(window), _p(out), _p(cnt))
+    else:
+        raise ValueError("pairs must be 'uniform' or 'power_law'")
     return dict(mean=out[0], ci_lo=out[1], ci_hi=out[2], stddev=out[3], sum=out[4], sumsq_dev=out[5],
                 n_valid=int(cnt[0]), n_skipped=int(cnt[1]))
 

@@ -755,6 +755,55 @@ static double pair_stress(const or_graph *g, const float *coords, uint64_t i, ui
   return e * e;
 }
 
+/* Pair q with the power-law partner (reading R19): step i and the draw as in
+ * sps_pair, j the cooling phase's power-law partner of i; *ok = 0 when the path
+ * has a single step. */
+static void sps_pair_power_law(const or_graph *g, const sampler *sp, uint32_t p, uint64_t q, uint64_t *i,
+                               uint64_t *j, uint32_t *ei, uint32_t *ej, int *ok) {
+  uint32_t r[4];
+  draw(sp->seed, q, 0, STREAM_SPS, sp->graph_id, r);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+  *i = start + mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), len);
+  int skip = 0;
+  partner_power_law(g, sp, *i, start, len, r[2], r[3], j, &skip);
+  *ok = !skip;
+  *ei = r[3] & 1u;
+  *ej = (r[3] >> 1) & 1u;
+}
+
+/* Eq. 2 with uniform (mode 0) or power-law (mode 1) partners; theta and W
+ * are read in mode 1 only. */
+void or_sampled_path_stress_pairs(const or_graph *g, const float *coords, uint32_t m, uint64_t seed,
+                                  uint32_t graph_id, uint32_t mode, double theta, uint32_t W, double *out,
+                                  uint64_t *counts) {
+  sampler sp;
+  sp.zipf = NULL;
+  if (mode == 1) make_sampler(&sp, 1, theta, W, seed, graph_id);
+  double sum = 0.0, dev = 0.0, mean = 0.0;
+  uint64_t n = 0, skipped = 0;
+  for (int pass = 1; pass <= 2; ++pass) {
+    for (uint32_t p = 0; p < g->n_paths; ++p) {
+      for (uint64_t q = (uint64_t)m * g->path_off[p]; q < (uint64_t)m * g->path_off[p + 1]; ++q) {
+        uint64_t i, j; uint32_t ei, ej; int valid = 1;
+        if (mode == 1) sps_pair_power_law(g, &sp, p, q, &i, &j, &ei, &ej, &valid);
+        else sps_pair(g, seed, graph_id, p, q, &i, &j, &ei, &ej);
+        double s = valid ? pair_stress(g, coords, i, j, ei, ej, &valid) : 0.0;
+        if (pass == 1) {
+          if (valid) { sum += s; ++n; } else { ++skipped; }
+        } else if (valid) {
+          dev += (s - mean) * (s - mean);
+        }
+      }
+    }
+    if (pass == 1) mean = n ? sum / (double)n : 0.0;
+  }
+  if (sp.zipf) free((void *)sp.zipf);
+  double sd = n > 1 ? sqrt(dev / (double)(n - 1)) : 0.0;
+  double half = n ? 1.96 * sd / sqrt((double)n) : 0.0;
+  out[0] = mean; out[1] = mean - half; out[2] = mean + half; out[3] = sd; out[4] = sum; out[5] = dev;
+  counts[0] = n; counts[1] = skipped;
+}
+
 void or_sampled_path_stress(const or_graph *g, const float *coords, uint32_t m, uint64_t seed, uint32_t graph_id,
                             double *out, uint64_t *counts) {
   double sum = 0.0;

@@ -176,13 +176,20 @@ def layout_timed(g: Graph, coords, params: LayoutParams | None = None, **kw):
     return it_ms[: last - p.first_iter], main_ms[: last - p.first_iter], int(launches.value)
 
 
-def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, graph_id: int = 0) -> dict:
-    """Sampled path stress (Eq. 2) with CI95; synchronises the current stream."""
+def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, graph_id: int = 0,
+                pairs: str = "uniform", zipf_theta: float = 0.99, zipf_window: int = 1000) -> dict:
+    """Sampled path stress (Eq. 2) with CI95; synchronises the current stream.
+    pairs="power_law" takes the cooling phase's power-law partner instead of a
+    uniform one (a measure of local structure)."""
     import torch
     _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    modes = {"uniform": 0, "power_law": 1}
+    if pairs not in modes:
+        raise ValueError(f"pairs must be one of {sorted(modes)}")
     r = StressResult()
-    check(lib().pgsgd_path_stress(g.handle, ctypes.c_void_p(coords.data_ptr()), int(pairs_per_step), int(seed),
-                                  int(graph_id), ctypes.byref(r), _stream(torch, coords.device)))
+    check(lib().pgsgd_path_stress_pairs(g.handle, ctypes.c_void_p(coords.data_ptr()), int(pairs_per_step),
+                                        int(seed), int(graph_id), modes[pairs], float(zipf_theta), int(zipf_window),
+                                        ctypes.byref(r), _stream(torch, coords.device)))
     return {f[0]: getattr(r, f[0]) for f in StressResult._fields_}
 
 

@@ -19,6 +19,7 @@ ERR_OOM = -3
 ERR_DEVICE = -4
 ERR_UNSUPPORTED = -5
 SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_BINNED, SCHEDULE_WINDOWED = 0, 1, 2, 3
+PAIRS_UNIFORM, PAIRS_POWER_LAW = 0, 1
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "RANGE", -3: "OOM", -4: "DEVICE", -5: "UNSUPPORTED"}
 
 
@@ -101,6 +102,7 @@ SIGNATURES = {
     "pgsgd_layout": ([_P, _P, _P, _P], _i32),
     "pgsgd_layout_timed": ([_P, _P, _P, _P, _P, _P, _P], _i32),
     "pgsgd_path_stress": ([_P, _P, _u32, _u64, _u32, _P, _P], _i32),
+    "pgsgd_path_stress_pairs": ([_P, _P, _u32, _u64, _u32, _u32, ctypes.c_double, _u32, _P, _P], _i32),
     "pgsgd_path_stress_exact": ([_P, _P, _P, _P, _P], _i32),
     "pgsgd_stress_forward": ([_P, _P, _P, _u64, _u32, _P, _P, _P], _i32),
     "pgsgd_stress_backward": ([_P, _P, _P, _u64, _u32, _P, _P, _P, _P], _i32),

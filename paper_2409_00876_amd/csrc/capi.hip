@@ -993,24 +993,40 @@ pgsgd_status pgsgd_apply_terms(pgsgd_graph* g, float eta, const uint64_t* i, con
   return ok();
 }
 
-pgsgd_status pgsgd_path_stress(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
-                               pgsgd_stress_result* out, void* stream) {
+pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed,
+                                     uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
+                                     pgsgd_stress_result* out, void* stream) {
   if (!g || !coords || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (pair_mode > PGSGD_PAIRS_POWER_LAW) return fail(PGSGD_ERR_INVALID_ARG, "unknown pair mode %u", pair_mode);
+  if (pair_mode == PGSGD_PAIRS_POWER_LAW) {
+    if (zipf_window < 1 || zipf_window > 65535)
+      return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", zipf_window);
+    if (!(zipf_theta >= 0.0) || !std::isfinite(zipf_theta))
+      return fail(PGSGD_ERR_INVALID_ARG, "zipf_theta must be finite and >= 0");
+  }
   if (m == 0) return fail(PGSGD_ERR_INVALID_ARG, "pairs_per_step must be >= 1");
   if (graph_id >= (1u << 24)) return fail(PGSGD_ERR_INVALID_ARG, "graph_id must be < 2^24");
   if ((double)m * (double)g->S >= 18446744073709551615.0) return fail(PGSGD_ERR_RANGE, "too many pairs");
   std::memset(out, 0, sizeof(*out));
   if (g->S == 0) return ok();
-  if ((size_t)g->path_slots * 8 > g->lds_limit) return fail(PGSGD_ERR_UNSUPPORTED, "too many paths for LDS");
+  const int mode = (int)pair_mode;
+  const size_t lds = (size_t)g->path_slots * 8 +
+                     (mode == 1 ? (size_t)(zipf_window + 1) * 4 + (size_t)(kGuideSize + 1) * 2 : 0);
+  if (lds > g->lds_limit) return fail(PGSGD_ERR_UNSUPPORTED, "too many paths for LDS");
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
+  if (mode == 1) {
+    pgsgd_status st = ensure_zipf(g, zipf_theta, zipf_window, s);
+    if (st) return st;
+  }
   StressLaunch P = make_stress_launch(g, coords, kStreamSps, graph_id, seed);
   P.m = m;
   P.count = g->S;
-  HIP_TRY(launch_sps_pass(P, 1, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
+  P.W = zipf_window;
+  HIP_TRY(launch_sps_pass(P, 1, mode, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
   HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
                               g->d_mean, nullptr, nullptr, s));
-  HIP_TRY(launch_sps_pass(P, 2, g->d_mean, g->d_part_f, nullptr, nullptr, s));
+  HIP_TRY(launch_sps_pass(P, 2, mode, g->d_mean, g->d_part_f, nullptr, nullptr, s));
   HIP_TRY(launch_reduce_parts(g->d_part_f, nullptr, nullptr, kStressBlocks, g->d_out_f + 1, nullptr, nullptr,
                               nullptr, nullptr, s));
   double f[2];
@@ -1028,6 +1044,11 @@ pgsgd_status pgsgd_path_stress(pgsgd_graph* g, const float* coords, uint32_t m, 
   out->ci_lo = out->mean - half;
   out->ci_hi = out->mean + half;
   return ok();
+}
+
+pgsgd_status pgsgd_path_stress(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
+                               pgsgd_stress_result* out, void* stream) {
+  return pgsgd_path_stress_pairs(g, coords, m, seed, graph_id, PGSGD_PAIRS_UNIFORM, 0.99, 1000, out, stream);
 }
 
 pgsgd_status pgsgd_path_stress_exact(pgsgd_graph* g, const float* coords, double* mean_out, uint64_t* pairs_out,

@@ -100,7 +100,7 @@ const void* bin_layout_kernel();
 // of squared deviations from mean_dev.  Final reductions write to out.
 constexpr uint32_t kStressBlocks = 2048;
 constexpr uint32_t kStressThreads = 256;
-hipError_t launch_sps_pass(const StressLaunch& P, int pass, const double* mean_dev, double* part_f,
+hipError_t launch_sps_pass(const StressLaunch& P, int pass, int mode, const double* mean_dev, double* part_f,
                            uint64_t* part_n, uint64_t* part_skip, hipStream_t s);
 // out_f[0] = sum of part_f; out_n[0..1] = sums of part_n / part_skip;
 // if mean_out: mean_out[0] = out_f[0] / out_n[0].

@@ -62,14 +62,29 @@ __device__ __forceinline__ double stress_fp64(const float* __restrict__ X, const
 // Sampled path stress: thread-strided over steps s; step s owns pairs
 // q = m*s .. m*s+m-1, which all belong to the path of s.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, const double* __restrict__ mean_dev,
+__device__ __forceinline__ void fill_loss_lds(char* lds, const StressLaunch& P, uint64_t*& off, uint32_t*& zipf,
+                                              uint16_t*& guide);
+
+// mode 0: uniform partner in the path (Eq. 2); mode 1: the power-law partner
+// of the layout's cooling phase (same draw words; no partner in a single-step
+// path: the pair is skipped).
+__global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, int mode, const double* __restrict__ mean_dev,
                                              double* __restrict__ part_f, uint64_t* __restrict__ part_n,
                                              uint64_t* __restrict__ part_skip) {
   extern __shared__ __align__(16) char lds[];
-  uint64_t* off = reinterpret_cast<uint64_t*>(lds);
+  uint64_t* off;
+  uint32_t* zipf;
+  uint16_t* guide;
   __shared__ double red_f[16];
   __shared__ uint64_t red_n[16];
-  fill_offsets(off, P);
+  if (mode == 1) {
+    fill_loss_lds(lds, P, off, zipf, guide);
+  } else {
+    off = reinterpret_cast<uint64_t*>(lds);
+    zipf = nullptr;
+    guide = nullptr;
+    fill_offsets(off, P);
+  }
   __syncthreads();
   const double mean = pass == 2 ? mean_dev[0] : 0.0;
   const float* __restrict__ X = P.coords;
@@ -84,7 +99,15 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, const dou
       const uint64_t q = (uint64_t)P.m * s + k;
       const Rand4 r = philox10((uint32_t)q, (uint32_t)(q >> 32), 0u, P.c3, P.k0, P.k1);
       const uint64_t i = start + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), len);
-      const uint64_t j = start + mulhi32(r.r2, (uint32_t)len);
+      uint64_t j;
+      if (mode == 1) {
+        if (!partner_power_law(i, start, len, r.r2, r.r3, zipf, guide, P.W, j)) {
+          ++ns;
+          continue;
+        }
+      } else {
+        j = start + mulhi32(r.r2, (uint32_t)len);
+      }
       uint64_t a, b;
       double d;
       if (!pair_terms(P.rec, i, j, r.r3 & 1u, (r.r3 >> 1) & 1u, a, b, d)) {
@@ -356,10 +379,11 @@ static uint32_t grid_for(uint64_t n, uint32_t cap) {
   return (uint32_t)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
-hipError_t launch_sps_pass(const StressLaunch& P, int pass, const double* mean_dev, double* part_f,
+hipError_t launch_sps_pass(const StressLaunch& P, int pass, int mode, const double* mean_dev, double* part_f,
                            uint64_t* part_n, uint64_t* part_skip, hipStream_t s) {
-  hipLaunchKernelGGL(k_sps, dim3(kStressBlocks), dim3(kStressThreads), (size_t)P.path_slots * 8, s, P, pass,
-                     mean_dev, part_f, part_n, part_skip);
+  const size_t lds = mode == 1 ? loss_lds_bytes(P) : (size_t)P.path_slots * 8;
+  hipLaunchKernelGGL(k_sps, dim3(kStressBlocks), dim3(kStressThreads), lds, s, P, pass, mode, mean_dev, part_f,
+                     part_n, part_skip);
   return hipGetLastError();
 }
 

@@ -338,15 +338,16 @@ def test_collision_free_batch_matches_fp64(P, which, it, request):
 # ---------------------------------------------------------------------------
 # T9: sampled path stress of the same layout
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pairs", ["uniform", "power_law"])
 @pytest.mark.parametrize("which,m", [("tiny", 100), ("mid", 1)])
-def test_sps_equals_oracle_on_same_layout(P, which, m, request):
+def test_sps_equals_oracle_on_same_layout(P, which, m, pairs, request):
     import torch
     sg, og, g = request.getfixturevalue(which)
     rng = np.random.default_rng(1)
     c0 = O.init_coords(og)
     c0 = (c0 + rng.normal(scale=50.0, size=c0.shape)).astype(np.float32)
-    r = P.path_stress(g, torch.from_numpy(c0).cuda(), m, 7)
-    o = O.sampled_path_stress(og, c0, m, 7)
+    r = P.path_stress(g, torch.from_numpy(c0).cuda(), m, 7, pairs=pairs)
+    o = O.sampled_path_stress(og, c0, m, 7, pairs=pairs)
     assert r["n_valid"] == o["n_valid"] and r["n_skipped"] == o["n_skipped"]
     assert r["n_valid"] + r["n_skipped"] == m * og.S
     assert abs(r["sum"] - o["sum"]) <= 1e-9 * abs(o["sum"])

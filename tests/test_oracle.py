@@ -500,6 +500,54 @@ def test_stress_of_scaled_line_is_closed_form(lam):
     assert abs(O.sps_expectation(g, c)[0] - (lam - 1) ** 2) < 1e-9
 
 
+@pytest.mark.parametrize("lam", [0.5, 2.0])
+def test_power_law_pair_stress_of_scaled_line_is_closed_form(lam):
+    # every pair of a scaled straight line has stress (lam - 1)^2, whichever partner is drawn
+    n = 3000
+    lens = (np.arange(n) % 5 + 1).astype(np.uint32)
+    g = O.Graph(lens, np.array([0, n], np.uint64), np.arange(n, dtype=np.uint32))
+    pos = np.concatenate([[0], np.cumsum(lens.astype(np.int64))])
+    c = np.zeros(4 * n, np.float32)
+    c[0:2 * n:2] = lam * pos[:-1]
+    c[1:2 * n:2] = lam * pos[1:]
+    r = O.sampled_path_stress(g, c, m=3, seed=9, pairs="power_law")
+    assert r["n_valid"] + r["n_skipped"] == 3 * n
+    assert abs(r["mean"] - (lam - 1) ** 2) <= 1e-6 * (lam - 1) ** 2
+
+
+def test_power_law_pairs_on_a_doubled_line():
+    # one long path of unit nodes laid out at twice the path distance: every valid pair has
+    # stress exactly 1; skipped pairs are exactly those whose two endpoints touch (d = 0), which
+    # needs hop 1 with the facing endpoint coins, so they stay a small fraction (the partner rule
+    # itself is pinned with the layout's sampling tests)
+    n = 20000
+    g = O.Graph(np.ones(n, np.uint32), np.array([0, n], np.uint64), np.arange(n, dtype=np.uint32))
+    pos = np.arange(n + 1, dtype=np.int64)
+    c = np.zeros(4 * n, np.float32)
+    c[0:2 * n:2] = 2 * pos[:-1]
+    c[1:2 * n:2] = 2 * pos[1:]
+    r = O.sampled_path_stress(g, c, m=1, seed=3, pairs="power_law")
+    assert r["n_valid"] + r["n_skipped"] == n
+    # P(hop = 1) = 1 / H_1000(0.99) ~ 0.13, then a quarter of the coin pairs face each other
+    assert 0.02 * n < r["n_skipped"] < 0.05 * n
+    assert abs(r["mean"] - 1.0) < 1e-9
+    # single-step paths have no power-law partner: every such pair is skipped
+    g1 = O.Graph(np.array([4, 3], np.uint32), np.array([0, 1, 2], np.uint64), np.array([0, 1], np.uint32))
+    r1 = O.sampled_path_stress(g1, np.zeros(8, np.float32), m=5, seed=1, pairs="power_law")
+    assert r1["n_valid"] == 0 and r1["n_skipped"] == 10
+
+
+def test_power_law_pairs_are_local_on_a_collapsed_layout(tiny_oracle):
+    # all points at the origin: every valid pair has stress exactly 1 in both modes, and the power-law
+    # pairs (hop <= 1000 steps) skip no more pairs than there are single-step paths allow
+    g = tiny_oracle
+    c = np.zeros(4 * g.n_nodes, np.float32)
+    for mode in ("uniform", "power_law"):
+        r = O.sampled_path_stress(g, c, m=2, seed=4, pairs=mode)
+        assert r["n_valid"] + r["n_skipped"] == 2 * g.S
+        assert abs(r["mean"] - 1.0) < 1e-12
+
+
 def test_two_node_path_stress_by_hand():
     # A (len 3) then B (len 2); layout: A.s=(0,0) A.e=(3,0) B.s=(3,4) B.e=(6,4)
     g = _two_node()
