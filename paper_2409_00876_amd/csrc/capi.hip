@@ -23,6 +23,7 @@
 #include "batch.h"
 #include "device.h"
 #include "internal.h"
+#include "stress.h"
 #include "local.h"
 
 using namespace pgsgd;

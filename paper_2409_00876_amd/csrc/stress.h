@@ -1,0 +1,53 @@
+// Stress kernels (sampled path stress, exact path stress, differentiable loss)
+// and the utility kernels of stress_kernels.hip: launch arguments and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace pgsgd {
+
+struct StressLaunch {
+  const StepRec* rec;
+  const float* coords;
+  const uint64_t* path_off;
+  const uint32_t* zipf;
+  const uint16_t* guide;
+  uint64_t n_nodes;
+  uint64_t S;
+  uint64_t count;          // steps (SPS) or pairs (loss)
+  uint32_t m;              // SPS pairs per step
+  uint32_t n_paths;
+  uint32_t path_slots;
+  uint32_t path_top;
+  uint32_t W;
+  uint32_t word2;          // counter word 2
+  uint32_t c3;
+  uint32_t k0, k1;
+};
+
+// SPS: pass 1 writes per-block (sum, n_valid, n_skipped); pass 2 per-block sum
+// of squared deviations from mean_dev.  Final reductions write to out.
+constexpr uint32_t kStressBlocks = 2048;
+constexpr uint32_t kStressThreads = 256;
+hipError_t launch_sps_pass(const StressLaunch& P, int pass, int mode, const double* mean_dev, double* part_f,
+                           uint64_t* part_n, uint64_t* part_skip, hipStream_t s);
+// out_f[0] = sum of part_f; out_n[0..1] = sums of part_n / part_skip;
+// if mean_out: mean_out[0] = out_f[0] / out_n[0].
+hipError_t launch_reduce_parts(const double* part_f, const uint64_t* part_n, const uint64_t* part_skip,
+                               uint32_t n_parts, double* out_f, uint64_t* out_n, double* mean_out,
+                               float* loss_out, uint64_t* n_valid_out, hipStream_t s);
+hipError_t launch_path_stress_exact(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
+hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
+hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,
+                             hipStream_t s);
+hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, uint32_t k0,
+                              uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s);
+hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, uint64_t* first_step,
+                              hipStream_t s);
+hipError_t launch_adam(float* x, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
+
+}  // namespace pgsgd

@@ -8,6 +8,7 @@
 // order, so results are deterministic for a given launch shape.
 #include "device.h"
 #include "internal.h"
+#include "stress.h"
 
 namespace pgsgd {
 
