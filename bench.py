@@ -50,12 +50,13 @@ def counters_file(kernel: str) -> str:
 
 def profile_commands(schedule: str) -> str:
     opt = "" if schedule == "windowed" else f" --schedule {schedule}"
-    return f"""rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline{opt}
-rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o fetch -- python3 bench.py --profile{opt}
-rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o write -- python3 bench.py --profile{opt}
-rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d gpurun_out/prof_tcc -o tcc -- python3 bench.py --profile{opt}
-rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d gpurun_out/prof_rdreq -o rdreq -- python3 bench.py --profile{opt}
-python3 bench.py --summarize gpurun_out/prof_trace gpurun_out/prof_fetch/fetch_counter_collection.csv gpurun_out/prof_write/write_counter_collection.csv gpurun_out/prof_tcc/tcc_counter_collection.csv gpurun_out/prof_rdreq/rdreq_counter_collection.csv{opt}"""
+    d = f"gpurun_out/prof_{schedule}"
+    return f"""rocprofv3 --kernel-trace --stats -f csv -d {d}/trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline{opt}
+rocprofv3 --pmc FETCH_SIZE -f csv -d {d}/fetch -o fetch -- python3 bench.py --profile{opt}
+rocprofv3 --pmc WRITE_SIZE -f csv -d {d}/write -o write -- python3 bench.py --profile{opt}
+rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d {d}/tcc -o tcc -- python3 bench.py --profile{opt}
+rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d {d}/rdreq -o rdreq -- python3 bench.py --profile{opt}
+python3 bench.py --summarize {d}/trace {d}/fetch/fetch_counter_collection.csv {d}/write/write_counter_collection.csv {d}/tcc/tcc_counter_collection.csv {d}/rdreq/rdreq_counter_collection.csv{opt}"""
 
 
 def kernel_source_hash(kernel: str) -> str:

@@ -201,6 +201,23 @@ def test_windowed_sampling_edge_graph(P):
         _compare_windowed(P, g, og, it, 0, 10 * og.S)
 
 
+def test_windowed_sampling_many_short_paths(P):
+    # 3,000 paths of 1-9 steps (windows of 2^8 steps span dozens of paths and take the
+    # path search), plus empty paths, and S not a multiple of the window
+    rng = np.random.default_rng(12)
+    n_nodes = 5000
+    lens = rng.integers(0, 10, size=3000)
+    steps = [[int(x) | (synth.REV_BIT if rng.random() < 0.1 else 0) for x in rng.integers(0, n_nodes, size=k)]
+             for k in lens]
+    off = np.cumsum([0] + [len(p_) for p_ in steps]).astype(np.uint64)
+    node_len = rng.integers(1, 30, size=n_nodes).astype(np.uint32)
+    sg = synth.SynthGraph(node_len, off, np.array([x for p_ in steps for x in p_], np.uint32), {}, "short")
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    assert og.S % (1 << O.window_shift(og.S)) != 0
+    for it in (0, 20):
+        _compare_windowed(P, g, og, it, 0, 10 * og.S)
+
+
 @pytest.mark.parametrize("it", [0, 15])
 def test_windowed_sampling_bitexact_mid(P, mid, it):
     sg, og, g = mid
