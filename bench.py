@@ -521,13 +521,14 @@ def main():
         traffic = None
 
     sps = P.path_stress(g, coords, pairs_per_step=10, seed=7)
+    # a stored oracle layout of this workload and seed (sequential run preferred, else the Hogwild mode)
     oracle_sps = None
-    gold = os.path.join(ROOT, "tests", "golden", f"oracle_sps_{a.workload}_seed{params.seed}_t16.json")
-    for cand in (gold, gold.replace("_t16", "_t1")):
-        if os.path.exists(cand):
-            with open(cand) as f:
-                oracle_sps = json.load(f)
-            break
+    import glob
+    golds = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"oracle_sps_{a.workload}_seed{params.seed}_t*.json")),
+                   key=lambda f: (not f.endswith("_t1.json"), f))
+    if golds:
+        with open(golds[0]) as f:
+            oracle_sps = json.load(f)
 
     rec = {
         "metric": "PG-SGD term updates/s + HBM GB/s at equal sampled path stress vs CPU oracle",
@@ -557,7 +558,8 @@ def main():
                      "iteration_frac": ALG_BYTES_PER_TERM * T / (avg_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "sps": {"mean": sps["mean"], "ci_lo": sps["ci_lo"], "ci_hi": sps["ci_hi"], "pairs_per_step": 10,
                 "oracle_mean": oracle_sps["sps_mean"] if oracle_sps else None,
-                "ratio_to_oracle": sps["mean"] / oracle_sps["sps_mean"] if oracle_sps else None},
+                "ratio_to_oracle": sps["mean"] / oracle_sps["sps_mean"] if oracle_sps else None,
+                "oracle_mode": oracle_sps.get("mode") if oracle_sps else None},
     }
     if traffic is not None:
         rec["roofline"]["traffic_frac"] = traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
