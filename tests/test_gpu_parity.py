@@ -201,6 +201,22 @@ def test_windowed_sampling_edge_graph(P):
         _compare_windowed(P, g, og, it, 0, 10 * og.S)
 
 
+def test_windowed_split_run_equals_full_run(P, tiny):
+    # one wave (automatic cap on tiny) makes the windowed layout deterministic: iterations
+    # [0, 7) + [7, 19) + [19, 30) in three calls (each counting ahead on the second stream)
+    # must give exactly the coordinates of one call over [0, 30)
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    a = torch.from_numpy(c0).cuda()
+    b = torch.from_numpy(c0).cuda()
+    P.layout(g, a, schedule=3)
+    for lo, hi in ((0, 7), (7, 19), (19, 30)):
+        P.layout(g, b, schedule=3, first_iter=lo, last_iter=hi)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_windowed_sampling_many_short_paths(P):
     # 3,000 paths of 1-9 steps (windows of 2^8 steps span dozens of paths and take the
     # path search), plus empty paths, and S not a multiple of the window
