@@ -63,9 +63,9 @@ def _load():
         "or_layout_reuse": ([P, u32, u32, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_apply_terms_f32": ([P, f64, P, P, P, u64, P], u64),
         "or_window_shift": ([u64], u32),
-        "or_window_counts": ([P, u64, u32, u32, u32, P, u32], None),
+        "or_window_counts": ([P, u64, u32, u32, u64, P, u32], None),
         "or_sample_terms_windowed": ([P, u32, f64, u32, u64, u32, u32, P, u64, u64, P, P, P], None),
-        "or_layout_windowed": ([P, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
+        "or_layout_windowed": ([P, u32, u32, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_sampled_path_stress": ([P, P, u32, u64, u32, P, P], None),
         "or_sampled_path_stress_pairs": ([P, P, u32, u64, u32, u32, f64, u32, P, P], None),
         "or_sps_expectation": ([P, P, P], None),
@@ -217,27 +217,35 @@ def window_shift(S: int) -> int:
     return int(_load().or_window_shift(int(S)))
 
 
-def window_counts(g: Graph, iter: int, terms_per_step=10, seed=24301, graph_id=0, threads=1) -> np.ndarray:
-    """Terms of iteration `iter` per window: the plain step draws counted by window
-    (`threads` host threads count disjoint term ranges; the sum is exact)."""
+def window_slots(g: Graph, terms_per_step=10, step_reduction=1) -> int:
+    """Slots of an iteration: ceil(terms_per_step * S / step_reduction)."""
+    return (terms_per_step * g.S + step_reduction - 1) // step_reduction
+
+
+def window_counts(g: Graph, iter: int, terms_per_step=10, seed=24301, graph_id=0, threads=1,
+                  step_reduction=1) -> np.ndarray:
+    """Slots of iteration `iter` per window: the plain step draws t < window_slots()
+    counted by window (`threads` host threads count disjoint term ranges; the sum is exact)."""
     sh = window_shift(g.S)
     c = np.zeros((g.S + (1 << sh) - 1) >> sh, dtype=np.uint64)
-    _load().or_window_counts(g._h, int(seed), int(graph_id), int(iter), int(terms_per_step), _p(c), int(threads))
+    _load().or_window_counts(g._h, int(seed), int(graph_id), int(iter),
+                             int(window_slots(g, terms_per_step, step_reduction)), _p(c), int(threads))
     return c
 
 
-def window_offsets(g: Graph, iter: int, terms_per_step=10, seed=24301, graph_id=0, threads=1) -> np.ndarray:
-    """First slot of every window (and T at the end)."""
-    c = window_counts(g, iter, terms_per_step, seed, graph_id, threads)
+def window_offsets(g: Graph, iter: int, terms_per_step=10, seed=24301, graph_id=0, threads=1,
+                   step_reduction=1) -> np.ndarray:
+    """First slot of every window (and the slot count at the end)."""
+    c = window_counts(g, iter, terms_per_step, seed, graph_id, threads, step_reduction)
     return np.concatenate([np.zeros(1, np.uint64), np.cumsum(c, dtype=np.uint64)])
 
 
 def sample_terms_windowed(g: Graph, iter: int, s_begin: int, count: int, n_iters=30, terms_per_step=10, theta=0.99,
-                          window=1000, seed=24301, graph_id=0, offsets=None, threads=1):
-    """Terms of the window-major enumeration, slots [s_begin, s_begin + count) (below T);
-    `offsets` from window_offsets() for the same iteration, computed here if absent."""
+                          window=1000, seed=24301, graph_id=0, offsets=None, threads=1, step_reduction=1):
+    """Terms of the window-major enumeration, slots [s_begin, s_begin + count) (below the slot
+    count); `offsets` from window_offsets() for the same iteration, computed here if absent."""
     if offsets is None:
-        offsets = window_offsets(g, iter, terms_per_step, seed, graph_id, threads)
+        offsets = window_offsets(g, iter, terms_per_step, seed, graph_id, threads, step_reduction)
     offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
     assert s_begin + count <= int(offsets[-1])
     i = np.zeros(count, dtype=np.uint64)
@@ -249,12 +257,15 @@ def sample_terms_windowed(g: Graph, iter: int, s_begin: int, count: int, n_iters
 
 
 def layout_windowed(g: Graph, coords: np.ndarray, n_iters=30, terms_per_step=10, eta_max=0.0, eta_min=0.01,
-                    theta=0.99, window=1000, seed=24301, graph_id=0, first_iter=0, last_iter=0) -> int:
-    """The layout loop with the window-major enumeration, sequentially."""
+                    theta=0.99, window=1000, seed=24301, graph_id=0, first_iter=0, last_iter=0, reuse_factor=1,
+                    step_reduction=1) -> int:
+    """The layout loop with the window-major enumeration, sequentially (with
+    reuse_factor > 1 or step_reduction > 1: the data-reuse variant on it)."""
     assert coords.dtype == np.float32 and coords.flags.c_contiguous and coords.size == 4 * g.n_nodes
-    return int(_load().or_layout_windowed(g._h, int(n_iters), int(terms_per_step), float(eta_max), float(eta_min),
-                                          float(theta), int(window), int(seed), int(graph_id), int(first_iter),
-                                          int(last_iter), _p(coords)))
+    return int(_load().or_layout_windowed(g._h, int(n_iters), int(terms_per_step), int(reuse_factor),
+                                          int(step_reduction), float(eta_max), float(eta_min), float(theta),
+                                          int(window), int(seed), int(graph_id), int(first_iter), int(last_iter),
+                                          _p(coords)))
 
 
 def apply_terms_f64(g: Graph, eta: float, i, j, flags, coords64: np.ndarray) -> int:

@@ -622,10 +622,10 @@ static void *count_worker(void *arg) {
 
 /* The counts n_w; `threads` threads count contiguous term ranges into their
  * own histograms, which are then summed (the same integers for any count). */
-void or_window_counts(const or_graph *g, uint64_t seed, uint32_t graph_id, uint32_t iter, uint32_t terms_per_step,
+void or_window_counts(const or_graph *g, uint64_t seed, uint32_t graph_id, uint32_t iter, uint64_t T,
                       uint64_t *counts, uint32_t threads) {
   uint32_t sh = or_window_shift(g->S);
-  uint64_t n_win = (g->S + (1ull << sh) - 1) >> sh, T = (uint64_t)terms_per_step * g->S;
+  uint64_t n_win = (g->S + (1ull << sh) - 1) >> sh;
   if (threads < 1) threads = 1;
   count_job *jobs = (count_job *)calloc(threads, sizeof(count_job));
   pthread_t *tid = (pthread_t *)calloc(threads, sizeof(pthread_t));
@@ -656,12 +656,12 @@ static void sample_slot(const or_graph *g, const sampler *sp, uint32_t iter, uin
   term_from_step(g, sp, iter, i, r, (lead[3] >> 3) & 1u, i_out, j_out, flags);
 }
 
-static uint64_t *window_offsets(const or_graph *g, const sampler *sp, uint32_t iter, uint32_t terms_per_step,
+static uint64_t *window_offsets(const or_graph *g, const sampler *sp, uint32_t iter, uint64_t T,
                                 uint64_t *n_win_out) {
   uint32_t sh = or_window_shift(g->S);
   uint64_t n_win = (g->S + (1ull << sh) - 1) >> sh;
   uint64_t *off = (uint64_t *)malloc(sizeof(uint64_t) * (n_win + 1));
-  or_window_counts(g, sp->seed, sp->graph_id, iter, terms_per_step, off + 1, 1);
+  or_window_counts(g, sp->seed, sp->graph_id, iter, T, off + 1, 1);
   off[0] = 0;
   for (uint64_t w = 0; w < n_win; ++w) off[w + 1] += off[w];
   *n_win_out = n_win;
@@ -689,11 +689,19 @@ void or_sample_terms_windowed(const or_graph *g, uint32_t n_iters, double theta,
 }
 
 /* The layout loop of Alg. 1 with the window-major enumeration, one thread,
- * slots in order. */
-uint64_t or_layout_windowed(const or_graph *g, uint32_t n_iters, uint32_t terms_per_step, double eta_max,
-                            double eta_min, double theta, uint32_t W, uint64_t seed, uint32_t graph_id, uint32_t first,
-                            uint32_t last, float *coords) {
-  if (g->S == 0 || n_iters == 0) return 0;
+ * slots in order.  With drf > 1 or srf > 1 it is the data-reuse variant on
+ * that enumeration (reading R20): ceil(terms_per_step * S / srf) slots per
+ * iteration (counted from the plain draws t below that number); after the
+ * primary updates of an aligned 64-slot group of a window, rounds k = 1..drf-1
+ * pair slot l's i-endpoint with slot (l + o_k) mod 64's j-endpoint of the same
+ * group (both present and not skipped, steps i of the same path), o_k from
+ * Philox stream 4 at counter (the group's first slot, iteration) as in the
+ * plain variant; d_ref from the two endpoints' path coordinates, pairs with
+ * the same slot or d = 0 skipped. */
+uint64_t or_layout_windowed(const or_graph *g, uint32_t n_iters, uint32_t terms_per_step, uint32_t drf, uint32_t srf,
+                            double eta_max, double eta_min, double theta, uint32_t W, uint64_t seed, uint32_t graph_id,
+                            uint32_t first, uint32_t last, float *coords) {
+  if (g->S == 0 || n_iters == 0 || drf < 1 || drf > 16 || srf < 1) return 0;
   if (eta_max <= 0.0) eta_max = (double)g->d_max * (double)g->d_max;
   double *eta = (double *)malloc(sizeof(double) * n_iters);
   or_schedule(n_iters, eta_max, eta_min, eta);
@@ -701,20 +709,40 @@ uint64_t or_layout_windowed(const or_graph *g, uint32_t n_iters, uint32_t terms_
   make_sampler(&sp, n_iters, theta, W, seed, graph_id);
   float *X = coords, *Y = coords + 2ull * g->n_nodes;
   uint32_t sh = or_window_shift(g->S);
-  uint64_t applied = 0;
+  uint64_t T = ((uint64_t)terms_per_step * g->S + srf - 1) / srf, applied = 0;
+  uint64_t ti[64], tj[64];
+  uint32_t tf[64], o[17];
   if (last == 0 || last > n_iters) last = n_iters;
   for (uint32_t it = first; it < last; ++it) {
     uint64_t n_win;
-    uint64_t *off = window_offsets(g, &sp, it, terms_per_step, &n_win);
-    for (uint64_t w = 0; w < n_win; ++w)
-      for (uint64_t k = 0; k < off[w + 1] - off[w]; ++k) {
-        uint64_t i, j;
-        uint32_t fl;
-        sample_slot(g, &sp, it, sh, w, off[w], k, &i, &j, &fl);
-        if (fl & 8u) continue;
-        uint64_t a = 2ull * step_node_id(g, i) + (fl & 1u), b = 2ull * step_node_id(g, j) + ((fl >> 1) & 1u);
-        applied += update_f32(X, Y, a, b, term_distance(g, i, j, fl), eta[it]);
+    uint64_t *off = window_offsets(g, &sp, it, T, &n_win);
+    for (uint64_t w = 0; w < n_win; ++w) {
+      uint64_t nw = off[w + 1] - off[w];
+      for (uint64_t g0 = 0; g0 < nw; g0 += 64) {
+        uint32_t n = (uint32_t)(nw - g0 < 64 ? nw - g0 : 64);
+        for (uint32_t l = 0; l < n; ++l) {
+          sample_slot(g, &sp, it, sh, w, off[w], g0 + l, &ti[l], &tj[l], &tf[l]);
+          if (tf[l] & 8u) continue;
+          uint64_t a = 2ull * step_node_id(g, ti[l]) + (tf[l] & 1u);
+          uint64_t b = 2ull * step_node_id(g, tj[l]) + ((tf[l] >> 1) & 1u);
+          applied += update_f32(X, Y, a, b, term_distance(g, ti[l], tj[l], tf[l]), eta[it]);
+        }
+        if (drf < 2) continue;
+        reuse_offsets(&sp, it, off[w] + g0, drf, o);
+        for (uint32_t k = 1; k < drf; ++k) {
+          for (uint32_t l = 0; l < n; ++l) {
+            uint32_t m = (l + o[k]) % 64;
+            if (m >= n || (tf[l] & 8u) || (tf[m] & 8u)) continue;
+            if (path_of_step(g, ti[l]) != path_of_step(g, ti[m])) continue;
+            uint32_t ei = tf[l] & 1u, ej = (tf[m] >> 1) & 1u;
+            uint64_t a = 2ull * step_node_id(g, ti[l]) + ei, b = 2ull * step_node_id(g, tj[m]) + ej;
+            int64_t d = or_endpoint_pos(g, ti[l], ei) - or_endpoint_pos(g, tj[m], ej);
+            if (a == b || d == 0) continue;
+            applied += update_f32(X, Y, a, b, d < 0 ? -d : d, eta[it]);
+          }
+        }
       }
+    }
     free(off);
   }
   free((void *)sp.zipf);

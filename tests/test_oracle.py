@@ -355,6 +355,82 @@ def test_windowed_layout_converges_on_a_linear_path():
 
 
 # ---------------------------------------------------------------------------
+# T5c: layout loops (plain, windowed, data reuse on both) against a fixed point
+# ---------------------------------------------------------------------------
+def _disjoint_paths_fixed_point():
+    """Three paths over disjoint nodes (some visited on the reverse strand), each laid out on
+    its own horizontal line at its path coordinates: every same-path pair has |v_a - v_b| = d,
+    so every update of a correct loop is zero and the layout must not move at all."""
+    rng = np.random.default_rng(5)
+    sizes = [700, 1, 450]
+    node_len, step_node, off = [], [], [0]
+    nid = 0
+    for n in sizes:
+        for _ in range(n):
+            node_len.append(int(rng.integers(1, 9)))
+            step_node.append(nid | (synth.REV_BIT if rng.random() < 0.2 else 0))
+            nid += 1
+        off.append(off[-1] + n)
+    g = O.Graph(np.array(node_len, np.uint32), np.array(off, np.uint64), np.array(step_node, np.uint32))
+    c = np.zeros(4 * nid, np.float32)
+    X, Y = c[:2 * nid], c[2 * nid:]
+    for p_, (b, e) in enumerate(zip(off[:-1], off[1:])):
+        for s_ in range(b, e):
+            node = step_node[s_] & 0x7FFFFFFF
+            for end in (0, 1):
+                X[2 * node + end] = g.endpoint_pos(s_, end)
+                Y[2 * node + end] = 1000.0 * p_
+    return g, c
+
+
+@pytest.mark.parametrize("loop", ["plain", "windowed", "reuse_plain", "reuse_windowed"])
+def test_layout_loops_keep_a_fixed_point(loop):
+    # pins d_ref (step positions, endpoint orientation), the same-path condition of reuse pairs
+    # and the update arithmetic of every loop: any wrong distance moves some point
+    g, c = _disjoint_paths_fixed_point()
+    before = c.copy()
+    if loop == "plain":
+        n = O.layout(g, c, n_iters=6)
+    elif loop == "windowed":
+        n = O.layout_windowed(g, c, n_iters=6)
+    elif loop == "reuse_plain":
+        n = O.layout_reuse(g, c, 4, 2, n_iters=6)
+    else:
+        n = O.layout_windowed(g, c, n_iters=6, reuse_factor=4, step_reduction=2)
+    assert n > 0
+    assert np.array_equal(c, before)
+
+
+def test_windowed_slot_count_with_step_reduction(tiny_oracle):
+    g = tiny_oracle
+    sh = O.window_shift(g.S)
+    for srf in (2, 3, 7):
+        T = O.window_slots(g, 10, srf)
+        assert T == -(-10 * g.S // srf)
+        i, _, _ = O.sample_terms(g, 5, 0, T)
+        brute = np.bincount((i >> np.uint64(sh)).astype(np.int64), minlength=(g.S + (1 << sh) - 1) >> sh)
+        assert np.array_equal(O.window_counts(g, 5, step_reduction=srf).astype(np.int64), brute)
+
+
+def test_reuse_offsets_follow_the_stated_draw():
+    # o_k = 1 + (byte k-1 of the words of Philox stream 4 at counter (group, 0, iter)) mod 63
+    for group, it, drf in ((0, 0, 16), (12345, 7, 5), ((1 << 33) + 9, 29, 9)):
+        o = O.reuse_offsets(it, group, drf, seed=24301, graph_id=2)
+        r = O.philox([group & 0xFFFFFFFF, group >> 32, it, (4 << 24) | 2], [24301, 0])
+        expect = [1 + ((int(r[(k - 1) // 4]) >> (8 * ((k - 1) % 4))) & 0xFF) % 63 for k in range(1, drf)]
+        assert o == expect and all(1 <= x <= 63 for x in o)
+
+
+def test_reuse_rounds_add_updates(tiny_oracle):
+    g = tiny_oracle
+    c0 = O.init_coords(g)
+    a, b = c0.copy(), c0.copy()
+    n1 = O.layout_windowed(g, a, n_iters=2, step_reduction=2)
+    n4 = O.layout_windowed(g, b, n_iters=2, reuse_factor=4, step_reduction=2)
+    assert 2.5 * n1 < n4 <= 4 * n1 + 10
+
+
+# ---------------------------------------------------------------------------
 # T6: one update against the closed form (two-node example) and the gradient
 # ---------------------------------------------------------------------------
 def _two_node():
