@@ -151,7 +151,7 @@ typedef struct {
  *            allocated on first use); the same terms as PLAIN
  *   WINDOWED window-major enumeration: the steps are cut into windows of
  *            2^h consecutive global steps (h = 14, decreased while there
- *            would be fewer than 64 windows but not below 6, increased while
+ *            would be fewer than 16 windows but not below 6, increased while
  *            there would be more than 32768); window w receives n_w slots,
  *            n_w = the number of the iteration's PLAIN step draws that fall
  *            in it (so (n_w) is multinomial(T, |w| / S)); slot s (windows in

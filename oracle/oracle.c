@@ -600,7 +600,7 @@ enum { STREAM_WINDOW = 5 };
 
 uint32_t or_window_shift(uint64_t S) {
   uint32_t sh = 14;
-  while (sh > 6 && ((S + (1ull << sh) - 1) >> sh) < 64) --sh;
+  while (sh > 6 && ((S + (1ull << sh) - 1) >> sh) < 16) --sh;
   while (((S + (1ull << sh) - 1) >> sh) > 32768) ++sh;
   return sh;
 }

@@ -11,7 +11,7 @@ namespace pgsgd {
 
 constexpr uint32_t kStreamWindow = 5;       // Philox stream of the window-slot draws
 constexpr uint32_t kLocalShift = 14;        // preferred window: 2^14 steps (about 1 MB of records and coordinates)
-constexpr uint32_t kLocalMinWindows = 64;   // smaller windows for small graphs, down to 2^6 steps
+constexpr uint32_t kLocalMinWindows = 16;   // smaller windows for small graphs, down to 2^6 steps
 constexpr uint32_t kLocalMaxWindows = 32768;
 constexpr uint32_t kLocalStreams = 1;       // runs per XCD worked on at the same time
 constexpr uint32_t kLocalMaxStreams = 16;
@@ -24,7 +24,7 @@ constexpr uint32_t kLocalGrab = 4;          // items a wave takes from its run's
 constexpr uint64_t kLocalNodesPerWave = 12;
 
 // log2 of the window length for S steps: 2^14, halved while there would be
-// fewer than 64 windows (not below 2^6), doubled while there would be more
+// fewer than 16 windows (not below 2^6), doubled while there would be more
 // than 32768.  Part of the sampling definition (the slot draws depend on it).
 inline uint32_t window_shift(uint64_t S) {
   auto n = [&](uint32_t sh) { return (S + (1ull << sh) - 1) >> sh; };

