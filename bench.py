@@ -378,7 +378,8 @@ def form_metric() -> dict:
 
 def form_reuse(workload: str = "chromosome", schemes=((1, 1), (2, 1), (2, 2), (4, 2), (4, 4))) -> dict:
     """Data-reuse variant: run time, updates/s and sampled path stress of full
-    layouts for several (DRF, SRF) schemes, against the plain loop (1, 1)."""
+    layouts for several (DRF, SRF) schemes with the plain and the windowed
+    enumeration, each against the plain loop (1, 1) of the plain schedule."""
     import torch
     import synth
     import paper_2409_00876_amd as P
@@ -386,28 +387,34 @@ def form_reuse(workload: str = "chromosome", schemes=((1, 1), (2, 1), (2, 2), (4
     g = P.Graph.from_synth(sg)
     c = g.new_coords()
     T = 10 * g.n_steps
-    rows = []
+    out = {}
     base = None
-    for drf, srf in schemes:
-        P.init_coords(g, c)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        it_ms, mk_ms, _ = P.layout_timed(g, c, reuse_factor=drf, step_reduction=srf)
-        wall = time.perf_counter() - t0
-        sps = P.path_stress(g, c, 10, 7)
-        sampled = 30 * ((T + srf - 1) // srf)
-        row = {"drf": drf, "srf": srf, "seconds": wall, "sampled_terms": sampled,
-               "updates_upper_bound": sampled * drf, "sampled_terms_per_s": sampled / wall,
-               "sps": sps["mean"], "sps_ci": [sps["ci_lo"], sps["ci_hi"]], "avg_iteration_ms": float(sum(it_ms) / 30)}
-        if base is None:
-            base = row
-        row["speedup_vs_plain"] = base["seconds"] / wall
-        row["sps_ratio_vs_plain"] = sps["mean"] / base["sps"]
-        row["quality"] = "good" if row["sps_ratio_vs_plain"] < 2 else (
-            "satisfying" if row["sps_ratio_vs_plain"] < 10 else "poor")
-        rows.append(row)
-        print(f"[reuse] {drf},{srf}: {wall:.2f} s, SPS {sps['mean']:.4g}", file=sys.stderr, flush=True)
-    return {"workload": workload, "schemes": rows}
+    for sched_name in ("plain", "windowed"):
+        rows = []
+        for drf, srf in schemes:
+            P.init_coords(g, c)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it_ms, mk_ms, _ = P.layout_timed(g, c, reuse_factor=drf, step_reduction=srf,
+                                             schedule=SCHEDULES[sched_name])
+            wall = time.perf_counter() - t0
+            sps = P.path_stress(g, c, 10, 7)
+            sampled = 30 * ((T + srf - 1) // srf)
+            row = {"drf": drf, "srf": srf, "seconds": wall, "sampled_terms": sampled,
+                   "updates_upper_bound": sampled * drf, "sampled_terms_per_s": sampled / wall,
+                   "sps": sps["mean"], "sps_ci": [sps["ci_lo"], sps["ci_hi"]],
+                   "avg_iteration_ms": float(sum(it_ms) / 30)}
+            if base is None:
+                base = row
+            row["speedup_vs_plain"] = base["seconds"] / wall
+            row["sps_ratio_vs_plain"] = sps["mean"] / base["sps"]
+            row["quality"] = "good" if row["sps_ratio_vs_plain"] < 2 else (
+                "satisfying" if row["sps_ratio_vs_plain"] < 10 else "poor")
+            rows.append(row)
+            print(f"[reuse] {sched_name} {drf},{srf}: {wall:.2f} s, SPS {sps['mean']:.4g}", file=sys.stderr,
+                  flush=True)
+        out[sched_name] = rows
+    return {"workload": workload, "schemes": out}
 
 
 def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:

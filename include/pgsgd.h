@@ -128,7 +128,8 @@ typedef struct {
 
 /* Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
  * Trade-off with Sampled Path Stress"), active when reuse_factor > 1 or
- * step_reduction > 1 (PLAIN or AUTO schedule only):
+ * step_reduction > 1, with the PLAIN or the WINDOWED schedule (BINNED is
+ * rejected).  PLAIN:
  *   - an iteration samples ceil(terms_per_step * S / step_reduction) terms in
  *     aligned groups of 64; a group's path is the path of the global step
  *     drawn by its first term (paths stay chosen with probability ∝ |p|), and
@@ -140,6 +141,12 @@ typedef struct {
  *     63, using the values already loaded (cross-lane shuffles, no new loads);
  *     d_ref is the path distance of the two endpoints; same-slot or d = 0
  *     pairs are skipped.  Each endpoint is stored once at the end.
+ * WINDOWED: ceil(terms_per_step * S / step_reduction) slots of the window-major
+ *   enumeration (counted from the plain step draws t below that number); a
+ *   group is an aligned run of 64 slots of one window, and the reuse rounds
+ *   pair lane l's i-endpoint with lane (l + o_k) mod 64's j-endpoint when both
+ *   steps i lie on the same path, o_k drawn as above at counter (the group's
+ *   first slot, 0, iter).
  * Updates per iteration: up to reuse_factor x the sampled terms. */
 
 /* Processing order of the terms of an iteration.
@@ -174,7 +181,7 @@ typedef struct {
  *            a concurrent update of a local node can be lost short.  Scratch: a few
  *            words per window, allocated on first use.  pgsgd_sample_terms
  *            records slots [t_begin, t_begin + count) in slot order.
- *   AUTO     WINDOWED, or PLAIN for the data-reuse variant */
+ *   AUTO     WINDOWED */
 enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_BINNED = 2, PGSGD_SCHEDULE_WINDOWED = 3 };
 
 /* Fills the defaults listed above (seed 24301, graph_id 0). */
@@ -425,11 +432,13 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph *g, const pgsgd_params *p, uint32_t 
                                 void *stream);
 /*
  * The data-reuse variant's terms and reuse offsets, recorded by its layout
- * kernel with the layout's launch shape: terms t in [t_begin, t_begin + count)
- * as in pgsgd_sample_terms (t_begin a multiple of 64), and, when offsets_out
- * (device, may be NULL) is given, the offsets o_1..o_{reuse_factor-1} of every
- * 64-term group of the range (reuse_factor - 1 bytes per group, in group
- * order).  Async.
+ * kernel with the layout's launch shape.  PLAIN: terms t in [t_begin, t_begin
+ * + count) as in pgsgd_sample_terms (t_begin a multiple of 64), and, when
+ * offsets_out (device, may be NULL) is given, the offsets o_1..o_{reuse_factor-1}
+ * of every 64-term group of the range (reuse_factor - 1 bytes per group, in
+ * group order).  WINDOWED: the slots of the range (below ceil(terms_per_step *
+ * S / step_reduction)) and, with offsets_out, the offsets of each slot's group
+ * (reuse_factor - 1 bytes per slot).  Async.
  */
 pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,
                                       uint64_t count, uint64_t *i_out, uint64_t *j_out, uint8_t *flags_out,

@@ -19,7 +19,8 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (GraphInfo, Params, PgsgdError, StressResult, Tune, check, lib)  # noqa: F401
+from ._lib import (SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
+                   check, lib)
 
 __all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
            "sample_terms", "sample_terms_reuse", "apply_terms", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
@@ -219,14 +220,17 @@ def sample_terms(g: Graph, iter: int, t_begin: int, count: int, params: LayoutPa
 
 def sample_terms_reuse(g: Graph, iter: int, t_begin: int, count: int, params: LayoutParams | None = None, **kw):
     """The data-reuse variant's terms (i, j, flags) and reuse offsets (uint8,
-    reuse_factor - 1 per 64-term group), recorded by its kernel."""
+    reuse_factor - 1 per 64-term group with the plain schedule, per slot with
+    the windowed one), recorded by its kernel."""
     p = _params(params, kw)
     dev = f"cuda:{g.device}"
     i = torch.empty(count, dtype=torch.int64, device=dev)
     j = torch.empty(count, dtype=torch.int64, device=dev)
     f = torch.full((count,), 255, dtype=torch.uint8, device=dev)
     n_groups = (t_begin + count + 63) // 64 - t_begin // 64
-    o = torch.zeros(max(1, n_groups * max(0, p.reuse_factor - 1)), dtype=torch.uint8, device=dev)
+    per = max(0, p.reuse_factor - 1)
+    windowed = p.schedule in (SCHEDULE_AUTO, SCHEDULE_WINDOWED)
+    o = torch.zeros(max(1, (count if windowed else n_groups) * per), dtype=torch.uint8, device=dev)
     check(lib().pgsgd_sample_terms_reuse(g.handle, ctypes.byref(p), int(iter), int(t_begin), int(count),
                                          ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
                                          ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(o.data_ptr()),

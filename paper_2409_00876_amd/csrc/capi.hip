@@ -214,9 +214,8 @@ pgsgd_status check_params(const pgsgd_params* p) {
   if (p->flags != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags must be 0");
   if (p->reuse_factor > 16) return fail(PGSGD_ERR_INVALID_ARG, "reuse_factor must be at most 16");
   if (p->schedule > PGSGD_SCHEDULE_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
-  if ((p->reuse_factor > 1 || p->step_reduction > 1) &&
-      (p->schedule == PGSGD_SCHEDULE_BINNED || p->schedule == PGSGD_SCHEDULE_WINDOWED))
-    return fail(PGSGD_ERR_INVALID_ARG, "the data-reuse variant runs with the plain schedule only");
+  if ((p->reuse_factor > 1 || p->step_reduction > 1) && p->schedule == PGSGD_SCHEDULE_BINNED)
+    return fail(PGSGD_ERR_INVALID_ARG, "the data-reuse variant runs with the plain or windowed schedule");
   if (p->zipf_window < 1 || p->zipf_window > 65535)
     return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", p->zipf_window);
   if (!(p->zipf_theta >= 0.0) || !std::isfinite(p->zipf_theta))
@@ -566,14 +565,12 @@ extern "C" {
 
 namespace {
 
-// AUTO selects WINDOWED (PLAIN for the data-reuse variant, which needs the
-// plain enumeration): on MI355X the window-major order keeps a window's
-// records and coordinates in the L2 and is 2-3x faster than PLAIN at the same
-// layout quality.  BINNED orders the plain terms by window but its binning
-// passes cost more than they save.
+// AUTO selects WINDOWED: on MI355X the window-major order keeps a window's
+// records and coordinates in the L2 and is about 3x faster than PLAIN at the
+// same layout quality.  BINNED orders the plain terms by window but its
+// binning passes cost more than they save.
 uint32_t resolve_schedule(const pgsgd_params* p) {
-  if (p->schedule != PGSGD_SCHEDULE_AUTO) return p->schedule;
-  return (p->reuse_factor > 1 || p->step_reduction > 1) ? PGSGD_SCHEDULE_PLAIN : PGSGD_SCHEDULE_WINDOWED;
+  return p->schedule != PGSGD_SCHEDULE_AUTO ? p->schedule : (uint32_t)PGSGD_SCHEDULE_WINDOWED;
 }
 
 // Binning scratch for chunks of up to min(T, kBinChunk) terms: windows of
@@ -748,7 +745,7 @@ pgsgd_status bin_blocks(pgsgd_graph* g, size_t lds, uint32_t* blocks) {
 pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms, float* main_ms,
                          uint32_t* main_launches, void* stream, uint64_t* trace_i = nullptr,
                          uint64_t* trace_j = nullptr, uint8_t* trace_f = nullptr, uint64_t trace_begin = 0,
-                         uint64_t trace_count = 0) {
+                         uint64_t trace_count = 0, uint8_t* trace_o = nullptr) {
   const bool tracing = trace_f != nullptr;
   if (!g || (!coords && !tracing)) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
   if (coords && ((uintptr_t)coords & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
@@ -787,6 +784,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     L.trace_i = trace_i;
     L.trace_j = trace_j;
     L.trace_f = trace_f;
+    L.trace_o = trace_o;
     if (tracing) {
       L.t_begin = trace_begin;
       L.t_end = trace_begin + trace_count;
@@ -911,9 +909,22 @@ pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph* g, const pgsgd_params* p, uin
   pgsgd_status st = check_params(p);
   if (st) return st;
   if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
-  if (t_begin % 64) return fail(PGSGD_ERR_INVALID_ARG, "t_begin must be a multiple of 64");
   if (t_begin + count < t_begin || t_begin + count >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term range too large");
   if (count == 0 || g->S == 0) return ok();
+  if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
+    // the windowed kernels record the slots; offsets_out gets the offsets of
+    // each recorded slot's group, reuse_factor - 1 bytes per slot
+    const uint64_t srf = p->step_reduction > 1 ? p->step_reduction : 1;
+    if (t_begin + count > ((uint64_t)p->terms_per_step * g->S + srf - 1) / srf)
+      return fail(PGSGD_ERR_INVALID_ARG, "the windowed schedule records slots of the iteration only");
+    pgsgd_params q = *p;
+    q.first_iter = iter;
+    q.last_iter = iter + 1;
+    q.schedule = PGSGD_SCHEDULE_WINDOWED;
+    return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, i_out, j_out, flags_out, t_begin, count,
+                       p->reuse_factor > 1 ? offsets_out : nullptr);
+  }
+  if (t_begin % 64) return fail(PGSGD_ERR_INVALID_ARG, "t_begin must be a multiple of 64");
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
   size_t lds;
@@ -946,7 +957,8 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t 
     // the binning (window count) kernels and the layout kernel process the
     // whole iteration; the terms (window-major slots) of [t_begin, t_begin +
     // count) are recorded
-    if (t_begin + count > (uint64_t)p->terms_per_step * g->S)
+    const uint64_t srf = p->step_reduction > 1 ? p->step_reduction : 1;
+    if (t_begin + count > ((uint64_t)p->terms_per_step * g->S + srf - 1) / srf)
       return fail(PGSGD_ERR_INVALID_ARG, "this schedule records terms of the iteration only (t < T)");
     pgsgd_params q = *p;
     q.first_iter = iter;

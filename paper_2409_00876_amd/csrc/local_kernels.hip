@@ -177,6 +177,127 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
   else apply_update_far_first(L.work, a, b, d, L.eta);
 }
 
+__device__ __forceinline__ float2 shfl_f2(float2 v, int src) {
+  return make_float2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+// The data-reuse variant on the window-major slots: the group of item m (64
+// slots of one window) makes its primary updates in registers, then rounds k =
+// 1..drf-1 pair lane l's i-endpoint with lane (l + o_k) mod 64's j-endpoint
+// (both live, unskipped, steps on the same path) through cross-lane shuffles;
+// the j-endpoint's move is shuffled back to its owner, and every endpoint is
+// stored once at the end.  o_k from Philox stream 4 at counter (the group's
+// first slot, iteration).  All lanes stay active up to the shuffles.
+__device__ __forceinline__ void local_item_reuse(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
+                                                 const uint64_t* __restrict__ xi, uint64_t m, uint32_t& q) {
+  const LayoutLaunch& L = P.L;
+  const uint32_t lane = threadIdx.x & 63u;
+  while (q + 1 < nq && uniform_u64(uload(xi + q + 1)) <= m) q = uniform_u32(q + 1);
+  const uint32_t w = uniform_u32(uload(P.worder + wb + q));
+  const uint64_t wbeg = uniform_u64(uload(P.woff + w));
+  const uint64_t nw = uniform_u64(uload(P.woff + w + 1)) - wbeg;
+  const uint64_t k0 = (m - uniform_u64(uload(xi + q))) * 64;  // the group's first slot in the window
+  const uint64_t k = k0 + lane;
+  const uint64_t s = wbeg + k;
+  const uint32_t slot_c3 = (kStreamWindow << 24) | (L.c3 & 0xFFFFFFu);
+  const Rand4 r = philox10((uint32_t)s, (uint32_t)(s >> 32), L.iter, slot_c3, L.k0, L.k1);
+  const uint32_t lead = uniform_u32(r.r3);
+  const bool cooling = L.cool_all || ((lead >> 3) & 1u);
+  const bool live = k < nw;
+  const uint64_t wstart = (uint64_t)w << P.win_shift;
+  const uint64_t wlen = min((uint64_t)1 << P.win_shift, L.S - wstart);
+  Term T;
+  T.i = wstart + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), wlen);
+  const uint32_t wp = uniform_u32(uload(P.wpath + w));
+  const uint32_t p = (wp >> 31) ? find_path(V.off, L.path_top, T.i) : wp;
+  const uint64_t start = V.off[p];
+  const uint64_t len = V.off[p + 1] - start;
+  bool ok = true;
+  if (cooling) ok = partner_power_law(T.i, start, len, r.r2, r.r3, V.zipf, V.guide, L.W, T.j);
+  else T.j = start + mulhi32(r.r2, (uint32_t)len);
+  T.flags = (r.r3 & 3u) | ((cooling ? 1u : 0u) << 2) | ((ok ? 0u : 1u) << 3);
+  bool valid = live && ok;
+  uint64_t a = 0, b = 0;
+  int64_t pa = 0, pb = 0;
+  if (valid) {
+    const StepRec si = load_rec(L.rec, T.i);
+    const StepRec sj = load_rec(L.rec, T.j);
+    const uint32_t ei = T.flags & 1u, ej = (T.flags >> 1) & 1u;
+    a = 2ull * (si.node_rev & kNodeMask) + ei;
+    b = 2ull * (sj.node_rev & kNodeMask) + ej;
+    pa = endpoint_pos(si, ei);
+    pb = endpoint_pos(sj, ej);
+    if (a == b || pa == pb) valid = false;
+  }
+  const uint32_t reuse_c3 = (4u << 24) | (L.c3 & 0xFFFFFFu);
+  const uint64_t s0 = wbeg + k0;
+  const Rand4 ro = philox10((uint32_t)s0, (uint32_t)(s0 >> 32), L.iter, reuse_c3, L.k0, L.k1);
+  const uint32_t ow[4] = {ro.r0, ro.r1, ro.r2, ro.r3};
+  if (L.trace_f) {  // parity hook: record the slots (and their groups' offsets) of [t_begin, t_end)
+    if (live && s >= L.t_begin && s < L.t_end) {
+      const uint64_t o = s - L.t_begin;
+      L.trace_i[o] = T.i;
+      L.trace_j[o] = T.j;
+      L.trace_f[o] = (uint8_t)(T.flags | (ok && !valid ? 8u : 0u));
+      if (L.trace_o)
+        for (uint32_t kk = 1; kk < L.drf; ++kk)
+          L.trace_o[o * (L.drf - 1) + kk - 1] =
+              (uint8_t)(1 + ((ow[(kk - 1) >> 2] >> (8 * ((kk - 1) & 3))) & 0xFFu) % 63);
+    }
+    return;
+  }
+  float2* __restrict__ Wc = L.work;
+  float2 A = make_float2(0.0f, 0.0f), B = make_float2(0.0f, 0.0f);
+  if (valid) {
+    if (cooling) {
+      A = Wc[a];
+      B = Wc[b];
+    } else {  // far-first: the uniform partner, then the window-local endpoint
+      B = Wc[b];
+      uint32_t lo = (uint32_t)a;
+      asm volatile("" : "+v"(lo) : "v"(B.x), "v"(B.y));
+      A = Wc[(a & ~0xFFFFFFFFull) | lo];
+    }
+    const float d = (float)(pa < pb ? pb - pa : pa - pb);
+    const float dx = A.x - B.x, dy = A.y - B.y;
+    const float mag = sqrtf(dx * dx + dy * dy);
+    if (mag != 0.0f) {
+      const float mu = fminf(L.eta / (d * d), 1.0f);
+      const float rr = mu * (mag - d) / (2.0f * mag);
+      A = make_float2(A.x - rr * dx, A.y - rr * dy);
+      B = make_float2(B.x + rr * dx, B.y + rr * dy);
+    }
+  }
+  for (uint32_t kk = 1; kk < L.drf; ++kk) {
+    const uint32_t o = 1 + ((ow[(kk - 1) >> 2] >> (8 * ((kk - 1) & 3))) & 0xFFu) % 63;
+    const int src = (int)((lane + o) & 63u);       // the j-endpoint this lane pairs with
+    const int dst = (int)((lane + 64u - o) & 63u);  // the lane pairing with this lane's j-endpoint
+    const uint32_t vm = __shfl((uint32_t)valid, src, 64);
+    const uint32_t pm = __shfl(p, src, 64);
+    const uint64_t bm = __shfl(b, src, 64);
+    const int64_t pbm = __shfl(pb, src, 64);
+    const float2 Bm = shfl_f2(B, src);
+    float2 disp = make_float2(0.0f, 0.0f);
+    if (valid && vm && pm == p && a != bm && pa != pbm) {
+      const float d = (float)(pa < pbm ? pbm - pa : pa - pbm);
+      const float dx = A.x - Bm.x, dy = A.y - Bm.y;
+      const float mag = sqrtf(dx * dx + dy * dy);
+      if (mag != 0.0f) {
+        const float mu = fminf(L.eta / (d * d), 1.0f);
+        const float rr = mu * (mag - d) / (2.0f * mag);
+        A = make_float2(A.x - rr * dx, A.y - rr * dy);
+        disp = make_float2(rr * dx, rr * dy);
+      }
+    }
+    const float2 back = shfl_f2(disp, dst);
+    B = make_float2(B.x + back.x, B.y + back.y);
+  }
+  if (valid) {
+    Wc[a] = A;
+    Wc[b] = B;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
   extern __shared__ __align__(16) char lds[];
   const LayoutLaunch& L = P.L;
@@ -209,7 +330,8 @@ __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
         if (m >= n_items) break;
         m_end = min(m + P.grab, n_items);
       }
-      local_item(P, V, wb, nq, xi, m, q);
+      if (L.drf > 1) local_item_reuse(P, V, wb, nq, xi, m, q);
+      else local_item(P, V, wb, nq, xi, m, q);
     }
   }
 }

@@ -261,7 +261,7 @@ def test_windowed_sampling_bitexact_chromosome(P, chromosome, it):
 def test_reuse_sampling_bitexact(P, which, it, request):
     sg, og, g = request.getfixturevalue(which)
     n = 1 << 16
-    i, j, f, o = P.sample_terms_reuse(g, it, 64 * 37, n, reuse_factor=4, step_reduction=2, graph_id=3)
+    i, j, f, o = P.sample_terms_reuse(g, it, 64 * 37, n, reuse_factor=4, step_reduction=2, graph_id=3, schedule=1)
     oi, oj, of = O.sample_terms_reuse(og, it, 64 * 37, n, graph_id=3)
     assert np.array_equal(_to_np_u64(i), oi) and np.array_equal(_to_np_u64(j), oj)
     assert np.array_equal(f.cpu().numpy(), of)
@@ -284,22 +284,48 @@ def test_reuse_off_is_the_plain_layout(P, tiny):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("schedule", [1, 3])
 @pytest.mark.parametrize("drf,srf", [(2, 1), (2, 2), (4, 4)])
-def test_reuse_layout_quality_matches_oracle_variant(P, tiny, drf, srf):
+def test_reuse_layout_quality_matches_oracle_variant(P, tiny, drf, srf, schedule):
     import torch
     sg, og, g = tiny
     c0 = O.init_coords(og)
     gpu, ora = [], []
     for sd in (101, 102, 103, 104):
         c = torch.from_numpy(c0).cuda()
-        P.layout(g, c, seed=sd, max_inflight_waves=1, reuse_factor=drf, step_reduction=srf)
+        P.layout(g, c, seed=sd, max_inflight_waves=1, reuse_factor=drf, step_reduction=srf, schedule=schedule)
         gpu.append(O.sps_expectation(og, c.cpu().numpy())[0])
         co = c0.copy()
-        O.layout_reuse(og, co, drf, srf, seed=sd)
+        if schedule == 1:
+            O.layout_reuse(og, co, drf, srf, seed=sd)
+        else:
+            O.layout_windowed(og, co, seed=sd, reuse_factor=drf, step_reduction=srf)
         ora.append(O.sps_expectation(og, co)[0])
     ratio = np.mean(gpu) / np.mean(ora)
-    print(f"reuse ({drf},{srf}): GPU {np.mean(gpu):.6f} oracle {np.mean(ora):.6f} ratio {ratio:.4f}")
+    print(f"reuse ({drf},{srf}) schedule {schedule}: GPU {np.mean(gpu):.6f} oracle {np.mean(ora):.6f} "
+          f"ratio {ratio:.4f}")
     assert abs(ratio - 1) <= 0.03
+
+
+@pytest.mark.parametrize("it", [0, 20])
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+def test_windowed_reuse_sampling_bitexact(P, which, it, request):
+    # slots of the window-major enumeration with step reduction, and every slot's group offsets
+    sg, og, g = request.getfixturevalue(which)
+    T = O.window_slots(og, 10, 2)
+    s0 = 1000 + 5 if which == "tiny" else T // 3 + 11
+    n = min(1 << 16, T - s0)
+    i, j, f, o = P.sample_terms_reuse(g, it, s0, n, reuse_factor=4, step_reduction=2, graph_id=3, schedule=3)
+    off = O.window_offsets(og, it, graph_id=3, threads=16, step_reduction=2)
+    oi, oj, of = O.sample_terms_windowed(og, it, s0, n, graph_id=3, offsets=off)
+    assert np.array_equal(_to_np_u64(i), oi) and np.array_equal(_to_np_u64(j), oj)
+    assert np.array_equal(f.cpu().numpy(), of)
+    go = o.cpu().numpy().reshape(-1, 3)
+    for k in range(0, n, 331):
+        s = s0 + k
+        w = int(np.searchsorted(off, s, side="right") - 1)
+        lead = int(off[w]) + ((s - int(off[w])) // 64) * 64
+        assert list(go[k]) == O.reuse_offsets(it, lead, 4, graph_id=3)
 
 
 # ---------------------------------------------------------------------------
