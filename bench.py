@@ -439,6 +439,101 @@ def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:
                       f"({threads} threads), {dt:.1f} s"}
 
 
+FP64_PEAK_TFLOPS = 78.6
+EXACT_FLOPS_PER_PAIR = 36  # 4 endpoint combinations x 9 (2 sub, 2 mul, add, sqrt, sub, div, mul; sqrt and div as 1)
+
+
+def form_kernels() -> dict:
+    """Each kernel of the path against its roofline, timed with HIP events on
+    the launch stream: algorithmic bytes (FP64 flops for the exact path
+    stress) per unit x units per launch / launch time."""
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    rows = []
+
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    def ev_time(fn, reps=1):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    def row(kernel, workload, unit, units, ms, bytes_per_unit=None, flops_per_unit=None, note_=""):
+        r = {"kernel": kernel, "workload": workload, "unit": unit, "units_per_launch": units, "ms": ms,
+             "units_per_s": units / (ms * 1e-3)}
+        if bytes_per_unit is not None:
+            gbs = bytes_per_unit * units / (ms * 1e-3) / 1e9
+            r.update(bound="hbm", bytes_per_unit=bytes_per_unit, achieved_gbs=gbs, frac=gbs / HBM_PEAK_GBS)
+        if flops_per_unit is not None:
+            tf = flops_per_unit * units / (ms * 1e-3) / 1e12
+            r.update(bound="alu-fp64", flops_per_unit=flops_per_unit, achieved_tflops=tf,
+                     frac=tf / FP64_PEAK_TFLOPS)
+        if note_:
+            r["note"] = note_
+        note(f"[kernels] {kernel} {workload}: {ms:.3f} ms, frac {r.get('frac', 0):.3f}")
+        rows.append(r)
+
+    # layout kernels, chromosome: an iteration with uniform partners (0) and a cooling one (15)
+    sg = synth.config_graph("chromosome")
+    g = P.Graph.from_synth(sg, device=0)
+    c = g.new_coords()
+    T = 10 * g.n_steps
+    for sched, name in ((3, "k_layout_local"), (1, "k_layout_iter")):
+        P.init_coords(g, c)
+        P.layout(g, c, schedule=sched, first_iter=0, last_iter=1)  # warm-up
+        for it in (0, 15):
+            it_ms, mk_ms, launches = P.layout_timed(g, c, schedule=sched, first_iter=it, last_iter=it + 1)
+            row(name, f"chromosome iteration {it}", "term", T / launches, float(mk_ms[0]) / launches, 64)
+            if sched == 3:
+                row("k_local_count + k_local_scan", f"chromosome iteration {it}", "term", T,
+                    float(it_ms[0]) - float(mk_ms[0]), note_="the rest of the iteration: counting pass (one Philox "
+                    "draw per term, ALU bound), scan, fill")
+    # sampled path stress (Eq. 2): two passes over m = 10 pairs per step
+    P.layout(g, c)
+    ms = ev_time(lambda: P.path_stress(g, c, 10, 7))
+    row("k_sps", "chromosome, m = 10", "pair", T, ms / 2, 48, note_="per pass; the two passes and the reductions / 2")
+    del g, c
+    torch.cuda.empty_cache()
+
+    # differentiable form, mid graph, 1e7 power-law pairs
+    sg = synth.config_graph("mid")
+    g = P.Graph.from_synth(sg, device=0)
+    x = g.new_coords()
+    P.init_coords(g, x)
+    n = 10_000_000
+    loss, nv = P.stress_forward(g, x, n, 1, seed=11)
+    ms = ev_time(lambda: P.stress_forward(g, x, n, 1, seed=11), reps=20)
+    row("k_stress_fwd", "mid, 1e7 pairs", "pair", n, ms, 48)
+    gr = torch.zeros_like(x)
+    one = torch.ones(1, device=x.device)
+    ms = ev_time(lambda: P.stress_backward(g, x, n, 1, one, nv, gr, seed=11), reps=20)
+    row("k_stress_bwd", "mid, 1e7 pairs", "pair", n, ms, 64, note_="48 B read + 2 x 8 B of atomic adds")
+    m_, v_ = torch.zeros_like(x), torch.zeros_like(x)
+    ms = ev_time(lambda: P.adam_step(x, gr, m_, v_, 1, lr=1.0), reps=20)
+    row("k_adam", "mid coordinates", "float", x.numel(), ms, 28, note_="x, grad, m, v read; x, m, v written")
+    del g, x, gr, m_, v_
+    torch.cuda.empty_cache()
+
+    # exact path stress (Eq. 1): 8 paths over a 40,000-node backbone (~6e9 step pairs)
+    sg = synth.generate(40_000, 0.2, 8, 77, name="exact-ps")
+    g = P.Graph.from_synth(sg, device=0)
+    c = g.new_coords()
+    P.init_coords(g, c)
+    P.layout(g, c)
+    _, pairs = P.path_stress_exact(g, c)
+    ms = ev_time(lambda: P.path_stress_exact(g, c))
+    row("k_path_stress_exact", "40K-node backbone, 8 paths", "step pair", pairs, ms,
+        flops_per_unit=EXACT_FLOPS_PER_PAIR)
+    return {"rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,7 +544,7 @@ def main():
                     help="processing order of the layout loop (the library's automatic choice is windowed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
-    ap.add_argument("--form", choices=["batched", "autograd", "metric", "reuse"], default=None,
+    ap.add_argument("--form", choices=["batched", "autograd", "metric", "reuse", "kernels"], default=None,
                     help="measure one of the two forms against the plain loop instead (separate JSON line)")
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--summarize", nargs="+", metavar="PATH",
@@ -476,6 +571,9 @@ def main():
         return
     if a.form == "reuse":
         print(json.dumps({"form": "reuse", **form_reuse()}))
+        return
+    if a.form == "kernels":
+        print(json.dumps({"form": "kernels", **form_kernels()}))
         return
 
     import torch
