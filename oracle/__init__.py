@@ -68,6 +68,10 @@ def _load():
         "or_layout_windowed": ([P, u32, u32, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_sampled_path_stress": ([P, P, u32, u64, u32, P, P], None),
         "or_sampled_path_stress_pairs": ([P, P, u32, u64, u32, u32, f64, u32, P, P], None),
+        "or_sps_segments": ([P, P, P], u64),
+        "or_sps_segment_counts": ([P, u32, u64, u32, P, u64, P], None),
+        "or_sps_windowed_pairs": ([P, u32, u64, u32, u64, u64, P, P, P], None),
+        "or_sampled_path_stress_windowed": ([P, P, u32, u64, u32, P, P], None),
         "or_sps_expectation": ([P, P, P], None),
         "or_path_stress_exact": ([P, P, P], None),
         "or_init_coords": ([P, u64, u32, f32, P], None),
@@ -289,7 +293,8 @@ def apply_terms_f32(g: Graph, eta: float, i, j, flags, coords: np.ndarray) -> in
 # ---------------------------------------------------------------------------
 def sampled_path_stress(g: Graph, coords: np.ndarray, m: int = 100, seed: int = 7, graph_id: int = 0,
                         pairs: str = "uniform", theta: float = 0.99, window: int = 1000) -> dict:
-    """Eq. 2 with its CI95; pairs="power_law" takes the cooling phase's partner (reading R19)."""
+    """Eq. 2 with its CI95; pairs="power_law" takes the cooling phase's partner (reading R19),
+    pairs="uniform_windowed" lists the uniform pairs' law window-major (reading R21)."""
     coords = np.ascontiguousarray(coords, dtype=np.float32)
     out = np.zeros(6, dtype=np.float64)
     cnt = np.zeros(2, dtype=np.uint64)
@@ -298,10 +303,41 @@ def sampled_path_stress(g: Graph, coords: np.ndarray, m: int = 100, seed: int = 
     elif pairs == "power_law":
         _load().or_sampled_path_stress_pairs(g._h, _p(coords), int(m), int(seed), int(graph_id), 1, float(theta),
                                              int(window), _p(out), _p(cnt))
+    elif pairs == "uniform_windowed":
+        _load().or_sampled_path_stress_windowed(g._h, _p(coords), int(m), int(seed), int(graph_id), _p(out), _p(cnt))
     else:
-        raise ValueError("pairs must be 'uniform' or 'power_law'")
+        raise ValueError("pairs must be 'uniform', 'power_law' or 'uniform_windowed'")
     return dict(mean=out[0], ci_lo=out[1], ci_hi=out[2], stddev=out[3], sum=out[4], sumsq_dev=out[5],
                 n_valid=int(cnt[0]), n_skipped=int(cnt[1]))
+
+
+def sps_segments(g: Graph):
+    """Segments of the window-major SPS order (reading R21): (start[n + 1], path[n])."""
+    n = int(_load().or_sps_segments(g._h, None, None))
+    start = np.zeros(n + 1, dtype=np.uint64)
+    path = np.zeros(max(1, n), dtype=np.uint32)
+    _load().or_sps_segments(g._h, _p(start), _p(path))
+    return start, path[:n]
+
+
+def sps_segment_counts(g: Graph, m: int = 100, seed: int = 7, graph_id: int = 0) -> np.ndarray:
+    start, _ = sps_segments(g)
+    n = len(start) - 1
+    out = np.zeros(max(1, n), dtype=np.uint64)
+    _load().or_sps_segment_counts(g._h, int(m), int(seed), int(graph_id), _p(start), n, _p(out))
+    return out[:n]
+
+
+def sps_windowed_pairs(g: Graph, m: int = 100, seed: int = 7, graph_id: int = 0, u_begin: int = 0, count=None):
+    """Pairs of slots [u_begin, u_begin + count) of the window-major SPS order: (i, j, e_i | e_j << 1)."""
+    if count is None:
+        count = m * g.S - u_begin
+    i = np.zeros(max(1, count), dtype=np.uint64)
+    j = np.zeros(max(1, count), dtype=np.uint64)
+    e = np.zeros(max(1, count), dtype=np.uint8)
+    _load().or_sps_windowed_pairs(g._h, int(m), int(seed), int(graph_id), int(u_begin), int(count), _p(i), _p(j),
+                                  _p(e))
+    return i[:count], j[:count], e[:count]
 
 
 def sps_expectation(g: Graph, coords: np.ndarray):

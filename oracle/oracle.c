@@ -832,6 +832,126 @@ void or_sampled_path_stress_pairs(const or_graph *g, const float *coords, uint32
   counts[0] = n; counts[1] = skipped;
 }
 
+/* ---------------------------------------------------------------------------
+ * Eq. 2 in window-major order (reading R21): the same law of pairs as the
+ * enumeration above (path p receives exactly m|p| pairs with i and j
+ * independent and uniform in p and independent endpoint coins), listed
+ * segment by segment.  The segments cut the global windows of 2^h steps (h
+ * as for the layout's window-major order) at path boundaries, in step order.
+ * Segment g receives n_g slots, the number of the pairs q of its path whose
+ * step i (as sps_pair draws it) falls in the segment; slot u (slots numbered
+ * consecutively over the segments) draws Philox stream 6 at counter u:
+ * i = segment start + floor(u64 * segment length / 2^64), j = path start +
+ * floor(r2 * |p| / 2^32), e_i = bit 0, e_j = bit 1 of r3.
+ * ------------------------------------------------------------------------- */
+enum { STREAM_SPS_SLOT = 6 };
+
+/* The segments: start[0..n] (start[n] = S) and path[0..n-1]; returns n.  With
+ * start = NULL only counts them. */
+uint64_t or_sps_segments(const or_graph *g, uint64_t *start, uint32_t *path) {
+  uint32_t sh = or_window_shift(g->S);
+  uint64_t n = 0;
+  for (uint32_t p = 0; p < g->n_paths; ++p) {
+    uint64_t a = g->path_off[p], b = g->path_off[p + 1];
+    while (a < b) {
+      uint64_t e = ((a >> sh) + 1) << sh;  /* the next window boundary */
+      if (e > b) e = b;
+      if (start) { start[n] = a; path[n] = p; }
+      ++n;
+      a = e;
+    }
+  }
+  if (start) start[n] = g->S;
+  return n;
+}
+
+/* the segment holding step i: the largest g with start[g] <= i */
+static uint64_t segment_of(const uint64_t *start, uint64_t n_seg, uint64_t i) {
+  uint64_t lo = 0, hi = n_seg;
+  while (hi - lo > 1) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (start[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+/* n_g of every segment (counts[0..n_seg-1]) */
+void or_sps_segment_counts(const or_graph *g, uint32_t m, uint64_t seed, uint32_t graph_id, const uint64_t *start,
+                           uint64_t n_seg, uint64_t *counts) {
+  memset(counts, 0, sizeof(uint64_t) * n_seg);
+  for (uint32_t p = 0; p < g->n_paths; ++p)
+    for (uint64_t q = (uint64_t)m * g->path_off[p]; q < (uint64_t)m * g->path_off[p + 1]; ++q) {
+      uint64_t i, j; uint32_t ei, ej;
+      sps_pair(g, seed, graph_id, p, q, &i, &j, &ei, &ej);
+      ++counts[segment_of(start, n_seg, i)];
+    }
+}
+
+static void sps_slot(const or_graph *g, uint64_t seed, uint32_t graph_id, uint64_t seg_start, uint64_t seg_len,
+                     uint32_t p, uint64_t u, uint64_t *i, uint64_t *j, uint32_t *ei, uint32_t *ej) {
+  uint32_t r[4];
+  draw(seed, u, 0, STREAM_SPS_SLOT, graph_id, r);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+  *i = seg_start + mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), seg_len);
+  *j = start + mulhi32(r[2], (uint32_t)len);
+  *ei = r[3] & 1u;
+  *ej = (r[3] >> 1) & 1u;
+}
+
+/* Lists the pairs of slots [u_begin, u_begin + count): i, j and e = e_i | e_j << 1. */
+void or_sps_windowed_pairs(const or_graph *g, uint32_t m, uint64_t seed, uint32_t graph_id, uint64_t u_begin,
+                           uint64_t count, uint64_t *i_out, uint64_t *j_out, uint8_t *e_out) {
+  uint64_t n_seg = or_sps_segments(g, NULL, NULL);
+  uint64_t *start = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+  uint32_t *path = (uint32_t *)malloc(sizeof(uint32_t) * (n_seg + 1));
+  uint64_t *cnt = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+  or_sps_segments(g, start, path);
+  or_sps_segment_counts(g, m, seed, graph_id, start, n_seg, cnt);
+  uint64_t u = 0;
+  for (uint64_t s = 0; s < n_seg; ++s)
+    for (uint64_t k = 0; k < cnt[s]; ++k, ++u) {
+      if (u < u_begin || u >= u_begin + count) continue;
+      uint64_t i, j; uint32_t ei, ej;
+      sps_slot(g, seed, graph_id, start[s], start[s + 1] - start[s], path[s], u, &i, &j, &ei, &ej);
+      i_out[u - u_begin] = i;
+      j_out[u - u_begin] = j;
+      e_out[u - u_begin] = (uint8_t)(ei | (ej << 1));
+    }
+  free(start); free(path); free(cnt);
+}
+
+void or_sampled_path_stress_windowed(const or_graph *g, const float *coords, uint32_t m, uint64_t seed,
+                                     uint32_t graph_id, double *out, uint64_t *counts) {
+  uint64_t n_seg = or_sps_segments(g, NULL, NULL);
+  uint64_t *start = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+  uint32_t *path = (uint32_t *)malloc(sizeof(uint32_t) * (n_seg + 1));
+  uint64_t *cnt = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+  or_sps_segments(g, start, path);
+  or_sps_segment_counts(g, m, seed, graph_id, start, n_seg, cnt);
+  double sum = 0.0, dev = 0.0, mean = 0.0;
+  uint64_t n = 0, skipped = 0;
+  for (int pass = 1; pass <= 2; ++pass) {
+    uint64_t u = 0;
+    for (uint64_t s = 0; s < n_seg; ++s)
+      for (uint64_t k = 0; k < cnt[s]; ++k, ++u) {
+        uint64_t i, j; uint32_t ei, ej; int valid;
+        sps_slot(g, seed, graph_id, start[s], start[s + 1] - start[s], path[s], u, &i, &j, &ei, &ej);
+        double st = pair_stress(g, coords, i, j, ei, ej, &valid);
+        if (pass == 1) {
+          if (valid) { sum += st; ++n; } else { ++skipped; }
+        } else if (valid) {
+          dev += (st - mean) * (st - mean);
+        }
+      }
+    if (pass == 1) mean = n ? sum / (double)n : 0.0;
+  }
+  free(start); free(path); free(cnt);
+  double sd = n > 1 ? sqrt(dev / (double)(n - 1)) : 0.0;
+  double half = n ? 1.96 * sd / sqrt((double)n) : 0.0;
+  out[0] = mean; out[1] = mean - half; out[2] = mean + half; out[3] = sd; out[4] = sum; out[5] = dev;
+  counts[0] = n; counts[1] = skipped;
+}
+
 void or_sampled_path_stress(const or_graph *g, const float *coords, uint32_t m, uint64_t seed, uint32_t graph_id,
                             double *out, uint64_t *counts) {
   double sum = 0.0;

@@ -666,6 +666,106 @@ def test_sps_pair_count_is_m_times_path_length(tiny_oracle):
 
 
 # ---------------------------------------------------------------------------
+# T8b: Eq. 2's pairs in window-major order (reading R21): the same law
+# ---------------------------------------------------------------------------
+def _small_graph_with_empty_path():
+    # paths of 5, 0 and 3 steps over 8 nodes of length 3
+    return O.Graph(np.full(8, 3, np.uint32), np.array([0, 5, 5, 8], np.uint64), np.arange(8, dtype=np.uint32))
+
+
+def test_sps_segments_tile_the_paths_along_window_boundaries(tiny_oracle):
+    graphs = [tiny_oracle, _disjoint_paths_fixed_point()[0], _small_graph_with_empty_path(),
+              O.Graph.from_synth(synth.linear_path(300, seed=4))]
+    for g in graphs:
+        start, path = O.sps_segments(g)
+        sh = O.window_shift(g.S)
+        off = g.path_off.astype(np.int64)
+        assert start[0] == 0 and int(start[-1]) == g.S and np.all(np.diff(start.astype(np.int64)) > 0)
+        for k in range(len(path)):
+            a, b, p = int(start[k]), int(start[k + 1]), int(path[k])
+            assert off[p] <= a < b <= off[p + 1], "a segment lies inside one path"
+            assert a >> sh == (b - 1) >> sh, "a segment lies inside one window"
+            assert a % (1 << sh) == 0 or a == off[p], "segments are maximal"
+            assert b % (1 << sh) == 0 or b == off[p + 1], "segments are maximal"
+
+
+def test_sps_segment_counts_are_the_histogram_of_the_plain_pair_draws():
+    # brute force over the plain pair enumeration of Eq. 2 (Philox stream 1 at counter q)
+    g, _ = _disjoint_paths_fixed_point()
+    m, seed, gid = 3, 7, 2
+    start, path = O.sps_segments(g)
+    off = g.path_off.astype(np.int64)
+    brute = np.zeros(len(path), np.int64)
+    for p in range(len(off) - 1):
+        length = int(off[p + 1] - off[p])
+        for q in range(m * int(off[p]), m * int(off[p + 1])):
+            r = O.philox([q & 0xFFFFFFFF, q >> 32, 0, (1 << 24) | gid], [seed, 0])
+            i = int(off[p]) + (((int(r[0]) | (int(r[1]) << 32)) * length) >> 64)
+            brute[np.searchsorted(start, i, side="right") - 1] += 1
+    counts = O.sps_segment_counts(g, m, seed, gid).astype(np.int64)
+    assert np.array_equal(counts, brute)
+    per_path = np.bincount(path.astype(np.int64), weights=counts, minlength=len(off) - 1)
+    assert np.array_equal(per_path.astype(np.int64), m * np.diff(off))
+
+
+def test_sps_windowed_pairs_follow_the_uniform_law(tiny_synth, tiny_oracle):
+    g, sg = tiny_oracle, tiny_synth
+    m = 30
+    i, j, e = O.sps_windowed_pairs(g, m, 7)
+    assert len(i) == m * g.S
+    start, path = O.sps_segments(g)
+    counts = O.sps_segment_counts(g, m, 7).astype(np.int64)
+    seg_of_slot = np.repeat(np.arange(len(counts)), counts)
+    assert np.all((i >= start[seg_of_slot]) & (i < start[seg_of_slot + 1])), "slot step outside its segment"
+    pi, pj = _path_of(sg.path_off, i), _path_of(sg.path_off, j)
+    assert np.array_equal(pi, pj), "the partner lies on the same path"
+    assert np.array_equal(np.bincount(pi, minlength=sg.n_paths), m * np.diff(sg.path_off.astype(np.int64)))
+    dof = g.S - 1
+    for x in (i, j):  # both ends uniform over the steps: every step has density m
+        c = np.bincount(x.astype(np.int64), minlength=g.S)
+        chi2 = float(np.sum((c - m) ** 2 / m))
+        assert abs(chi2 - dof) < 5 * math.sqrt(2 * dof)
+    # i and j independent: relative positions in the longest path, 8 x 8 table
+    lens = np.diff(sg.path_off.astype(np.int64))
+    p0 = int(np.argmax(lens))
+    sel = pi == p0
+    bi = ((i[sel].astype(np.int64) - int(sg.path_off[p0])) * 8) // int(lens[p0])
+    bj = ((j[sel].astype(np.int64) - int(sg.path_off[p0])) * 8) // int(lens[p0])
+    tab = np.bincount(bi * 8 + bj, minlength=64).reshape(8, 8).astype(np.float64)
+    exp = np.outer(tab.sum(1), tab.sum(0)) / tab.sum()
+    chi2 = float(np.sum((tab - exp) ** 2 / exp))
+    assert chi2 < 49 + 5 * math.sqrt(2 * 49)
+    for b in (0, 1):
+        assert abs(((e >> b) & 1).mean() - 0.5) < 0.01
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.5, 2.0])
+def test_sps_on_lines_per_path_is_closed_form(lam):
+    # each path on its own line at its path coordinates, scaled by lam: a same-path pair has
+    # mag = lam * d, a pair across paths would not (the lines lie 1000 * lam apart)
+    g, c = _disjoint_paths_fixed_point()
+    c = c * np.float32(lam)
+    for pairs in ("uniform", "uniform_windowed"):
+        s = O.sampled_path_stress(g, c, m=7, pairs=pairs)
+        assert s["n_valid"] + s["n_skipped"] == 7 * g.S
+        assert abs(s["mean"] - (lam - 1) ** 2) < 1e-12
+        assert s["stddev"] < 1e-9
+
+
+def test_sps_windowed_matches_its_expectation_within_ci(tiny_oracle):
+    g = tiny_oracle
+    c = O.init_coords(g)
+    O.layout(g, c, first_iter=0, last_iter=20)
+    exp_mean, frac_valid = O.sps_expectation(g, c)
+    s = O.sampled_path_stress(g, c, m=100, seed=7, pairs="uniform_windowed")
+    n = s["n_valid"]
+    assert n + s["n_skipped"] == 100 * g.S
+    assert abs(s["mean"] - exp_mean) < 3.29 * s["stddev"] / math.sqrt(n)
+    assert abs(n / (100 * g.S) - frac_valid) < 5 * math.sqrt(frac_valid * (1 - frac_valid) / (100 * g.S)) + 1e-9
+    assert abs((s["ci_hi"] - s["ci_lo"]) / 2 - 1.96 * s["stddev"] / math.sqrt(n)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
 # Differentiable form: loss and gradient
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("lam", [0.5, 2.0])
