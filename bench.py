@@ -498,7 +498,11 @@ def form_kernels() -> dict:
     # sampled path stress (Eq. 2): two passes over m = 10 pairs per step
     P.layout(g, c)
     ms = ev_time(lambda: P.path_stress(g, c, 10, 7))
-    row("k_sps", "chromosome, m = 10", "pair", T, ms / 2, 48, note_="per pass; the two passes and the reductions / 2")
+    row("k_sps", "chromosome, m = 10", "pair", T, ms / 2, 48,
+        note_="uniform order, per pass: (coordinate copy, two passes, reductions) / 2")
+    ms = ev_time(lambda: P.path_stress(g, c, 10, 7, pairs="uniform_windowed"))
+    row("k_sps_win", "chromosome, m = 10", "pair", T, ms / 2, 48,
+        note_="window-major order, per pass: (copy, segment count and scan, two passes, reductions) / 2")
     del g, c
     torch.cuda.empty_cache()
 
@@ -630,7 +634,10 @@ def main():
                                 or counters.get("kernel") != kernel):
         traffic = None
 
-    sps = P.path_stress(g, coords, pairs_per_step=10, seed=7)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    sps = P.path_stress(g, coords, pairs_per_step=10, seed=7, pairs="uniform_windowed")
+    sps_s = time.perf_counter() - ts
     # a stored oracle layout of this workload and seed (sequential run preferred, else the Hogwild mode)
     oracle_sps = None
     import glob
@@ -669,6 +676,7 @@ def main():
                      "iteration_ms": avg_iter_ms,
                      "iteration_frac": ALG_BYTES_PER_TERM * T / (avg_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "sps": {"mean": sps["mean"], "ci_lo": sps["ci_lo"], "ci_hi": sps["ci_hi"], "pairs_per_step": 10,
+                "pair_order": "window-major (same law as the uniform order)", "seconds": sps_s,
                 "oracle_mean": oracle_sps["sps_mean"] if oracle_sps else None,
                 "ratio_to_oracle": sps["mean"] / oracle_sps["sps_mean"] if oracle_sps else None,
                 "oracle_mode": oracle_sps.get("mode") if oracle_sps else None},

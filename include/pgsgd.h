@@ -281,7 +281,7 @@ pgsgd_status pgsgd_path_stress(pgsgd_graph *g, const float *coords, uint32_t pai
                                uint32_t graph_id, pgsgd_stress_result *out, void *stream);
 
 /* Pair modes of pgsgd_path_stress_pairs. */
-enum { PGSGD_PAIRS_UNIFORM = 0, PGSGD_PAIRS_POWER_LAW = 1 };
+enum { PGSGD_PAIRS_UNIFORM = 0, PGSGD_PAIRS_POWER_LAW = 1, PGSGD_PAIRS_UNIFORM_WINDOWED = 2 };
 
 /*
  * pgsgd_path_stress with a choice of partner: PGSGD_PAIRS_UNIFORM is Eq. 2
@@ -291,8 +291,26 @@ enum { PGSGD_PAIRS_UNIFORM = 0, PGSGD_PAIRS_POWER_LAW = 1 };
  * room)] from word 2; a single-step path has none and the pair counts as
  * skipped).  The power-law mode measures how well the layout keeps short path
  * distances.  zipf_theta, zipf_window are read in that mode only (same limits
- * as in pgsgd_params).  Synchronises the stream.  Errors: INVALID_ARG (unknown
- * mode, bad Zipf parameters), UNSUPPORTED (LDS), DEVICE.
+ * as in pgsgd_params).
+ * PGSGD_PAIRS_UNIFORM_WINDOWED samples the same law of pairs as
+ * PGSGD_PAIRS_UNIFORM (each path exactly pairs_per_step * |p| pairs, i and j
+ * independent and uniform in the path, independent coins) in window-major
+ * order, for locality: the windows of 2^h global steps (h as for the
+ * WINDOWED schedule) cut at path boundaries form segments in step order;
+ * segment g receives n_g slots, the number of the uniform mode's pairs of its
+ * path whose step i falls in it; slot u (numbered over the segments in order)
+ * draws Philox stream 6 at counter u: i = segment start + floor(u64 *
+ * segment length / 2^64), j = path start + floor(r2 * |p| / 2^32), e_i = bit
+ * 0, e_j = bit 1 of r3.  Its segment tables are allocated on first use (about
+ * 20 bytes per segment); it needs 8 bytes per path slot plus 4 bytes per
+ * segment of LDS and pairs_per_step * 2^(h+1) < 2^32.  Its waves take the
+ * 64-slot groups from shared counters, so sum and sumsq_dev are reproducible
+ * only up to the rounding of their FP64 summation order (the pairs, n_valid
+ * and n_skipped are exact).
+ * Every mode first copies coords into the graph's interleaved working copy,
+ * so calls on one graph must be ordered on one stream (as for pgsgd_layout).
+ * Synchronises the stream.  Errors: INVALID_ARG (unknown mode, bad Zipf
+ * parameters), UNSUPPORTED (LDS, segment counts), DEVICE, OOM.
  */
 pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
                                      uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,

@@ -181,10 +181,11 @@ def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, grap
                 pairs: str = "uniform", zipf_theta: float = 0.99, zipf_window: int = 1000) -> dict:
     """Sampled path stress (Eq. 2) with CI95; synchronises the current stream.
     pairs="power_law" takes the cooling phase's power-law partner instead of a
-    uniform one (a measure of local structure)."""
+    uniform one (a measure of local structure); pairs="uniform_windowed"
+    samples the uniform law in window-major order (faster on large graphs)."""
     import torch
     _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
-    modes = {"uniform": 0, "power_law": 1}
+    modes = {"uniform": 0, "power_law": 1, "uniform_windowed": 2}
     if pairs not in modes:
         raise ValueError(f"pairs must be one of {sorted(modes)}")
     r = StressResult()

@@ -158,6 +158,16 @@ struct pgsgd_graph {
   uint32_t* d_lorder = nullptr;
   uint32_t* d_lsbeg = nullptr;
   uint32_t* d_lwpath = nullptr;
+  // window-major sampled path stress tables (allocated on first use)
+  uint32_t sps_shift = 0, sps_nseg = 0, sps_xstride = 0;
+  uint64_t* d_sseg_start = nullptr;
+  uint32_t* d_sseg_path = nullptr;
+  uint32_t* d_swseg = nullptr;
+  uint32_t* d_scount = nullptr;
+  uint64_t* d_soff = nullptr;
+  uint32_t* d_ssbeg = nullptr;
+  uint64_t* d_sxitem = nullptr;
+  uint64_t* d_squeue = nullptr;
 
   ~pgsgd_graph() {
     DeviceGuard g(device);
@@ -166,7 +176,8 @@ struct pgsgd_graph {
                     (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_tag,
                     (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem,
                     (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
-                    (void*)d_lsbeg, (void*)d_lwpath})
+                    (void*)d_lsbeg, (void*)d_lwpath, (void*)d_sseg_start, (void*)d_sseg_path, (void*)d_swseg,
+                    (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue})
       if (p) (void)hipFree(p);
   }
 };
@@ -661,6 +672,63 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   return PGSGD_OK;
 }
 
+// Segments of the window-major sampled path stress: the windows of the
+// windowed schedule cut at path boundaries, in step order; run x (XCD x)
+// holds the segments starting in the x-th eighth of the steps.
+pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
+  const uint32_t shift = window_shift(g->S);
+  if (g->d_sseg_start && g->sps_shift == shift) return PGSGD_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  for (void** q : {(void**)&g->d_sseg_start, (void**)&g->d_sseg_path, (void**)&g->d_swseg, (void**)&g->d_scount,
+                   (void**)&g->d_soff, (void**)&g->d_ssbeg, (void**)&g->d_sxitem, (void**)&g->d_squeue})
+    if (*q) {
+      (void)hipFree(*q);
+      *q = nullptr;
+    }
+  const uint64_t nwin = (g->S + (1ull << shift) - 1) >> shift;
+  std::vector<uint64_t> start;
+  std::vector<uint32_t> path;
+  for (uint32_t p = 0; p < g->n_paths; ++p)
+    for (uint64_t a = g->h_path_off[p], b = g->h_path_off[p + 1]; a < b;) {
+      const uint64_t e = std::min<uint64_t>(b, ((a >> shift) + 1) << shift);
+      start.push_back(a);
+      path.push_back(p);
+      a = e;
+    }
+  start.push_back(g->S);
+  const uint64_t nseg = path.size();
+  if (nseg >= (1ull << 31)) return fail(PGSGD_ERR_UNSUPPORTED, "too many segments");
+  std::vector<uint32_t> wseg(nwin + 1), sbeg(kXcds + 1);
+  for (uint64_t w = 0, k = 0; w <= nwin; ++w) {  // first segment starting at or after the window's start
+    while (k < nseg && start[k] < (w << shift)) ++k;
+    wseg[w] = (uint32_t)(w == nwin ? nseg : k);
+  }
+  for (uint32_t x = 0, k = 0; x <= kXcds; ++x) {  // first segment starting at or after x * S / 8
+    while (k < nseg && (unsigned __int128)start[k] * kXcds < (unsigned __int128)x * g->S) ++k;
+    sbeg[x] = x == kXcds ? (uint32_t)nseg : k;
+  }
+  uint32_t longest = 0;
+  for (uint32_t x = 0; x < kXcds; ++x) longest = std::max(longest, sbeg[x + 1] - sbeg[x]);
+  g->sps_shift = shift;
+  g->sps_nseg = (uint32_t)nseg;
+  g->sps_xstride = longest + 1;
+  pgsgd_status st;
+  if ((st = dev_alloc(g, &g->d_sseg_start, nseg + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_sseg_path, nseg))) return st;
+  if ((st = dev_alloc(g, &g->d_swseg, nwin + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_scount, nseg))) return st;
+  if ((st = dev_alloc(g, &g->d_soff, nseg + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_ssbeg, kXcds + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_sxitem, (size_t)kXcds * g->sps_xstride))) return st;
+  if ((st = dev_alloc(g, &g->d_squeue, (size_t)2 * kXcds * 16))) return st;
+  HIP_TRY(hipMemcpy(g->d_sseg_start, start.data(), sizeof(uint64_t) * (nseg + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->d_sseg_path, path.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->d_swseg, wseg.data(), sizeof(uint32_t) * (nwin + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->d_ssbeg, sbeg.data(), sizeof(uint32_t) * (kXcds + 1), hipMemcpyHostToDevice));
+  HIP_TRY(launch_fill_u32(g->d_scount, nseg, 0u, s));  // the histogram must start at zero
+  return PGSGD_OK;
+}
+
 // Automatic wave cap of the windowed schedule (see kLocalNodesPerWave).
 uint64_t auto_local_waves(const pgsgd_graph* g) {
   const uint32_t sh = window_shift(g->S);
@@ -1010,7 +1078,7 @@ pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32
                                      uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
                                      pgsgd_stress_result* out, void* stream) {
   if (!g || !coords || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
-  if (pair_mode > PGSGD_PAIRS_POWER_LAW) return fail(PGSGD_ERR_INVALID_ARG, "unknown pair mode %u", pair_mode);
+  if (pair_mode > PGSGD_PAIRS_UNIFORM_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown pair mode %u", pair_mode);
   if (pair_mode == PGSGD_PAIRS_POWER_LAW) {
     if (zipf_window < 1 || zipf_window > 65535)
       return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", zipf_window);
@@ -1036,10 +1104,43 @@ pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32
   P.m = m;
   P.count = g->S;
   P.W = zipf_window;
-  HIP_TRY(launch_sps_pass(P, 1, mode, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
-  HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
-                              g->d_mean, nullptr, nullptr, s));
-  HIP_TRY(launch_sps_pass(P, 2, mode, g->d_mean, g->d_part_f, nullptr, nullptr, s));
+  P.work = g->d_work;
+  if (mode == PGSGD_PAIRS_UNIFORM_WINDOWED) {
+    pgsgd_status st = ensure_sps_windowed(g, s);
+    if (st) return st;
+    if ((size_t)g->path_slots * 8 + (size_t)g->sps_nseg * 4 > g->lds_limit)
+      return fail(PGSGD_ERR_UNSUPPORTED, "the segment histogram (%u segments) exceeds the %zu-byte LDS of a block",
+                  g->sps_nseg, g->lds_limit);
+    if (((uint64_t)m << (g->sps_shift + 1)) >= (1ull << 32))
+      return fail(PGSGD_ERR_UNSUPPORTED, "pairs_per_step %u too large for 32-bit segment counts", m);
+    SpsWinLaunch W{};
+    W.P = P;
+    W.slot_c3 = (kStreamSpsSlot << 24) | (graph_id & 0xFFFFFFu);
+    W.win_shift = g->sps_shift;
+    W.n_seg = g->sps_nseg;
+    W.xstride = g->sps_xstride;
+    W.count_blocks = (uint32_t)g->n_cu * 2;
+    W.seg_start = g->d_sseg_start;
+    W.seg_path = g->d_sseg_path;
+    W.wseg = g->d_swseg;
+    W.count = g->d_scount;
+    W.seg_off = g->d_soff;
+    W.sbeg = g->d_ssbeg;
+    W.xitem = g->d_sxitem;
+    W.queue = g->d_squeue;
+    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+    HIP_TRY(launch_sps_win_count_scan(W, s));
+    HIP_TRY(launch_sps_win_pass(W, 1, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, s));
+    HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
+                                g->d_mean, nullptr, nullptr, s));
+    HIP_TRY(launch_sps_win_pass(W, 2, g->d_mean, g->d_part_f, nullptr, nullptr, kStressBlocks, s));
+  } else {
+    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+    HIP_TRY(launch_sps_pass(P, 1, mode, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
+    HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
+                                g->d_mean, nullptr, nullptr, s));
+    HIP_TRY(launch_sps_pass(P, 2, mode, g->d_mean, g->d_part_f, nullptr, nullptr, s));
+  }
   HIP_TRY(launch_reduce_parts(g->d_part_f, nullptr, nullptr, kStressBlocks, g->d_out_f + 1, nullptr, nullptr,
                               nullptr, nullptr, s));
   double f[2];

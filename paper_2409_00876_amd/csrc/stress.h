@@ -9,9 +9,12 @@
 
 namespace pgsgd {
 
+constexpr uint32_t kStreamSpsSlot = 6;  // Philox stream of the window-major sampled path stress slots
+
 struct StressLaunch {
   const StepRec* rec;
   const float* coords;
+  const float2* work;      // interleaved copy of coords (sampled path stress only)
   const uint64_t* path_off;
   const uint32_t* zipf;
   const uint16_t* guide;
@@ -39,6 +42,30 @@ hipError_t launch_sps_pass(const StressLaunch& P, int pass, int mode, const doub
 hipError_t launch_reduce_parts(const double* part_f, const uint64_t* part_n, const uint64_t* part_skip,
                                uint32_t n_parts, double* out_f, uint64_t* out_n, double* mean_out,
                                float* loss_out, uint64_t* n_valid_out, hipStream_t s);
+// Sampled path stress in window-major order: segments (the windows of
+// 2^win_shift steps cut at path boundaries, in step order) get the counts of
+// the plain pair draws that fall in them; each segment's slots draw their pair
+// inside it.  Runs: XCD x takes the segments [sbeg[x], sbeg[x + 1]).
+struct SpsWinLaunch {
+  StressLaunch P;             // rec, work, path_off, S, m, path table, c3 of the plain pair draws, key
+  uint32_t slot_c3;           // Philox word 3 of the slot draws
+  uint32_t win_shift;
+  uint32_t n_seg;
+  uint32_t xstride;           // row length of xitem
+  uint32_t count_blocks;
+  const uint64_t* seg_start;  // [n_seg + 1], seg_start[n_seg] = S
+  const uint32_t* seg_path;   // [n_seg]
+  const uint32_t* wseg;       // [n_win + 1] first segment of every window
+  uint32_t* count;            // [n_seg] histogram (zeroed again by the scan)
+  uint64_t* seg_off;          // [n_seg + 1] first slot of every segment
+  const uint32_t* sbeg;       // [kXcds + 1] first segment of every run
+  uint64_t* xitem;            // [kXcds][xstride] prefix of 64-slot items over the segments of each run
+  uint64_t* queue;            // [2][kXcds][16] item counters of the two passes (zeroed by the scan)
+};
+hipError_t launch_sps_win_count_scan(const SpsWinLaunch& W, hipStream_t s);
+// grid: blocks a multiple of kXcds
+hipError_t launch_sps_win_pass(const SpsWinLaunch& W, int pass, const double* mean_dev, double* part_f,
+                               uint64_t* part_n, uint64_t* part_skip, uint32_t blocks, hipStream_t s);
 hipError_t launch_path_stress_exact(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,

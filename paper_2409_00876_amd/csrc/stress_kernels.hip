@@ -59,6 +59,17 @@ __device__ __forceinline__ double stress_fp64(const float* __restrict__ X, const
   return e * e;
 }
 
+// The same value from the interleaved copy (W[e] = (x, y) of endpoint e).
+__device__ __forceinline__ double stress_work(const float2* __restrict__ W, uint64_t a, uint64_t b, double d) {
+#pragma clang fp contract(off)
+  const float2 va = W[a], vb = W[b];
+  const double dx = (double)va.x - (double)vb.x;
+  const double dy = (double)va.y - (double)vb.y;
+  const double mag = sqrt(dx * dx + dy * dy);
+  const double e = (mag - d) / d;
+  return e * e;
+}
+
 // ---------------------------------------------------------------------------
 // Sampled path stress: thread-strided over steps s; step s owns pairs
 // q = m*s .. m*s+m-1, which all belong to the path of s.
@@ -88,8 +99,6 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, int mode,
   }
   __syncthreads();
   const double mean = pass == 2 ? mean_dev[0] : 0.0;
-  const float* __restrict__ X = P.coords;
-  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
   double acc = 0.0;
   uint64_t nv = 0, ns = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -115,14 +124,190 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, int mode,
         ++ns;
         continue;
       }
-      double dx, dy, mag;
-      const double st = stress_fp64(X, Y, a, b, d, dx, dy, mag);
+      const double st = stress_work(P.work, a, b, d);
       if (pass == 1) {
         acc += st;
         ++nv;
       } else {
 #pragma clang fp contract(off)
         acc += (st - mean) * (st - mean);
+      }
+    }
+  }
+  acc = block_sum(acc, red_f);
+  nv = block_sum(nv, red_n);
+  ns = block_sum(ns, red_n);
+  if (threadIdx.x == 0) {
+    part_f[blockIdx.x] = acc;
+    if (part_n) part_n[blockIdx.x] = nv;
+    if (part_skip) part_skip[blockIdx.x] = ns;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sampled path stress in window-major order.  The pairs of Eq. 2 keep their
+// law (path p receives m|p| pairs, i and j independent and uniform in p) and
+// are listed segment by segment: segment g (a window of 2^win_shift steps cut
+// at path boundaries) receives the number n_g of the plain pair draws whose
+// step i falls in it, and slot u (numbered consecutively over the segments)
+// draws i uniformly in its segment and j uniformly in its path from the slot
+// stream at counter u.  XCD x (blocks b with b mod 8 = x) walks the segments
+// of run x with all its waves, 64 slots per wave and item, so the i side of
+// the pairs (records and coordinates of one window) stays in the XCD's L2 and
+// only the j side reaches into the rest of the path.  The waves take their
+// items from one counter per run, so they all stay near the same window (a
+// static share per wave drifts apart over thousands of items); the FP64
+// block sums then depend on which wave took which item, so a result is
+// reproducible up to the rounding of that sum order.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kSpsGrab = 4;  // items a wave takes from its run's counter at once
+
+// loads at wave-uniform addresses through the constant address space (scalar loads)
+template <typename T>
+__device__ __forceinline__ T uload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  return ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32) | uniform_u32((uint32_t)v);
+}
+
+}  // namespace
+
+// The segment histogram: step s owns the plain pairs q = m*s .. m*s+m-1 (all
+// of the path of s); each draws its i as k_sps does and counts its segment.
+__global__ __launch_bounds__(1024) void k_sps_win_count(SpsWinLaunch W) {
+  extern __shared__ __align__(16) char lds[];
+  const StressLaunch& P = W.P;
+  uint64_t* off = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (size_t)P.path_slots * 8);
+  fill_offsets(off, P);
+  for (uint32_t k = threadIdx.x; k < W.n_seg; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < P.S; s += stride) {
+    const uint32_t p = find_path(off, P.path_top, s);
+    const uint64_t start = off[p], len = off[p + 1] - start;
+    for (uint32_t k = 0; k < P.m; ++k) {
+      const uint64_t q = (uint64_t)P.m * s + k;
+      const Rand4 r = philox10((uint32_t)q, (uint32_t)(q >> 32), 0u, P.c3, P.k0, P.k1);
+      const uint64_t i = start + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), len);
+      const uint32_t w = (uint32_t)(i >> W.win_shift);
+      uint32_t lo = W.wseg[w], hi = W.wseg[w + 1];  // the segments of window w: the last with start <= i
+      while (hi - lo > 1) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (W.seg_start[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      atomicAdd(&hist[lo], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < W.n_seg; k += blockDim.x)
+    if (hist[k]) atomicAdd(&W.count[k], hist[k]);
+}
+
+// One block: seg_off = exclusive prefix of the counts, the per-run item
+// prefixes and zeroed item counters, then the histogram back to zero.
+__global__ __launch_bounds__(1024) void k_sps_win_scan(SpsWinLaunch W) {
+  __shared__ uint64_t part[1024];
+  const uint32_t n = W.n_seg;
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t k0 = min(n, threadIdx.x * per);
+  const uint32_t k1 = min(n, k0 + per);
+  uint64_t s = 0;
+  for (uint32_t k = k0; k < k1; ++k) s += W.count[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t acc = 0;
+    for (uint32_t k = 0; k < blockDim.x; ++k) {
+      const uint64_t v = part[k];
+      part[k] = acc;
+      acc += v;
+    }
+    W.seg_off[n] = acc;
+  }
+  __syncthreads();
+  uint64_t acc = part[threadIdx.x];
+  for (uint32_t k = k0; k < k1; ++k) {
+    W.seg_off[k] = acc;
+    acc += W.count[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kXcds) {
+    const uint32_t run = threadIdx.x;
+    uint64_t* xi = W.xitem + (size_t)run * W.xstride;
+    uint64_t items = 0;
+    const uint32_t b = W.sbeg[run], e = W.sbeg[run + 1];
+    for (uint32_t g = b; g < e; ++g) {
+      xi[g - b] = items;
+      items += (W.count[g] + 63) >> 6;
+    }
+    xi[e - b] = items;
+  }
+  if (threadIdx.x < 2 * kXcds) W.queue[(size_t)threadIdx.x * 16] = 0;
+  __syncthreads();
+  for (uint32_t k = k0; k < k1; ++k) W.count[k] = 0;
+}
+
+// One pass: the waves of XCD x take the items of run x from its counter,
+// kSpsGrab at a time; every wave leaves once the counter has passed the run's
+// last item.
+__global__ __launch_bounds__(256) void k_sps_win(SpsWinLaunch W, int pass, const double* __restrict__ mean_dev,
+                                                 double* __restrict__ part_f, uint64_t* __restrict__ part_n,
+                                                 uint64_t* __restrict__ part_skip) {
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  const StressLaunch& P = W.P;
+  const double mean = pass == 2 ? mean_dev[0] : 0.0;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t x = blockIdx.x % kXcds;
+  const uint32_t gb = uload(W.sbeg + x);
+  const uint32_t nq = uload(W.sbeg + x + 1) - gb;
+  const uint64_t* __restrict__ xi = W.xitem + (size_t)x * W.xstride;
+  const uint64_t n_items = uniform_u64(uload(xi + nq));
+  unsigned long long* ctr = reinterpret_cast<unsigned long long*>(W.queue + ((size_t)(pass - 1) * kXcds + x) * 16);
+  double acc = 0.0;
+  uint64_t nv = 0, ns = 0;
+  uint32_t q = 0;
+  for (uint64_t m = 0, m_end = 0;; ++m) {
+    if (m >= m_end) {
+      uint64_t base = 0;
+      if (lane == 0) base = atomicAdd(ctr, (unsigned long long)kSpsGrab);
+      m = uniform_u64(base);
+      if (m >= n_items) break;
+      m_end = min(m + kSpsGrab, n_items);
+    }
+    while (q + 1 < nq && uniform_u64(uload(xi + q + 1)) <= m) q = uniform_u32(q + 1);
+    const uint32_t g = gb + q;
+    const uint64_t u0 = uniform_u64(uload(W.seg_off + g)) + (m - uniform_u64(uload(xi + q))) * 64;
+    const uint64_t u_end = uniform_u64(uload(W.seg_off + g + 1));
+    const uint64_t sst = uniform_u64(uload(W.seg_start + g));
+    const uint64_t slen = uniform_u64(uload(W.seg_start + g + 1)) - sst;
+    const uint32_t p = uniform_u32(uload(W.seg_path + g));
+    const uint64_t pst = uniform_u64(uload(P.path_off + p));
+    const uint64_t plen = uniform_u64(uload(P.path_off + p + 1)) - pst;
+    const uint64_t u = u0 + lane;
+    if (u < u_end) {
+      const Rand4 r = philox10((uint32_t)u, (uint32_t)(u >> 32), 0u, W.slot_c3, P.k0, P.k1);
+      const uint64_t i = sst + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), slen);
+      const uint64_t j = pst + mulhi32(r.r2, (uint32_t)plen);
+      uint64_t a, b;
+      double d;
+      if (!pair_terms(P.rec, i, j, r.r3 & 1u, (r.r3 >> 1) & 1u, a, b, d)) {
+        ++ns;
+      } else {
+        const double st = stress_work(P.work, a, b, d);
+        if (pass == 1) {
+          acc += st;
+          ++nv;
+        } else {
+#pragma clang fp contract(off)
+          acc += (st - mean) * (st - mean);
+        }
       }
     }
   }
@@ -385,6 +570,22 @@ hipError_t launch_sps_pass(const StressLaunch& P, int pass, int mode, const doub
   const size_t lds = mode == 1 ? loss_lds_bytes(P) : (size_t)P.path_slots * 8;
   hipLaunchKernelGGL(k_sps, dim3(kStressBlocks), dim3(kStressThreads), lds, s, P, pass, mode, mean_dev, part_f,
                      part_n, part_skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_sps_win_count_scan(const SpsWinLaunch& W, hipStream_t s) {
+  const size_t lds = (size_t)W.P.path_slots * 8 + (size_t)W.n_seg * 4;
+  hipLaunchKernelGGL(k_sps_win_count, dim3(W.count_blocks), dim3(1024), lds, s, W);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_sps_win_scan, dim3(1), dim3(1024), 0, s, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_sps_win_pass(const SpsWinLaunch& W, int pass, const double* mean_dev, double* part_f,
+                               uint64_t* part_n, uint64_t* part_skip, uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_sps_win, dim3(blocks), dim3(kStressThreads), 0, s, W, pass, mean_dev, part_f, part_n,
+                     part_skip);
   return hipGetLastError();
 }
 

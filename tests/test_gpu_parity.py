@@ -397,7 +397,7 @@ def test_collision_free_batch_matches_fp64(P, which, it, request):
 # ---------------------------------------------------------------------------
 # T9: sampled path stress of the same layout
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("pairs", ["uniform", "power_law"])
+@pytest.mark.parametrize("pairs", ["uniform", "power_law", "uniform_windowed"])
 @pytest.mark.parametrize("which,m", [("tiny", 100), ("mid", 1)])
 def test_sps_equals_oracle_on_same_layout(P, which, m, pairs, request):
     import torch
@@ -412,6 +412,55 @@ def test_sps_equals_oracle_on_same_layout(P, which, m, pairs, request):
     assert abs(r["sum"] - o["sum"]) <= 1e-9 * abs(o["sum"])
     assert abs(r["sumsq_dev"] - o["sumsq_dev"]) <= 1e-9 * abs(o["sumsq_dev"])
     assert abs(r["ci_hi"] - o["ci_hi"]) <= 1e-9 * abs(o["ci_hi"])
+
+
+def _short_paths_synth():
+    # 3,000 paths of 0-9 steps: windows hold dozens of segments
+    rng = np.random.default_rng(12)
+    n_nodes = 5000
+    lens = rng.integers(0, 10, size=3000)
+    steps = [[int(x) | (synth.REV_BIT if rng.random() < 0.1 else 0) for x in rng.integers(0, n_nodes, size=k)]
+             for k in lens]
+    off = np.cumsum([0] + [len(p_) for p_ in steps]).astype(np.uint64)
+    node_len = rng.integers(1, 30, size=n_nodes).astype(np.uint32)
+    return synth.SynthGraph(node_len, off, np.array([x for p_ in steps for x in p_], np.uint32), {}, "short")
+
+
+@pytest.mark.parametrize("which", ["edge", "short_paths"])
+def test_sps_windowed_equals_oracle_on_edge_graphs(P, which):
+    import torch
+    sg = _edge_synth() if which == "edge" else _short_paths_synth()
+    og, g = O.Graph.from_synth(sg), P.Graph.from_synth(sg)
+    rng = np.random.default_rng(3)
+    c0 = (O.init_coords(og) + rng.normal(scale=20.0, size=4 * og.n_nodes)).astype(np.float32)
+    for m, seed in ((1, 7), (13, 9)):
+        r = P.path_stress(g, torch.from_numpy(c0).cuda(), m, seed, pairs="uniform_windowed")
+        o = O.sampled_path_stress(og, c0, m, seed, pairs="uniform_windowed")
+        assert r["n_valid"] == o["n_valid"] and r["n_skipped"] == o["n_skipped"]
+        assert r["n_valid"] + r["n_skipped"] == m * og.S
+        assert abs(r["sum"] - o["sum"]) <= 1e-9 * abs(o["sum"])
+        assert abs(r["sumsq_dev"] - o["sumsq_dev"]) <= 1e-9 * abs(o["sumsq_dev"])
+
+
+def test_sps_windowed_agrees_with_uniform_order_on_chromosome(P, chromosome):
+    # full size, the benchmark's call: the two orders sample the same law, so on one layout
+    # their means agree within the combined standard error; pair counts are exact
+    import torch
+    sg, og, g = chromosome
+    c = g.new_coords()
+    P.init_coords(g, c)
+    P.layout(g, c, first_iter=0, last_iter=3)
+    a = P.path_stress(g, c, 1, 7, pairs="uniform")
+    b = P.path_stress(g, c, 1, 7, pairs="uniform_windowed")
+    b2 = P.path_stress(g, c, 1, 7, pairs="uniform_windowed")
+    # the same pairs again; only the order of the FP64 block sums may differ
+    assert b["n_valid"] == b2["n_valid"] and b["n_skipped"] == b2["n_skipped"]
+    assert abs(b["sum"] - b2["sum"]) <= 1e-12 * abs(b["sum"])
+    for r in (a, b):
+        assert r["n_valid"] + r["n_skipped"] == og.S
+    se = math.sqrt(a["stddev"] ** 2 / a["n_valid"] + b["stddev"] ** 2 / b["n_valid"])
+    assert abs(a["mean"] - b["mean"]) < 4.5 * se
+    assert abs(a["n_skipped"] - b["n_skipped"]) < 6 * math.sqrt(a["n_skipped"] + 1) + 10
 
 
 # ---------------------------------------------------------------------------
