@@ -51,9 +51,9 @@ def counters_file(kernel: str) -> str:
     return os.path.join(ROOT, "profiles", f"{COUNTERS_NAME[kernel]}_chromosome_counters.json")
 
 
-def profile_commands(schedule: str) -> str:
+def profile_commands(schedule: str, d: str) -> str:
+    """The rocprofv3 runs behind a counter summary, writing under directory d."""
     opt = "" if schedule == "windowed" else f" --schedule {schedule}"
-    d = f"gpurun_out/prof_{schedule}"
     return f"""rocprofv3 --kernel-trace --stats -f csv -d {d}/trace -o trace -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline{opt}
 rocprofv3 --pmc FETCH_SIZE -f csv -d {d}/fetch -o fetch -- python3 bench.py --profile{opt}
 rocprofv3 --pmc WRITE_SIZE -f csv -d {d}/write -o write -- python3 bench.py --profile{opt}
@@ -99,7 +99,8 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
     benchmark) and .md, for the layout kernel of `schedule`."""
     import csv
     copy_bytes = 1 << 30
-    command = profile_commands(schedule)
+    # the passes write to <d>/trace, <d>/fetch, ...: d is the trace directory's parent
+    command = profile_commands(schedule, os.path.relpath(os.path.dirname(os.path.abspath(trace_dir.rstrip("/"))), ROOT))
     kernel = DOMINANT[SCHEDULES[schedule]]
 
     fetch_rows = _read_counters(fetch_csv)
