@@ -120,11 +120,21 @@ typedef struct {
   uint32_t first_iter;        /* run iterations [first_iter, last_iter) ... */
   uint32_t last_iter;         /* ... ; last_iter = 0 means n_iters */
   uint32_t max_inflight_waves;/* cap on concurrently running 64-term groups (waves); 0 = automatic */
-  uint32_t flags;             /* reserved, must be 0 */
+  uint32_t flags;             /* PGSGD_FLAG_* (0: defaults) */
   uint32_t schedule;          /* processing order of an iteration's terms: PGSGD_SCHEDULE_* */
   uint16_t reuse_factor;      /* data reuse: updates per sampled term (DRF), 0 or 1 = off, at most 16 */
   uint16_t step_reduction;    /* data reuse: sampled terms per iteration divided by this (SRF), 0 or 1 = off */
 } pgsgd_params;
+
+/* pgsgd_params.flags.  A WINDOWED layout over several iterations may count
+ * iteration t + 1 (its window histogram and offsets, in a second set of
+ * buffers) on a stream of the graph's own while iteration t is laid out;
+ * by default it does so when an iteration has at least 2^31 terms.  The
+ * sampled terms and, with one wave, the coordinates are the same either way.
+ * PGSGD_FLAG_COUNT_AHEAD forces the overlap, PGSGD_FLAG_COUNT_IN_ORDER keeps
+ * every pass on the caller's stream; setting both is INVALID_ARG.  Batched
+ * layouts keep the passes in order. */
+enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
 
 /* Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
  * Trade-off with Sampled Path Stress"), active when reuse_factor > 1 or
@@ -236,7 +246,7 @@ pgsgd_status pgsgd_init_coords(pgsgd_graph *g, uint64_t seed, uint32_t graph_id,
  *        skipped; otherwise mu = min(eta / d^2, 1) and both points move by
  *        mu * (|v_i - v_j| - d) / 2 towards (or away from) each other.
  * Async.  A graph with S = 0 returns OK without work.
- * Errors: INVALID_ARG (NULL, flags != 0, zipf_window out of range, graph_id >=
+ * Errors: INVALID_ARG (NULL, unknown or conflicting flags, zipf_window out of range, graph_id >=
  * 2^24, first_iter > last_iter), RANGE (term count >= 2^48), DEVICE.
  */
 pgsgd_status pgsgd_layout(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
+from ._lib import (FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
                    check, lib)
 
 __all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",

@@ -20,6 +20,7 @@ ERR_DEVICE = -4
 ERR_UNSUPPORTED = -5
 SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_BINNED, SCHEDULE_WINDOWED = 0, 1, 2, 3
 PAIRS_UNIFORM, PAIRS_POWER_LAW, PAIRS_UNIFORM_WINDOWED = 0, 1, 2
+FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER = 1, 2
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "RANGE", -3: "OOM", -4: "DEVICE", -5: "UNSUPPORTED"}
 
 

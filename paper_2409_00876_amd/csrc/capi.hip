@@ -168,6 +168,14 @@ struct pgsgd_graph {
   uint32_t* d_ssbeg = nullptr;
   uint64_t* d_sxitem = nullptr;
   uint64_t* d_squeue = nullptr;
+  // second count/offset set and the counting stream: the counts of iteration
+  // t + 1 are computed on count_stream while iteration t is laid out
+  uint32_t* d_lcount2 = nullptr;
+  uint64_t* d_loff2 = nullptr;
+  uint64_t* d_lxitem2 = nullptr;
+  uint64_t* d_lqueue2 = nullptr;
+  hipStream_t count_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_count[2] = {nullptr, nullptr}, ev_layout[2] = {nullptr, nullptr};
 
   ~pgsgd_graph() {
     DeviceGuard g(device);
@@ -177,8 +185,12 @@ struct pgsgd_graph {
                     (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem,
                     (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
                     (void*)d_lsbeg, (void*)d_lwpath, (void*)d_sseg_start, (void*)d_sseg_path, (void*)d_swseg,
-                    (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue})
+                    (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue,
+                    (void*)d_lcount2, (void*)d_loff2, (void*)d_lxitem2, (void*)d_lqueue2})
       if (p) (void)hipFree(p);
+    for (hipEvent_t e : {ev_start, ev_count[0], ev_count[1], ev_layout[0], ev_layout[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (count_stream) (void)hipStreamDestroy(count_stream);
   }
 };
 
@@ -222,7 +234,10 @@ pgsgd_status ensure_zipf(pgsgd_graph* g, double theta, uint32_t W, hipStream_t s
 
 pgsgd_status check_params(const pgsgd_params* p) {
   if (!p) return fail(PGSGD_ERR_INVALID_ARG, "params is NULL");
-  if (p->flags != 0) return fail(PGSGD_ERR_INVALID_ARG, "params.flags must be 0");
+  if (p->flags & ~(uint32_t)(PGSGD_FLAG_COUNT_AHEAD | PGSGD_FLAG_COUNT_IN_ORDER))
+    return fail(PGSGD_ERR_INVALID_ARG, "unknown bits in params.flags");
+  if ((p->flags & PGSGD_FLAG_COUNT_AHEAD) && (p->flags & PGSGD_FLAG_COUNT_IN_ORDER))
+    return fail(PGSGD_ERR_INVALID_ARG, "params.flags: COUNT_AHEAD and COUNT_IN_ORDER exclude each other");
   if (p->reuse_factor > 16) return fail(PGSGD_ERR_INVALID_ARG, "reuse_factor must be at most 16");
   if (p->schedule > PGSGD_SCHEDULE_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
   if ((p->reuse_factor > 1 || p->step_reduction > 1) && p->schedule == PGSGD_SCHEDULE_BINNED)
@@ -625,7 +640,8 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   if (g->d_lcount && g->loc_nwin == nwin && g->loc_shift == shift && g->loc_streams == streams) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
   for (void** q : {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
-                   (void**)&g->d_lorder, (void**)&g->d_lsbeg, (void**)&g->d_lwpath})
+                   (void**)&g->d_lorder, (void**)&g->d_lsbeg, (void**)&g->d_lwpath, (void**)&g->d_lcount2,
+                   (void**)&g->d_loff2, (void**)&g->d_lxitem2, (void**)&g->d_lqueue2})
     if (*q) {
       (void)hipFree(*q);
       *q = nullptr;
@@ -665,12 +681,30 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   if ((st = dev_alloc(g, &g->d_lorder, nwin))) return st;
   if ((st = dev_alloc(g, &g->d_lsbeg, runs + 1))) return st;
   if ((st = dev_alloc(g, &g->d_lwpath, nwin))) return st;
+  if ((st = dev_alloc(g, &g->d_lcount2, nwin))) return st;
+  if ((st = dev_alloc(g, &g->d_loff2, nwin + 1))) return st;
+  if ((st = dev_alloc(g, &g->d_lxitem2, (size_t)runs * g->loc_xstride))) return st;
+  if ((st = dev_alloc(g, &g->d_lqueue2, (size_t)runs * 16))) return st;
   HIP_TRY(hipMemcpy(g->d_lorder, order.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(g->d_lsbeg, sbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(g->d_lwpath, wpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
-  HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histogram must start at zero
+  HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histograms must start at zero
+  HIP_TRY(launch_fill_u32(g->d_lcount2, nwin, 0u, s));
   return PGSGD_OK;
 }
+
+// The counting stream and its events (created on first use).
+pgsgd_status ensure_count_stream(pgsgd_graph* g) {
+  if (g->count_stream) return PGSGD_OK;
+  HIP_TRY(hipStreamCreateWithFlags(&g->count_stream, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&g->ev_start, &g->ev_count[0], &g->ev_count[1], &g->ev_layout[0], &g->ev_layout[1]})
+    HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return PGSGD_OK;
+}
+
+// Iterations with at least this many terms count the next iteration on a
+// second stream (layout_impl).
+constexpr uint64_t kOverlapMinTerms = 1ull << 31;
 
 // Segments of the window-major sampled path stress: the windows of the
 // windowed schedule cut at path boundaries, in step order; run x (XCD x)
@@ -783,15 +817,23 @@ pgsgd_status local_plan(pgsgd_graph* g, const pgsgd_params* p, size_t lds, const
   return PGSGD_OK;
 }
 
-// One windowed iteration (W.L.iter, cool_all and eta set): counts and
-// offsets, run counters cleared, layout.  With e_mid set, an event is recorded
-// between the counting and the layout kernel.
+// The layout part of a windowed iteration whose counts and offsets are in W:
+// run counters cleared, layout kernel.  With e_mid set, an event is recorded
+// right before the layout kernel.
+hipError_t local_layout(const LocalLaunch& W, uint32_t blocks, uint32_t threads, hipStream_t s,
+                        hipEvent_t e_mid = nullptr) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(W.queue), 2ull * kXcds * W.streams * 16, 0u, s);
+  if (!e && e_mid) e = hipEventRecord(e_mid, s);
+  if (!e) e = launch_layout_local(W, blocks, threads, s);
+  return e;
+}
+
+// One windowed iteration (W.L.iter, cool_all and eta set) on one stream:
+// counts and offsets, then the layout part.
 hipError_t local_iteration(const LocalLaunch& W, uint32_t blocks, uint32_t threads, hipStream_t s,
                            hipEvent_t e_mid = nullptr) {
   hipError_t e = launch_local_count_scan(W, s);
-  if (!e) e = launch_fill_u32(reinterpret_cast<uint32_t*>(W.queue), 2ull * kXcds * W.streams * 16, 0u, s);
-  if (!e && e_mid) e = hipEventRecord(e_mid, s);
-  if (!e) e = launch_layout_local(W, blocks, threads, s);
+  if (!e) e = local_layout(W, blocks, threads, s, e_mid);
   return e;
 }
 
@@ -897,13 +939,56 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     }
   } events_free{ev};
   if (!tracing) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  // Windowed layouts of several iterations of at least kOverlapMinTerms
+  // terms count iteration it + 1 on the graph's counting stream while
+  // iteration it is laid out, alternating between two count/offset sets: a
+  // set is rewritten only after the layout that read it (two iterations
+  // earlier) has finished.  On smaller graphs the counting blocks slow the
+  // short layout launches down more than they save, so the passes stay in
+  // order there.
+  const bool ahead = (p->flags & PGSGD_FLAG_COUNT_AHEAD) ||
+                     (!(p->flags & PGSGD_FLAG_COUNT_IN_ORDER) && W.L.n_terms >= kOverlapMinTerms);
+  const bool overlap = windowed && !tracing && n_run > 1 && ahead;
+  LocalLaunch Wset[2] = {W, W};
+  hipStream_t s2 = nullptr;
+  bool set_used[2] = {false, false};
+  auto count_into = [&](uint32_t it, uint32_t k) -> hipError_t {
+    LocalLaunch C = Wset[k];
+    C.L.iter = it;
+    hipError_t e = set_used[k] ? hipStreamWaitEvent(s2, g->ev_layout[k], 0) : hipSuccess;
+    if (!e) e = launch_local_count_scan(C, s2);
+    if (!e) e = hipEventRecord(g->ev_count[k], s2);
+    return e;
+  };
+  if (overlap) {
+    if ((st = ensure_count_stream(g))) return st;
+    s2 = g->count_stream;
+    Wset[1].wcount = g->d_lcount2;
+    Wset[1].woff = g->d_loff2;
+    Wset[1].xitem = g->d_lxitem2;
+    Wset[1].queue = g->d_lqueue2;
+    // the counting stream starts after all earlier work on the caller's stream
+    HIP_TRY(hipEventRecord(g->ev_start, s));
+    HIP_TRY(hipStreamWaitEvent(s2, g->ev_start, 0));
+    HIP_TRY(count_into(p->first_iter, 0));
+  }
   for (uint32_t it = p->first_iter; it < last; ++it) {
     const size_t e0 = (size_t)(it - p->first_iter) * ev_per_iter;
     L.iter = it;
     L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
     L.eta = eta[it];
     if (iter_ms) HIP_TRY(hipEventRecord(ev[e0], s));
-    if (windowed) {
+    if (overlap) {
+      const uint32_t k = (it - p->first_iter) & 1u;
+      HIP_TRY(hipStreamWaitEvent(s, g->ev_count[k], 0));
+      if (it + 1 < last) HIP_TRY(count_into(it + 1, k ^ 1u));
+      LocalLaunch Wi = Wset[k];
+      Wi.L = L;
+      HIP_TRY(local_layout(Wi, blocks, threads, s, iter_ms ? ev[e0 + 1] : nullptr));
+      HIP_TRY(hipEventRecord(g->ev_layout[k], s));
+      set_used[k] = true;
+      if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
+    } else if (windowed) {
       W.L = L;
       HIP_TRY(local_iteration(W, blocks, threads, s, iter_ms ? ev[e0 + 1] : nullptr));
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));

@@ -217,6 +217,24 @@ def test_windowed_split_run_equals_full_run(P, tiny):
     assert torch.equal(a, b)
 
 
+def test_windowed_count_ahead_equals_in_order(P, tiny):
+    # one wave makes the windowed layout deterministic: counting each next iteration on the
+    # graph's second stream must give exactly the coordinates of the in-order passes
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    a = torch.from_numpy(c0).cuda()
+    b = torch.from_numpy(c0).cuda()
+    P.layout(g, a, schedule=3, max_inflight_waves=1, flags=P.FLAG_COUNT_AHEAD)
+    P.layout(g, b, schedule=3, max_inflight_waves=1, flags=P.FLAG_COUNT_IN_ORDER)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert not torch.equal(a, torch.from_numpy(c0).cuda())
+    for bad in (P.FLAG_COUNT_AHEAD | P.FLAG_COUNT_IN_ORDER, 4):
+        with pytest.raises(P.PgsgdError):
+            P.layout(g, a, schedule=3, flags=bad)
+
+
 def test_windowed_sampling_many_short_paths(P):
     # 3,000 paths of 1-9 steps (windows of 2^8 steps span dozens of paths and take the
     # path search), plus empty paths, and S not a multiple of the window
