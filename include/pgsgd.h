@@ -356,7 +356,8 @@ pgsgd_status pgsgd_stress_forward(pgsgd_graph *g, const pgsgd_params *p, const f
  * grad_out_dev[0] * dL/dcoords into grad_coords (device, [2][n_nodes][2]
  * float32) with float32 atomics; dL/dv_a = (2/n_valid)(mag - d)/d^2 (v_a - v_b)/mag,
  * dL/dv_b = -dL/dv_a, zero when mag = 0.  n_valid_dev is the forward's count.
- * Async.
+ * Forward and backward read the graph's interleaved working copy of coords,
+ * so calls on one graph must be ordered on one stream.  Async.
  */
 pgsgd_status pgsgd_stress_backward(pgsgd_graph *g, const pgsgd_params *p, const float *coords, uint64_t n_pairs,
                                    uint32_t step, const float *grad_out_dev, const uint64_t *n_valid_dev,

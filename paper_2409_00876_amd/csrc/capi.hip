@@ -1288,6 +1288,8 @@ pgsgd_status pgsgd_stress_forward(pgsgd_graph* g, const pgsgd_params* p, const f
   P.W = p->zipf_window;
   P.word2 = step;
   P.count = g->S ? n_pairs : 0;
+  P.work = g->d_work;
+  if (P.count) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
   HIP_TRY(launch_stress_fwd(P, g->d_part_f, g->d_part_n, s));
   HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, kStressBlocks, nullptr, nullptr, nullptr, loss_dev,
                               n_valid_dev, s));
@@ -1312,6 +1314,8 @@ pgsgd_status pgsgd_stress_backward(pgsgd_graph* g, const pgsgd_params* p, const 
   P.W = p->zipf_window;
   P.word2 = step;
   P.count = n_pairs;
+  P.work = g->d_work;
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
   HIP_TRY(launch_stress_bwd(P, grad_out_dev, n_valid_dev, grad_coords, s));
   return ok();
 }

@@ -59,6 +59,16 @@ __device__ __forceinline__ double stress_fp64(const float* __restrict__ X, const
   return e * e;
 }
 
+// v_a - v_b from the interleaved copy in FP64; returns |v_a - v_b|.
+__device__ __forceinline__ double delta_work(const float2* __restrict__ W, uint64_t a, uint64_t b, double& dx,
+                                             double& dy) {
+#pragma clang fp contract(off)
+  const float2 va = W[a], vb = W[b];
+  dx = (double)va.x - (double)vb.x;
+  dy = (double)va.y - (double)vb.y;
+  return sqrt(dx * dx + dy * dy);
+}
+
 // The same value from the interleaved copy (W[e] = (x, y) of endpoint e).
 __device__ __forceinline__ double stress_work(const float2* __restrict__ W, uint64_t a, uint64_t b, double d) {
 #pragma clang fp contract(off)
@@ -439,8 +449,6 @@ __global__ __launch_bounds__(256) void k_stress_fwd(StressLaunch P, double* __re
   uint16_t* guide;
   fill_loss_lds(lds, P, off, zipf, guide);
   __syncthreads();
-  const float* __restrict__ X = P.coords;
-  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
   double acc = 0.0;
   uint64_t nv = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -448,8 +456,7 @@ __global__ __launch_bounds__(256) void k_stress_fwd(StressLaunch P, double* __re
     uint64_t a, b;
     double d;
     if (!loss_pair(P, off, zipf, guide, q, a, b, d)) continue;
-    double dx, dy, mag;
-    acc += stress_fp64(X, Y, a, b, d, dx, dy, mag);
+    acc += stress_work(P.work, a, b, d);
     ++nv;
   }
   acc = block_sum(acc, red_f);
@@ -460,6 +467,9 @@ __global__ __launch_bounds__(256) void k_stress_fwd(StressLaunch P, double* __re
   }
 }
 
+// The adjoint, scattered with float32 atomics into the planar gradient
+// (atomics are served per 4-byte word, so an interleaved scratch would not
+// make them cheaper); the coordinates come from the interleaved copy.
 __global__ __launch_bounds__(256) void k_stress_bwd(StressLaunch P, const float* __restrict__ grad_out,
                                                     const uint64_t* __restrict__ n_valid,
                                                     float* __restrict__ grad) {
@@ -472,20 +482,18 @@ __global__ __launch_bounds__(256) void k_stress_bwd(StressLaunch P, const float*
   const uint64_t n = n_valid[0];
   if (n == 0) return;
   const double scale = (double)grad_out[0] * 2.0 / (double)n;
-  const float* __restrict__ X = P.coords;
-  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
-  float* __restrict__ GX = grad;
-  float* __restrict__ GY = grad + 2ull * P.n_nodes;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.count; q += stride) {
     uint64_t a, b;
     double d;
     if (!loss_pair(P, off, zipf, guide, q, a, b, d)) continue;
-    double dx, dy, mag;
-    (void)stress_fp64(X, Y, a, b, d, dx, dy, mag);
+    double dx, dy;
+    const double mag = delta_work(P.work, a, b, dx, dy);
     if (mag == 0.0) continue;
     const double c = scale * (mag - d) / (d * d) / mag;
     const float gx = (float)(c * dx), gy = (float)(c * dy);
+    float* __restrict__ GX = grad;
+    float* __restrict__ GY = grad + 2ull * P.n_nodes;
     unsafeAtomicAdd(&GX[a], gx);
     unsafeAtomicAdd(&GY[a], gy);
     unsafeAtomicAdd(&GX[b], -gx);
