@@ -13,6 +13,7 @@ Bars (from the method's definition):
   - differentiable loss within 1e-5, gradient against the oracle's analytic
     FP64 gradient and FP64 finite differences.
 """
+import ctypes
 import glob
 import json
 import math
@@ -458,6 +459,32 @@ def test_sps_windowed_equals_oracle_on_edge_graphs(P, which):
         assert r["n_valid"] + r["n_skipped"] == m * og.S
         assert abs(r["sum"] - o["sum"]) <= 1e-9 * abs(o["sum"])
         assert abs(r["sumsq_dev"] - o["sumsq_dev"]) <= 1e-9 * abs(o["sumsq_dev"])
+
+
+def test_sps_mode_and_size_errors(P, tiny):
+    import torch
+    from paper_2409_00876_amd import _lib
+    sg, og, g = tiny
+    c = torch.from_numpy(O.init_coords(og)).cuda()
+    r = _lib.StressResult()
+    st = P.lib().pgsgd_path_stress_pairs(g.handle, ctypes.c_void_p(c.data_ptr()), 10, 7, 0, 3, 0.99, 1000,
+                                         ctypes.byref(r), None)
+    assert st == _lib.ERR_INVALID_ARG and "pair mode" in P.lib().pgsgd_last_error().decode()
+    # 32-bit segment counts: pairs_per_step * 2^(h + 1) must stay below 2^32
+    with pytest.raises(P.PgsgdError, match="32-bit"):
+        P.path_stress(g, c, 1 << 23, 7, pairs="uniform_windowed")
+    # 16,000 two-step paths: the path table fits the LDS of the uniform order, the segment
+    # histogram beside it does not
+    n_paths = 16000
+    sg2 = synth.SynthGraph(np.full(100, 5, np.uint32), (2 * np.arange(n_paths + 1)).astype(np.uint64),
+                           (np.arange(2 * n_paths) % 100).astype(np.uint32), {}, "many-paths")
+    og2, g2 = O.Graph.from_synth(sg2), P.Graph.from_synth(sg2)
+    c2 = torch.from_numpy(O.init_coords(og2)).cuda()
+    r2 = P.path_stress(g2, c2, 3, 7)
+    o2 = O.sampled_path_stress(og2, c2.cpu().numpy(), 3, 7)
+    assert r2["n_valid"] == o2["n_valid"] and r2["n_skipped"] == o2["n_skipped"]
+    with pytest.raises(P.PgsgdError, match="segment histogram"):
+        P.path_stress(g2, c2, 3, 7, pairs="uniform_windowed")
 
 
 def test_sps_windowed_agrees_with_uniform_order_on_chromosome(P, chromosome):
