@@ -1260,6 +1260,8 @@ pgsgd_status pgsgd_path_stress_exact(pgsgd_graph* g, const float* coords, double
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
   StressLaunch P = make_stress_launch(g, coords, kStreamSps, 0, 0);
+  P.work = g->d_work;
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
   HIP_TRY(launch_path_stress_exact(P, g->d_part_f, g->d_part_n, s));
   HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, kStressBlocks, g->d_out_f, g->d_out_n, nullptr,
                               nullptr, nullptr, s));

@@ -49,12 +49,12 @@ __device__ __forceinline__ bool pair_terms(const StepRec* __restrict__ rec, uint
   return dd != 0;
 }
 
-__device__ __forceinline__ double stress_fp64(const float* __restrict__ X, const float* __restrict__ Y, uint64_t a,
-                                              uint64_t b, double d, double& dx, double& dy, double& mag) {
+// ((|v_a - v_b| - d)/d)^2 in FP64 from the two endpoints' float32 coordinates.
+__device__ __forceinline__ double stress_xy(float xa, float ya, float xb, float yb, double d) {
 #pragma clang fp contract(off)
-  dx = (double)X[a] - (double)X[b];
-  dy = (double)Y[a] - (double)Y[b];
-  mag = sqrt(dx * dx + dy * dy);
+  const double dx = (double)xa - (double)xb;
+  const double dy = (double)ya - (double)yb;
+  const double mag = sqrt(dx * dx + dy * dy);
   const double e = (mag - d) / d;
   return e * e;
 }
@@ -69,15 +69,10 @@ __device__ __forceinline__ double delta_work(const float2* __restrict__ W, uint6
   return sqrt(dx * dx + dy * dy);
 }
 
-// The same value from the interleaved copy (W[e] = (x, y) of endpoint e).
+// The stress of endpoints a and b of the interleaved copy (W[e] = (x, y) of endpoint e).
 __device__ __forceinline__ double stress_work(const float2* __restrict__ W, uint64_t a, uint64_t b, double d) {
-#pragma clang fp contract(off)
   const float2 va = W[a], vb = W[b];
-  const double dx = (double)va.x - (double)vb.x;
-  const double dy = (double)va.y - (double)vb.y;
-  const double mag = sqrt(dx * dx + dy * dy);
-  const double e = (mag - d) / d;
-  return e * e;
+  return stress_xy(va.x, va.y, vb.x, vb.y, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,8 +341,8 @@ __global__ __launch_bounds__(256) void k_path_stress_exact(StressLaunch P, doubl
   __shared__ uint64_t red_n[16];
   fill_offsets(off, P);
   __syncthreads();
-  const float* __restrict__ X = P.coords;
-  const float* __restrict__ Y = P.coords + 2ull * P.n_nodes;
+  // both endpoints of a node are 16 contiguous bytes of the interleaved copy
+  const float4* __restrict__ W4 = reinterpret_cast<const float4*>(P.work);
   double acc = 0.0;
   uint64_t np = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -355,18 +350,18 @@ __global__ __launch_bounds__(256) void k_path_stress_exact(StressLaunch P, doubl
     const uint32_t p = find_path(off, P.path_top, i);
     const uint64_t end = off[p + 1];
     const StepRec si = load_rec(P.rec, i);
+    const float4 ci = W4[si.node_rev & kNodeMask];
     for (uint64_t j = i + 1; j < end; ++j) {
       const StepRec sj = load_rec(P.rec, j);
+      const float4 cj = W4[sj.node_rev & kNodeMask];
       double sum = 0.0;
       uint32_t nv = 0;
       for (uint32_t e = 0; e < 4; ++e) {
         const uint32_t ei = e & 1u, ej = e >> 1;
         const int64_t dd = endpoint_pos(si, ei) - endpoint_pos(sj, ej);
         if (dd == 0) continue;
-        const uint64_t a = 2ull * (si.node_rev & kNodeMask) + ei;
-        const uint64_t b = 2ull * (sj.node_rev & kNodeMask) + ej;
-        double dx, dy, mag;
-        sum += stress_fp64(X, Y, a, b, (double)(dd < 0 ? -dd : dd), dx, dy, mag);
+        sum += stress_xy(ei ? ci.z : ci.x, ei ? ci.w : ci.y, ej ? cj.z : cj.x, ej ? cj.w : cj.y,
+                         (double)(dd < 0 ? -dd : dd));
         ++nv;
       }
       if (nv) {
