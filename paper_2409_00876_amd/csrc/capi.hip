@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <new>
 #include <string>
@@ -208,6 +209,18 @@ pgsgd_status dev_alloc(pgsgd_graph* g, T** p, size_t count) {
   }
   g->device_bytes += bytes;
   return PGSGD_OK;
+}
+
+// Frees a set of lazily allocated device buffers and nulls their pointers.
+// The ensure_* functions below free their whole set when any allocation or
+// copy fails, so a later call never finds a partly built set behind a
+// non-null first pointer.
+void free_set(std::initializer_list<void**> set) {
+  for (void** q : set)
+    if (*q) {
+      (void)hipFree(*q);
+      *q = nullptr;
+    }
 }
 
 // Ensures the graph holds the power-law table for (theta, W) on the device.
@@ -608,25 +621,26 @@ pgsgd_status ensure_bins(pgsgd_graph* g, uint64_t n_terms, hipStream_t s) {
   const uint32_t nwin = (uint32_t)((g->S + (1ull << shift) - 1) >> shift);
   if (g->d_tag && g->bin_chunk >= chunk && g->bin_nwin == nwin) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
-  for (void** q : {(void**)&g->d_tag, (void**)&g->d_entries, (void**)&g->d_wcount, (void**)&g->d_woff,
-                   (void**)&g->d_cursor, (void**)&g->d_xitem})
-    if (*q) {
-      (void)hipFree(*q);
-      *q = nullptr;
-    }
+  const auto set = {(void**)&g->d_tag, (void**)&g->d_entries, (void**)&g->d_wcount, (void**)&g->d_woff,
+                    (void**)&g->d_cursor, (void**)&g->d_xitem};
+  free_set(set);
   g->bin_chunk = chunk;
   g->bin_nwin = nwin;
   g->bin_shift = shift;
   g->bin_xstride = nwin / kXcds + 2;
-  pgsgd_status st;
-  if ((st = dev_alloc(g, &g->d_tag, chunk))) return st;
-  if ((st = dev_alloc(g, &g->d_entries, chunk))) return st;
-  if ((st = dev_alloc(g, &g->d_wcount, nwin))) return st;
-  if ((st = dev_alloc(g, &g->d_woff, nwin + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_cursor, nwin))) return st;
-  if ((st = dev_alloc(g, &g->d_xitem, (size_t)kXcds * g->bin_xstride))) return st;
-  HIP_TRY(launch_fill_u32(g->d_wcount, nwin, 0u, s));  // the histogram must start at zero
-  return PGSGD_OK;
+  const pgsgd_status st = [&]() -> pgsgd_status {
+    pgsgd_status e;
+    if ((e = dev_alloc(g, &g->d_tag, chunk))) return e;
+    if ((e = dev_alloc(g, &g->d_entries, chunk))) return e;
+    if ((e = dev_alloc(g, &g->d_wcount, nwin))) return e;
+    if ((e = dev_alloc(g, &g->d_woff, nwin + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_cursor, nwin))) return e;
+    if ((e = dev_alloc(g, &g->d_xitem, (size_t)kXcds * g->bin_xstride))) return e;
+    HIP_TRY(launch_fill_u32(g->d_wcount, nwin, 0u, s));  // the histogram must start at zero
+    return PGSGD_OK;
+  }();
+  if (st) free_set(set);
+  return st;
 }
 
 // Window-major scratch: windows of 2^window_shift(S) steps, grouped into
@@ -639,13 +653,10 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
                 g->lds_limit);
   if (g->d_lcount && g->loc_nwin == nwin && g->loc_shift == shift && g->loc_streams == streams) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
-  for (void** q : {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
-                   (void**)&g->d_lorder, (void**)&g->d_lsbeg, (void**)&g->d_lwpath, (void**)&g->d_lcount2,
-                   (void**)&g->d_loff2, (void**)&g->d_lxitem2, (void**)&g->d_lqueue2})
-    if (*q) {
-      (void)hipFree(*q);
-      *q = nullptr;
-    }
+  const auto set = {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
+                    (void**)&g->d_lorder, (void**)&g->d_lsbeg, (void**)&g->d_lwpath, (void**)&g->d_lcount2,
+                    (void**)&g->d_loff2, (void**)&g->d_lxitem2, (void**)&g->d_lqueue2};
+  free_set(set);
   g->loc_nwin = nwin;
   g->loc_shift = shift;
   g->loc_streams = streams;
@@ -673,32 +684,39 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   uint32_t longest = 0;
   for (uint32_t r = 0; r < runs; ++r) longest = std::max(longest, sbeg[r + 1] - sbeg[r]);
   g->loc_xstride = longest + 1;
-  pgsgd_status st;
-  if ((st = dev_alloc(g, &g->d_lcount, nwin))) return st;
-  if ((st = dev_alloc(g, &g->d_loff, nwin + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_lxitem, (size_t)runs * g->loc_xstride))) return st;
-  if ((st = dev_alloc(g, &g->d_lqueue, (size_t)runs * 16))) return st;
-  if ((st = dev_alloc(g, &g->d_lorder, nwin))) return st;
-  if ((st = dev_alloc(g, &g->d_lsbeg, runs + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_lwpath, nwin))) return st;
-  if ((st = dev_alloc(g, &g->d_lcount2, nwin))) return st;
-  if ((st = dev_alloc(g, &g->d_loff2, nwin + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_lxitem2, (size_t)runs * g->loc_xstride))) return st;
-  if ((st = dev_alloc(g, &g->d_lqueue2, (size_t)runs * 16))) return st;
-  HIP_TRY(hipMemcpy(g->d_lorder, order.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(g->d_lsbeg, sbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(g->d_lwpath, wpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
-  HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histograms must start at zero
-  HIP_TRY(launch_fill_u32(g->d_lcount2, nwin, 0u, s));
-  return PGSGD_OK;
+  const pgsgd_status st = [&]() -> pgsgd_status {
+    pgsgd_status e;
+    if ((e = dev_alloc(g, &g->d_lcount, nwin))) return e;
+    if ((e = dev_alloc(g, &g->d_loff, nwin + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_lxitem, (size_t)runs * g->loc_xstride))) return e;
+    if ((e = dev_alloc(g, &g->d_lqueue, (size_t)runs * 16))) return e;
+    if ((e = dev_alloc(g, &g->d_lorder, nwin))) return e;
+    if ((e = dev_alloc(g, &g->d_lsbeg, runs + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_lwpath, nwin))) return e;
+    if ((e = dev_alloc(g, &g->d_lcount2, nwin))) return e;
+    if ((e = dev_alloc(g, &g->d_loff2, nwin + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_lxitem2, (size_t)runs * g->loc_xstride))) return e;
+    if ((e = dev_alloc(g, &g->d_lqueue2, (size_t)runs * 16))) return e;
+    HIP_TRY(hipMemcpy(g->d_lorder, order.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_lsbeg, sbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_lwpath, wpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
+    HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histograms must start at zero
+    HIP_TRY(launch_fill_u32(g->d_lcount2, nwin, 0u, s));
+    return PGSGD_OK;
+  }();
+  if (st) free_set(set);
+  return st;
 }
 
 // The counting stream and its events (created on first use).
+// The stream is set last, so a failed creation leaves no half-made set behind it.
 pgsgd_status ensure_count_stream(pgsgd_graph* g) {
   if (g->count_stream) return PGSGD_OK;
-  HIP_TRY(hipStreamCreateWithFlags(&g->count_stream, hipStreamNonBlocking));
   for (hipEvent_t* e : {&g->ev_start, &g->ev_count[0], &g->ev_count[1], &g->ev_layout[0], &g->ev_layout[1]})
-    HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  hipStream_t st = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  g->count_stream = st;
   return PGSGD_OK;
 }
 
@@ -713,12 +731,9 @@ pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
   const uint32_t shift = window_shift(g->S);
   if (g->d_sseg_start && g->sps_shift == shift) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
-  for (void** q : {(void**)&g->d_sseg_start, (void**)&g->d_sseg_path, (void**)&g->d_swseg, (void**)&g->d_scount,
-                   (void**)&g->d_soff, (void**)&g->d_ssbeg, (void**)&g->d_sxitem, (void**)&g->d_squeue})
-    if (*q) {
-      (void)hipFree(*q);
-      *q = nullptr;
-    }
+  const auto set = {(void**)&g->d_sseg_start, (void**)&g->d_sseg_path, (void**)&g->d_swseg, (void**)&g->d_scount,
+                    (void**)&g->d_soff, (void**)&g->d_ssbeg, (void**)&g->d_sxitem, (void**)&g->d_squeue};
+  free_set(set);
   const uint64_t nwin = (g->S + (1ull << shift) - 1) >> shift;
   std::vector<uint64_t> start;
   std::vector<uint32_t> path;
@@ -746,21 +761,25 @@ pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
   g->sps_shift = shift;
   g->sps_nseg = (uint32_t)nseg;
   g->sps_xstride = longest + 1;
-  pgsgd_status st;
-  if ((st = dev_alloc(g, &g->d_sseg_start, nseg + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_sseg_path, nseg))) return st;
-  if ((st = dev_alloc(g, &g->d_swseg, nwin + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_scount, nseg))) return st;
-  if ((st = dev_alloc(g, &g->d_soff, nseg + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_ssbeg, kXcds + 1))) return st;
-  if ((st = dev_alloc(g, &g->d_sxitem, (size_t)kXcds * g->sps_xstride))) return st;
-  if ((st = dev_alloc(g, &g->d_squeue, (size_t)2 * kXcds * 16))) return st;
-  HIP_TRY(hipMemcpy(g->d_sseg_start, start.data(), sizeof(uint64_t) * (nseg + 1), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(g->d_sseg_path, path.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(g->d_swseg, wseg.data(), sizeof(uint32_t) * (nwin + 1), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(g->d_ssbeg, sbeg.data(), sizeof(uint32_t) * (kXcds + 1), hipMemcpyHostToDevice));
-  HIP_TRY(launch_fill_u32(g->d_scount, nseg, 0u, s));  // the histogram must start at zero
-  return PGSGD_OK;
+  const pgsgd_status st = [&]() -> pgsgd_status {
+    pgsgd_status e;
+    if ((e = dev_alloc(g, &g->d_sseg_start, nseg + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_sseg_path, nseg))) return e;
+    if ((e = dev_alloc(g, &g->d_swseg, nwin + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_scount, nseg))) return e;
+    if ((e = dev_alloc(g, &g->d_soff, nseg + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_ssbeg, kXcds + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_sxitem, (size_t)kXcds * g->sps_xstride))) return e;
+    if ((e = dev_alloc(g, &g->d_squeue, (size_t)2 * kXcds * 16))) return e;
+    HIP_TRY(hipMemcpy(g->d_sseg_start, start.data(), sizeof(uint64_t) * (nseg + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_sseg_path, path.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_swseg, wseg.data(), sizeof(uint32_t) * (nwin + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_ssbeg, sbeg.data(), sizeof(uint32_t) * (kXcds + 1), hipMemcpyHostToDevice));
+    HIP_TRY(launch_fill_u32(g->d_scount, nseg, 0u, s));  // the histogram must start at zero
+    return PGSGD_OK;
+  }();
+  if (st) free_set(set);
+  return st;
 }
 
 // Automatic wave cap of the windowed schedule (see kLocalNodesPerWave).
