@@ -18,6 +18,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pgsgd.h"
@@ -139,6 +140,7 @@ struct pgsgd_graph {
   uint64_t* d_out_n = nullptr;  // [4]
   double* d_mean = nullptr;
   size_t device_bytes = 0;
+  std::unordered_map<void*, size_t> alloc_bytes;  // size of every lazily allocated buffer
   int layout_blocks_per_cu = 0;  // occupancy of k_layout_iter, filled on first use
   int bin_blocks_per_cu = 0;     // occupancy of k_bin_layout, filled on first use
   // binning scratch (allocated on first binned layout)
@@ -208,6 +210,7 @@ pgsgd_status dev_alloc(pgsgd_graph* g, T** p, size_t count) {
                 bytes, hipGetErrorString(e));
   }
   g->device_bytes += bytes;
+  g->alloc_bytes[(void*)*p] = bytes;
   return PGSGD_OK;
 }
 
@@ -215,9 +218,14 @@ pgsgd_status dev_alloc(pgsgd_graph* g, T** p, size_t count) {
 // The ensure_* functions below free their whole set when any allocation or
 // copy fails, so a later call never finds a partly built set behind a
 // non-null first pointer.
-void free_set(std::initializer_list<void**> set) {
+void free_set(pgsgd_graph* g, std::initializer_list<void**> set) {
   for (void** q : set)
     if (*q) {
+      auto it = g->alloc_bytes.find(*q);
+      if (it != g->alloc_bytes.end()) {
+        g->device_bytes -= it->second;
+        g->alloc_bytes.erase(it);
+      }
       (void)hipFree(*q);
       *q = nullptr;
     }
@@ -623,7 +631,7 @@ pgsgd_status ensure_bins(pgsgd_graph* g, uint64_t n_terms, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
   const auto set = {(void**)&g->d_tag, (void**)&g->d_entries, (void**)&g->d_wcount, (void**)&g->d_woff,
                     (void**)&g->d_cursor, (void**)&g->d_xitem};
-  free_set(set);
+  free_set(g, set);
   g->bin_chunk = chunk;
   g->bin_nwin = nwin;
   g->bin_shift = shift;
@@ -639,7 +647,7 @@ pgsgd_status ensure_bins(pgsgd_graph* g, uint64_t n_terms, hipStream_t s) {
     HIP_TRY(launch_fill_u32(g->d_wcount, nwin, 0u, s));  // the histogram must start at zero
     return PGSGD_OK;
   }();
-  if (st) free_set(set);
+  if (st) free_set(g, set);
   return st;
 }
 
@@ -656,7 +664,7 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   const auto set = {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
                     (void**)&g->d_lorder, (void**)&g->d_lsbeg, (void**)&g->d_lwpath, (void**)&g->d_lcount2,
                     (void**)&g->d_loff2, (void**)&g->d_lxitem2, (void**)&g->d_lqueue2};
-  free_set(set);
+  free_set(g, set);
   g->loc_nwin = nwin;
   g->loc_shift = shift;
   g->loc_streams = streams;
@@ -704,7 +712,7 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
     HIP_TRY(launch_fill_u32(g->d_lcount2, nwin, 0u, s));
     return PGSGD_OK;
   }();
-  if (st) free_set(set);
+  if (st) free_set(g, set);
   return st;
 }
 
@@ -733,7 +741,7 @@ pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
   const auto set = {(void**)&g->d_sseg_start, (void**)&g->d_sseg_path, (void**)&g->d_swseg, (void**)&g->d_scount,
                     (void**)&g->d_soff, (void**)&g->d_ssbeg, (void**)&g->d_sxitem, (void**)&g->d_squeue};
-  free_set(set);
+  free_set(g, set);
   const uint64_t nwin = (g->S + (1ull << shift) - 1) >> shift;
   std::vector<uint64_t> start;
   std::vector<uint32_t> path;
@@ -778,7 +786,7 @@ pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
     HIP_TRY(launch_fill_u32(g->d_scount, nseg, 0u, s));  // the histogram must start at zero
     return PGSGD_OK;
   }();
-  if (st) free_set(set);
+  if (st) free_set(g, set);
   return st;
 }
 
