@@ -461,6 +461,26 @@ def test_sps_windowed_equals_oracle_on_edge_graphs(P, which):
         assert abs(r["sumsq_dev"] - o["sumsq_dev"]) <= 1e-9 * abs(o["sumsq_dev"])
 
 
+def test_graph_without_steps(P):
+    # two nodes and two empty paths: every call succeeds and leaves the coordinates alone
+    import torch
+    sg = synth.SynthGraph(np.array([3, 4], np.uint32), np.zeros(3, np.uint64), np.zeros(0, np.uint32), {}, "empty")
+    g = P.Graph.from_synth(sg)
+    assert g.n_steps == 0
+    c = torch.arange(8, dtype=torch.float32, device="cuda")
+    before = c.clone()
+    for sched in (0, 1, 2, 3):
+        P.layout(g, c, schedule=sched)
+    for pairs in ("uniform", "uniform_windowed", "power_law"):
+        r = P.path_stress(g, c, 10, 7, pairs=pairs)
+        assert r["n_valid"] == 0 and r["n_skipped"] == 0 and r["mean"] == 0.0
+    assert P.path_stress_exact(g, c) == (0.0, 0)
+    loss, nv = P.stress_forward(g, c, 1000, 1)
+    assert float(loss) == 0.0 and int(nv) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(c, before)
+
+
 def test_sps_mode_and_size_errors(P, tiny):
     import torch
     from paper_2409_00876_amd import _lib
