@@ -245,9 +245,15 @@ pgsgd_status pgsgd_init_coords(pgsgd_graph *g, uint64_t seed, uint32_t graph_id,
  *   terms with the same coordinate slot, d_ref = 0 or coincident points are
  *        skipped; otherwise mu = min(eta / d^2, 1) and both points move by
  *        mu * (|v_i - v_j| - d) / 2 towards (or away from) each other.
- * Async.  A graph with S = 0 returns OK without work.
+ * The schedule (PGSGD_SCHEDULE_*) sets the order in which an iteration's
+ * terms are processed.  Async on stream: work the call places on the graph's
+ * own counting stream (see pgsgd_params.flags) starts after the work already
+ * on stream and is joined back into stream before the call's last kernel, so
+ * stream order holds.  The graph's scratch buffers and working copy are
+ * shared by all calls on the graph: order them on one stream.  A graph with
+ * S = 0 returns OK without work.
  * Errors: INVALID_ARG (NULL, unknown or conflicting flags, zipf_window out of range, graph_id >=
- * 2^24, first_iter > last_iter), RANGE (term count >= 2^48), DEVICE.
+ * 2^24, first_iter > last_iter), RANGE (term count >= 2^48), UNSUPPORTED (LDS limits), DEVICE, OOM.
  */
 pgsgd_status pgsgd_layout(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);
 
