@@ -184,7 +184,7 @@ enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
  *            pieces, XCD x takes piece x of every path), a window at a time
  *            per XCD, so its step records and the coordinates of the nodes
  *            it visits stay in the XCD's L2.  max_inflight_waves caps the
- *            waves (automatic: about nodes_w / 12, nodes_w = 2^h * n_nodes *
+ *            waves (automatic: about nodes_w / 8, nodes_w = 2^h * n_nodes *
  *            n_paths / S the nodes a window visits, at most the PLAIN cap).
  *            Uniform-partner updates read the partner first and the window-
  *            local endpoint after it arrived, which keeps the window in which

@@ -16,12 +16,12 @@ constexpr uint32_t kLocalMaxWindows = 32768;
 constexpr uint32_t kLocalStreams = 1;       // runs per XCD worked on at the same time
 constexpr uint32_t kLocalMaxStreams = 16;
 constexpr uint32_t kLocalGrab = 4;          // items a wave takes from its run's counter at once
-// Automatic wave cap: waves <= nodes_w / 12, nodes_w ~ 2^shift * n_nodes *
-// n_paths / S the nodes a window visits (an XCD's in-flight terms then stay
-// below about two thirds of its window's nodes), never above the plain cap.
+// Automatic wave cap: waves <= nodes_w / 8, nodes_w ~ 2^shift * n_nodes *
+// n_paths / S the node ids a window spans (an XCD's in-flight terms then
+// number about as many as its window's node ids), never above the plain cap.
 // With the far-first update order of uniform-partner terms, layout quality on
 // locality-ordered graphs is flat up to this cap.
-constexpr uint64_t kLocalNodesPerWave = 12;
+constexpr uint64_t kLocalNodesPerWave = 8;
 
 // log2 of the window length for S steps: 2^14, halved while there would be
 // fewer than 16 windows (not below 2^6), doubled while there would be more
