@@ -32,6 +32,22 @@ def test_library_exports_every_declared_symbol():
     assert P.lib().pgsgd_version().startswith(b"pgsgd-gfx950")
 
 
+def test_binding_constants_match_the_header():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    declared = {name: int(val) for name, val in re.findall(r"\b(PGSGD_[A-Z_]+)\s*=\s*(-?\d+)", text)}
+    binding = {"PGSGD_OK": _lib.OK, "PGSGD_ERR_INVALID_ARG": _lib.ERR_INVALID_ARG, "PGSGD_ERR_RANGE": _lib.ERR_RANGE,
+               "PGSGD_ERR_OOM": _lib.ERR_OOM, "PGSGD_ERR_DEVICE": _lib.ERR_DEVICE,
+               "PGSGD_ERR_UNSUPPORTED": _lib.ERR_UNSUPPORTED,
+               "PGSGD_SCHEDULE_AUTO": _lib.SCHEDULE_AUTO, "PGSGD_SCHEDULE_PLAIN": _lib.SCHEDULE_PLAIN,
+               "PGSGD_SCHEDULE_BINNED": _lib.SCHEDULE_BINNED, "PGSGD_SCHEDULE_WINDOWED": _lib.SCHEDULE_WINDOWED,
+               "PGSGD_PAIRS_UNIFORM": _lib.PAIRS_UNIFORM, "PGSGD_PAIRS_POWER_LAW": _lib.PAIRS_POWER_LAW,
+               "PGSGD_PAIRS_UNIFORM_WINDOWED": _lib.PAIRS_UNIFORM_WINDOWED,
+               "PGSGD_FLAG_COUNT_AHEAD": _lib.FLAG_COUNT_AHEAD, "PGSGD_FLAG_COUNT_IN_ORDER": _lib.FLAG_COUNT_IN_ORDER}
+    for name, val in declared.items():
+        assert name in binding, f"{name} declared in pgsgd.h but missing from the binding"
+        assert binding[name] == val, f"{name}: header {val}, binding {binding[name]}"
+
+
 def test_params_default_matches_paper_settings():
     p = _lib.Params()
     P.lib().pgsgd_params_default(ctypes.byref(p))
