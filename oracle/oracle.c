@@ -35,6 +35,11 @@
  *       are skipped (still counted as sampled terms).
  *   R9  sampled path stress draws exactly m*|p| uniform pairs per path,
  *       excludes pairs with d = 0 and pools all paths (Eq. 2).
+ *   R17 the data-reuse variant (described in words only) on the plain order.
+ *   R18 the window-major order of an iteration's terms (same law of terms).
+ *   R19 a sampled stress with the power-law partner instead of a uniform one.
+ *   R20 the data-reuse variant on the window-major order.
+ *   R21 Eq. 2's pairs visited in window-major order (same law of pairs).
  */
 #include <math.h>
 #include <pthread.h>
