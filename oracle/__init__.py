@@ -62,6 +62,8 @@ def _load():
         "or_reuse_offsets": ([u64, u32, u32, u64, u32, P], None),
         "or_layout_reuse": ([P, u32, u32, u32, u32, f64, f64, f64, u32, u64, u32, u32, u32, P], u64),
         "or_apply_terms_f32": ([P, f64, P, P, P, u64, P], u64),
+        "or_apply_terms_f64_scaled": ([P, f64, f64, P, P, P, u64, P], u64),
+        "or_sampled_path_stress_threaded": ([P, P, u32, u64, u32, u32, u32, P, P], None),
         "or_window_shift": ([u64], u32),
         "or_window_counts": ([P, u64, u32, u32, u64, P, u32], None),
         "or_sample_terms_windowed": ([P, u32, f64, u32, u64, u32, u32, P, u64, u64, P, P, P], None),
@@ -280,6 +282,17 @@ def apply_terms_f64(g: Graph, eta: float, i, j, flags, coords64: np.ndarray) -> 
     return int(_load().or_apply_terms_f64(g._h, float(eta), _p(i), _p(j), _p(flags), len(i), _p(coords64)))
 
 
+def apply_terms_f64_scaled(g: Graph, eta: float, r_scale: float, i, j, flags, coords64: np.ndarray) -> int:
+    """apply_terms_f64 with every update's r multiplied by r_scale: a planted error, used only to
+    measure the resolution of the batch check."""
+    assert coords64.dtype == np.float64 and coords64.flags.c_contiguous
+    i = np.ascontiguousarray(i, dtype=np.uint64)
+    j = np.ascontiguousarray(j, dtype=np.uint64)
+    flags = np.ascontiguousarray(flags, dtype=np.uint8)
+    return int(_load().or_apply_terms_f64_scaled(g._h, float(eta), float(r_scale), _p(i), _p(j), _p(flags), len(i),
+                                                 _p(coords64)))
+
+
 def apply_terms_f32(g: Graph, eta: float, i, j, flags, coords: np.ndarray) -> int:
     assert coords.dtype == np.float32 and coords.flags.c_contiguous
     i = np.ascontiguousarray(i, dtype=np.uint64)
@@ -292,13 +305,17 @@ def apply_terms_f32(g: Graph, eta: float, i, j, flags, coords: np.ndarray) -> in
 # Metrics (Eq. 1, Eq. 2)
 # ---------------------------------------------------------------------------
 def sampled_path_stress(g: Graph, coords: np.ndarray, m: int = 100, seed: int = 7, graph_id: int = 0,
-                        pairs: str = "uniform", theta: float = 0.99, window: int = 1000) -> dict:
+                        pairs: str = "uniform", theta: float = 0.99, window: int = 1000, threads: int = 1) -> dict:
     """Eq. 2 with its CI95; pairs="power_law" takes the cooling phase's partner (reading R19),
-    pairs="uniform_windowed" lists the uniform pairs' law window-major (reading R21)."""
+    pairs="uniform_windowed" lists the uniform pairs' law window-major (reading R21).  threads > 1
+    evaluates the uniform orders on that many host threads (the same pairs; sums in another order)."""
     coords = np.ascontiguousarray(coords, dtype=np.float32)
     out = np.zeros(6, dtype=np.float64)
     cnt = np.zeros(2, dtype=np.uint64)
-    if pairs == "uniform":
+    if threads > 1 and pairs in ("uniform", "uniform_windowed"):
+        _load().or_sampled_path_stress_threaded(g._h, _p(coords), int(m), int(seed), int(graph_id),
+                                                0 if pairs == "uniform" else 1, int(threads), _p(out), _p(cnt))
+    elif pairs == "uniform":
         _load().or_sampled_path_stress(g._h, _p(coords), int(m), int(seed), int(graph_id), _p(out), _p(cnt))
     elif pairs == "power_law":
         _load().or_sampled_path_stress_pairs(g._h, _p(coords), int(m), int(seed), int(graph_id), 1, float(theta),

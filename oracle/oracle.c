@@ -449,6 +449,31 @@ uint64_t or_apply_terms_f64(const or_graph *g, double eta, const uint64_t *i, co
   return applied;
 }
 
+/* The FP64 batch with every update's r multiplied by r_scale: a deliberately
+ * wrong update, used only to measure how small an error of the update the
+ * batch check can detect (r_scale = 1 is or_apply_terms_f64). */
+uint64_t or_apply_terms_f64_scaled(const or_graph *g, double eta, double r_scale, const uint64_t *i,
+                                   const uint64_t *j, const uint8_t *flags, uint64_t count, double *coords64) {
+  double *X = coords64, *Y = coords64 + 2ull * g->n_nodes;
+  uint64_t applied = 0;
+  for (uint64_t k = 0; k < count; ++k) {
+    if (flags[k] & 8u) continue;
+    uint64_t a = 2ull * step_node_id(g, i[k]) + (flags[k] & 1u);
+    uint64_t b = 2ull * step_node_id(g, j[k]) + ((flags[k] >> 1) & 1u);
+    double d = (double)term_distance(g, i[k], j[k], flags[k]);
+    double dx = X[a] - X[b], dy = Y[a] - Y[b];
+    double mag = sqrt(dx * dx + dy * dy);
+    if (mag == 0.0) continue;
+    double mu = eta / (d * d);
+    if (mu > 1.0) mu = 1.0;
+    double r = r_scale * mu * (mag - d) / (2.0 * mag);
+    X[a] -= r * dx; Y[a] -= r * dy;
+    X[b] += r * dx; Y[b] += r * dy;
+    ++applied;
+  }
+  return applied;
+}
+
 /* Same, with FP32 storage and FP64 math (what one oracle term does). */
 uint64_t or_apply_terms_f32(const or_graph *g, double eta, const uint64_t *i, const uint64_t *j,
                             const uint8_t *flags, uint64_t count, float *coords) {
@@ -979,6 +1004,131 @@ void or_sampled_path_stress(const or_graph *g, const float *coords, uint32_t m, 
       if (valid) dev += (s - mean) * (s - mean);
     }
   }
+  double sd = n > 1 ? sqrt(dev / (double)(n - 1)) : 0.0;
+  double half = n ? 1.96 * sd / sqrt((double)n) : 0.0;
+  out[0] = mean; out[1] = mean - half; out[2] = mean + half; out[3] = sd; out[4] = sum; out[5] = dev;
+  counts[0] = n; counts[1] = skipped;
+}
+
+/* ---------------------------------------------------------------------------
+ * Eq. 2 evaluated by several threads, for the stored results of large
+ * layouts: exactly the pairs of or_sampled_path_stress (order 0, pair index q
+ * over [0, m*S), path p holding q in [m*off[p], m*off[p+1])) or of
+ * or_sampled_path_stress_windowed (order 1, slot index u over [0, m*S)).  The
+ * index range is cut into one contiguous piece per thread; each thread sums
+ * its piece in FP64 and the pieces are added in thread order, so only the
+ * rounding of the sums differs from the one-thread evaluation (the pairs,
+ * n_valid and n_skipped are the same).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const or_graph *g; const float *coords; uint32_t m, graph_id, order; uint64_t seed;
+  uint64_t b, e;                                       /* index range of this thread */
+  const uint64_t *seg_start; const uint32_t *seg_path; /* order 1: segments */
+  const uint64_t *seg_off; uint64_t n_seg;             /* order 1: first slot of every segment */
+  uint64_t *hist;                                      /* order 1, counting: per-segment counts */
+  int pass; double mean;
+  double sum, dev; uint64_t n, skipped;
+} sps_job;
+
+/* the pair of index k in the job's order */
+static void sps_job_pair(const sps_job *jb, uint64_t k, uint64_t *seg_hint, uint64_t *i, uint64_t *j, uint32_t *ei,
+                         uint32_t *ej) {
+  const or_graph *g = jb->g;
+  if (jb->order == 0) {
+    uint32_t p = path_of_step(g, k / jb->m);
+    sps_pair(g, jb->seed, jb->graph_id, p, k, i, j, ei, ej);
+    return;
+  }
+  uint64_t s = *seg_hint;
+  while (s + 1 < jb->n_seg && jb->seg_off[s + 1] <= k) ++s;
+  *seg_hint = s;
+  sps_slot(g, jb->seed, jb->graph_id, jb->seg_start[s], jb->seg_start[s + 1] - jb->seg_start[s], jb->seg_path[s], k,
+           i, j, ei, ej);
+}
+
+static void *sps_count_worker(void *arg) {
+  sps_job *jb = (sps_job *)arg;
+  memset(jb->hist, 0, sizeof(uint64_t) * jb->n_seg);
+  for (uint64_t q = jb->b; q < jb->e; ++q) {
+    uint64_t i, j; uint32_t ei, ej;
+    sps_pair(jb->g, jb->seed, jb->graph_id, path_of_step(jb->g, q / jb->m), q, &i, &j, &ei, &ej);
+    ++jb->hist[segment_of(jb->seg_start, jb->n_seg, i)];
+  }
+  return NULL;
+}
+
+static void *sps_sum_worker(void *arg) {
+  sps_job *jb = (sps_job *)arg;
+  uint64_t seg = 0;
+  if (jb->order == 1 && jb->b < jb->e) {  /* the segment holding slot b: the largest s with seg_off[s] <= b */
+    uint64_t lo = 0, hi = jb->n_seg;
+    while (hi - lo > 1) {
+      uint64_t mid = lo + (hi - lo) / 2;
+      if (jb->seg_off[mid] <= jb->b) lo = mid; else hi = mid;
+    }
+    seg = lo;
+  }
+  for (uint64_t k = jb->b; k < jb->e; ++k) {
+    uint64_t i, j; uint32_t ei, ej; int valid;
+    sps_job_pair(jb, k, &seg, &i, &j, &ei, &ej);
+    double s = pair_stress(jb->g, jb->coords, i, j, ei, ej, &valid);
+    if (jb->pass == 1) {
+      if (valid) { jb->sum += s; ++jb->n; } else { ++jb->skipped; }
+    } else if (valid) {
+      jb->dev += (s - jb->mean) * (s - jb->mean);
+    }
+  }
+  return NULL;
+}
+
+static void sps_run(sps_job *jobs, uint32_t threads, void *(*fn)(void *)) {
+  pthread_t *tid = (pthread_t *)calloc(threads, sizeof(pthread_t));
+  for (uint32_t k = 0; k < threads; ++k) pthread_create(&tid[k], NULL, fn, &jobs[k]);
+  for (uint32_t k = 0; k < threads; ++k) pthread_join(tid[k], NULL);
+  free(tid);
+}
+
+void or_sampled_path_stress_threaded(const or_graph *g, const float *coords, uint32_t m, uint64_t seed,
+                                     uint32_t graph_id, uint32_t order, uint32_t threads, double *out,
+                                     uint64_t *counts) {
+  if (threads < 1) threads = 1;
+  uint64_t total = (uint64_t)m * g->S, n_seg = 0;
+  uint64_t *seg_start = NULL, *seg_off = NULL;
+  uint32_t *seg_path = NULL;
+  sps_job *jobs = (sps_job *)calloc(threads, sizeof(sps_job));
+  for (uint32_t k = 0; k < threads; ++k) {
+    jobs[k].g = g; jobs[k].coords = coords; jobs[k].m = m; jobs[k].graph_id = graph_id; jobs[k].order = order;
+    jobs[k].seed = seed; jobs[k].b = total * k / threads; jobs[k].e = total * (k + 1) / threads;
+  }
+  if (order == 1) {
+    n_seg = or_sps_segments(g, NULL, NULL);
+    seg_start = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+    seg_path = (uint32_t *)malloc(sizeof(uint32_t) * (n_seg + 1));
+    seg_off = (uint64_t *)calloc(n_seg + 1, sizeof(uint64_t));
+    or_sps_segments(g, seg_start, seg_path);
+    for (uint32_t k = 0; k < threads; ++k) {
+      jobs[k].seg_start = seg_start; jobs[k].seg_path = seg_path; jobs[k].n_seg = n_seg;
+      jobs[k].hist = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg ? n_seg : 1));
+    }
+    sps_run(jobs, threads, sps_count_worker);
+    for (uint32_t k = 0; k < threads; ++k) {  /* seg_off = exclusive prefix of the summed counts */
+      for (uint64_t s = 0; s < n_seg; ++s) seg_off[s + 1] += jobs[k].hist[s];
+      free(jobs[k].hist);
+      jobs[k].hist = NULL;
+    }
+    for (uint64_t s = 0; s < n_seg; ++s) seg_off[s + 1] += seg_off[s];
+    for (uint32_t k = 0; k < threads; ++k) jobs[k].seg_off = seg_off;
+  }
+  double sum = 0.0, dev = 0.0, mean;
+  uint64_t n = 0, skipped = 0;
+  for (uint32_t k = 0; k < threads; ++k) jobs[k].pass = 1;
+  sps_run(jobs, threads, sps_sum_worker);
+  for (uint32_t k = 0; k < threads; ++k) { sum += jobs[k].sum; n += jobs[k].n; skipped += jobs[k].skipped; }
+  mean = n ? sum / (double)n : 0.0;
+  for (uint32_t k = 0; k < threads; ++k) { jobs[k].pass = 2; jobs[k].mean = mean; }
+  sps_run(jobs, threads, sps_sum_worker);
+  for (uint32_t k = 0; k < threads; ++k) dev += jobs[k].dev;
+  free(jobs); free(seg_start); free(seg_path); free(seg_off);
   double sd = n > 1 ? sqrt(dev / (double)(n - 1)) : 0.0;
   double half = n ? 1.96 * sd / sqrt((double)n) : 0.0;
   out[0] = mean; out[1] = mean - half; out[2] = mean + half; out[3] = sd; out[4] = sum; out[5] = dev;

@@ -249,7 +249,7 @@ def test_window_shift_bounds(S):
     sh, n = _windows(S)
     assert 6 <= sh
     assert n <= 32768
-    assert n >= 16 or sh == 6           # small graphs: windows down to 64 steps
+    assert n >= 16 or sh == 6           # at least 16 windows unless they are at their 64-step minimum
     assert sh <= 14 or _windows(S)[1] > 16384  # longer than 2^14 only when 2^14 would exceed the window cap
 
 
@@ -809,3 +809,105 @@ def test_init_coords_follow_first_visits(tiny_synth, tiny_oracle):
         seen.add(n)
         assert X[2 * n] == np.float32(pos[s]) and X[2 * n + 1] == np.float32(pos[s] + int(sg.node_len[n]))
     assert np.all(np.abs(Y) <= 5.0) and abs(float(Y.mean())) < 0.5
+
+
+# ---------------------------------------------------------------------------
+# The power-law direction coin (Alg. 1's power-law partner, reading R4): bit 2
+# of word 3 of the term's own draw, fair, independent of the group's cooling
+# coin and of both endpoint coins, and flipped only where the path has no room
+# in the drawn direction
+# ---------------------------------------------------------------------------
+def test_power_law_direction_coin_is_bit2_fair_and_independent():
+    from scipy.stats import chi2 as chi2_dist
+    from scipy.stats import chi2_contingency
+    L = 3000
+    g = O.Graph(np.full(L, 3, np.uint32), np.array([0, L], np.uint64), np.arange(L, dtype=np.uint32))
+    N = 64 * 4096
+    it = 21  # a cooling iteration: every term takes the power-law partner
+    i, j, f = O.sample_terms(g, it, 0, N)
+    i, j = i.astype(np.int64), j.astype(np.int64)
+    down = (j < i).astype(np.int64)
+    assert np.all(j != i)
+    inner = (i > 0) & (i < L - 1)
+    # the definition: bit 2 of r3 of the term's own draw (counter (t, 0, iter, stream 0 | graph 0))
+    bit2 = np.array([(int(O.philox([t, 0, it, 0], [24301, 0])[3]) >> 2) & 1 for t in range(N)])
+    lead3 = np.array([(int(O.philox([t - t % 64, 0, it, 0], [24301, 0])[3]) >> 3) & 1 for t in range(0, N, 64)])
+    group = np.repeat(lead3, 64)
+    assert np.array_equal(down[inner], bit2[inner])
+    # flips only at the path ends, towards the inside
+    assert np.all(down[i == 0] == 0) and np.all(down[i == L - 1] == 1)
+    # fair and independent of both endpoint coins: chi-square over the 8 cells (down, e_i, e_j)
+    ei, ej, gi = f[inner] & 1, (f[inner] >> 1) & 1, group[inner]
+
+    def fair_p(dirn):
+        counts = np.bincount(dirn * 4 + ei * 2 + ej, minlength=8)
+        e = counts.sum() / 8
+        return chi2_dist.sf(float(np.sum((counts - e) ** 2 / e)), 7)
+
+    def indep_p(dirn):  # 2 x 2 contingency with the group coin (shared by 64 terms, so not a uniform cell)
+        return chi2_contingency(np.array([[np.sum((dirn == x) & (gi == y)) for y in (0, 1)] for x in (0, 1)]))[1]
+
+    assert fair_p(down[inner]) > 1e-4 and indep_p(down[inner]) > 1e-4
+    # a direction taken from the group coin or an endpoint coin fails one of the two
+    for wrong in (gi, ei, ej):
+        assert min(fair_p(wrong), indep_p(wrong)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The initial layout's jitter (reading R11): Y[k] = jitter * (u - 1/2) with
+# u = (r0 >> 8) / 2^24 from Philox stream 3 at counter k, in FP32
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,graph_id,jitter", [(5, 0, 10.0), ((7 << 32) | 3, 9, 2.5)])
+def test_init_jitter_follows_the_stream3_draw(tiny_oracle, seed, graph_id, jitter):
+    g = tiny_oracle
+    c = O.init_coords(g, seed=seed, jitter=jitter, graph_id=graph_id)
+    Y = c[2 * g.n_nodes:]
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for k in list(range(0, 2 * g.n_nodes, 97)) + [2 * g.n_nodes - 1]:
+        r0 = int(O.philox([k, 0, 0, (3 << 24) | graph_id], key)[0])
+        u = np.float32(r0 >> 8) * np.float32(1.0 / 16777216.0)
+        assert Y[k] == np.float32(jitter) * (u - np.float32(0.5)), k
+
+
+def test_init_jitter_is_uniform_and_independent_between_endpoints(tiny_oracle):
+    from scipy.stats import chi2 as chi2_dist
+    g = tiny_oracle
+    Y = O.init_coords(g, seed=5, jitter=10.0)[2 * g.n_nodes:].astype(np.float64)
+    u = Y / 10.0 + 0.5
+    assert np.all((u >= 0) & (u < 1))
+    counts = np.bincount(np.floor(u * 16).astype(np.int64), minlength=16)
+    e = u.size / 16
+    assert chi2_dist.sf(float(np.sum((counts - e) ** 2 / e)), 15) > 1e-4
+    # the two endpoints of a node draw independently
+    assert abs(np.corrcoef(u[0::2], u[1::2])[0, 1]) < 4 / np.sqrt(g.n_nodes)
+
+
+# ---------------------------------------------------------------------------
+# The threaded evaluation of Eq. 2 (stored results of large layouts) against
+# the one-thread evaluation: the same pairs, so equal counts and sums up to
+# the rounding of the summation order
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pairs", ["uniform", "uniform_windowed"])
+@pytest.mark.parametrize("threads", [2, 3, 7])
+def test_threaded_sps_equals_one_thread(tiny_oracle, pairs, threads):
+    g = tiny_oracle
+    rng = np.random.default_rng(3)
+    c = (O.init_coords(g) + rng.normal(scale=40.0, size=4 * g.n_nodes)).astype(np.float32)
+    a = O.sampled_path_stress(g, c, m=20, seed=7, pairs=pairs)
+    b = O.sampled_path_stress(g, c, m=20, seed=7, pairs=pairs, threads=threads)
+    assert a["n_valid"] == b["n_valid"] and a["n_skipped"] == b["n_skipped"]
+    for k in ("sum", "sumsq_dev", "mean", "stddev"):
+        assert b[k] == pytest.approx(a[k], rel=1e-12), k
+
+
+def test_threaded_sps_on_a_graph_with_empty_paths():
+    node_len = np.array([2, 3, 1, 4, 5], np.uint32)
+    off = np.array([0, 0, 3, 3, 5, 5], np.uint64)
+    steps = np.array([0, 1, 2, 3 | 0x80000000, 4], np.uint32)
+    g = O.Graph(node_len, off, steps)
+    c = np.linspace(-5, 5, 4 * 5).astype(np.float32)
+    for pairs in ("uniform", "uniform_windowed"):
+        a = O.sampled_path_stress(g, c, m=7, seed=1, pairs=pairs)
+        b = O.sampled_path_stress(g, c, m=7, seed=1, pairs=pairs, threads=4)
+        assert (a["n_valid"], a["n_skipped"]) == (b["n_valid"], b["n_skipped"])
+        assert b["sum"] == pytest.approx(a["sum"], rel=1e-12)
