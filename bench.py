@@ -34,17 +34,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SCHEDULES = {"plain": 1, "binned": 2, "windowed": 3}
-DOMINANT = {1: "k_layout_iter", 2: "k_bin_layout", 3: "k_layout_local"}  # the layout kernel of each schedule
+SCHEDULES = {"plain": 1, "windowed": 3}
+DOMINANT = {1: "k_layout_iter", 3: "k_layout_local"}  # the layout kernel of each schedule
 ALG_BYTES_PER_TERM = 64  # 2 step records (16 B each) + 2 endpoints read (8 B each) + written (8 B each)
 CSRC = "paper_2409_00876_amd/csrc/"
 # the sources each layout kernel is compiled from (a counter summary is valid for this hash only)
 KERNEL_SOURCES = {
-    "k_layout_iter": [CSRC + "layout_kernels.hip", CSRC + "binned_kernels.hip", CSRC + "device.h", CSRC + "internal.h"],
-    "k_bin_layout": [CSRC + "layout_kernels.hip", CSRC + "binned_kernels.hip", CSRC + "device.h", CSRC + "internal.h"],
+    "k_layout_iter": [CSRC + "layout_kernels.hip", CSRC + "device.h", CSRC + "internal.h"],
     "k_layout_local": [CSRC + "local_kernels.hip", CSRC + "local.h", CSRC + "device.h", CSRC + "internal.h"],
 }
-COUNTERS_NAME = {"k_layout_iter": "layout_iter", "k_bin_layout": "bin_layout", "k_layout_local": "layout_local"}
+COUNTERS_NAME = {"k_layout_iter": "layout_iter", "k_layout_local": "layout_local"}
 
 
 def counters_file(kernel: str) -> str:
@@ -105,7 +104,7 @@ def summarize_counters(trace_dir: str, fetch_csv: str, write_csv: str, tcc_csv: 
 
     fetch_rows = _read_counters(fetch_csv)
     dom = "pgsgd::" + kernel
-    iter_kernels = ("pgsgd::k_bin_", "pgsgd::k_layout_iter", "pgsgd::k_local_", "pgsgd::k_layout_local")
+    iter_kernels = ("pgsgd::k_layout_iter", "pgsgd::k_local_", "pgsgd::k_layout_local")
 
     def per_kernel(rows, counter):
         lay = [v for k, c, v in rows if c == counter and k.startswith(dom)]

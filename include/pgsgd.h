@@ -138,8 +138,7 @@ enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
 
 /* Data-reuse variant (Section "A Case Study: Explore the Performance-Quality
  * Trade-off with Sampled Path Stress"), active when reuse_factor > 1 or
- * step_reduction > 1, with the PLAIN or the WINDOWED schedule (BINNED is
- * rejected).  PLAIN:
+ * step_reduction > 1, with the PLAIN or the WINDOWED schedule.  PLAIN:
  *   - an iteration samples ceil(terms_per_step * S / step_reduction) terms in
  *     aligned groups of 64; a group's path is the path of the global step
  *     drawn by its first term (paths stay chosen with probability ∝ |p|), and
@@ -162,10 +161,6 @@ enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
 /* Processing order of the terms of an iteration.
  *   PLAIN    term groups in index order over a grid capped by
  *            max_inflight_waves
- *   BINNED   the PLAIN terms, binned by the window of consecutive path steps
- *            holding their step i and processed window by window, XCD by XCD
- *            (scratch of 6 bytes per term of a chunk of up to 2^30 terms,
- *            allocated on first use); the same terms as PLAIN
  *   WINDOWED window-major enumeration: the steps are cut into windows of
  *            2^h consecutive global steps (h = 14, decreased while there
  *            would be fewer than 16 windows but not below 6, increased while
@@ -191,8 +186,9 @@ enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
  *            a concurrent update of a local node can be lost short.  Scratch: a few
  *            words per window, allocated on first use.  pgsgd_sample_terms
  *            records slots [t_begin, t_begin + count) in slot order.
- *   AUTO     WINDOWED */
-enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_BINNED = 2, PGSGD_SCHEDULE_WINDOWED = 3 };
+ *   AUTO     WINDOWED
+ * The value 2 is reserved (INVALID_ARG). */
+enum { PGSGD_SCHEDULE_AUTO = 0, PGSGD_SCHEDULE_PLAIN = 1, PGSGD_SCHEDULE_WINDOWED = 3 };
 
 /* Fills the defaults listed above (seed 24301, graph_id 0). */
 void pgsgd_params_default(pgsgd_params *p);
@@ -411,7 +407,8 @@ typedef struct pgsgd_batch pgsgd_batch;
  *             max_inflight_waves is ignored).
  * tune = NULL picks defaults (4 branches; 256 threads, 1 group per item, 2
  * blocks per CU, 1 phase).  The sampled terms do not depend on tune.  The
- * data-reuse variant and the BINNED schedule are rejected (INVALID_ARG).
+ * data-reuse variant (reuse_factor > 1 or step_reduction > 1) is rejected
+ * (INVALID_ARG) for both forms.
  */
 pgsgd_status pgsgd_batch_create(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
                                 float *const *coords, const pgsgd_tune *tune, pgsgd_batch **out);
@@ -456,10 +453,9 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph *const *graphs, uint32_t n, co
  * flags_out (device uint8: bit0 e_i, bit1 e_j, bit2 cooling, bit3 skipped).
  * The terms are recorded by the layout kernels of the schedule p->schedule
  * resolves to, with the launch shape pgsgd_layout uses: PLAIN records with the
- * plain kernel; BINNED and WINDOWED run their counting and layout kernels over
- * the whole iteration (without updating coordinates) and record the terms
- * (WINDOWED: the slots) of the range, which must lie in [0, terms_per_step *
- * S).  With the data-reuse variant active it records that variant's terms
+ * plain kernel; WINDOWED runs its counting and layout kernels over the whole
+ * iteration (without updating coordinates) and records the slots of the range,
+ * which must lie in [0, terms_per_step * S).  With the data-reuse variant active it records that variant's terms
  * (see pgsgd_sample_terms_reuse).  Async.
  */
 pgsgd_status pgsgd_sample_terms(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,
@@ -486,6 +482,21 @@ pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph *g, const pgsgd_params *p, uin
  */
 pgsgd_status pgsgd_apply_terms(pgsgd_graph *g, float eta, const uint64_t *i, const uint64_t *j,
                                const uint8_t *flags, uint64_t count, float *coords, void *stream);
+
+/*
+ * The collision-free batch of the update's parity check, applied by the
+ * layout kernel itself: runs iteration iter of pgsgd_layout (Alg. 1's inner
+ * loop with the update rule of pgsgd_layout) with the kernels and launch shape
+ * of the schedule p resolves to, but applies only the terms t (WINDOWED: the
+ * slots) of [t_begin, t_begin + count) with mask[t - t_begin] != 0; every
+ * other term of the iteration is sampled and dropped.  mask: device, count
+ * bytes.  coords: device, updated in place.  The range must lie inside the
+ * iteration's terms_per_step * S terms.  Terms of the subset that touch the
+ * same slot race, as in pgsgd_layout.  Errors: INVALID_ARG (NULL, range, the
+ * data-reuse variant), and those of pgsgd_layout.  Async.
+ */
+pgsgd_status pgsgd_apply_slots(pgsgd_graph *g, const pgsgd_params *p, uint32_t iter, uint64_t t_begin,
+                               uint64_t count, const uint8_t *mask, float *coords, void *stream);
 
 #ifdef __cplusplus
 }

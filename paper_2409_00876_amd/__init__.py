@@ -23,7 +23,7 @@ from ._lib import (FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDUL
                    check, lib)
 
 __all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
-           "sample_terms", "sample_terms_reuse", "apply_terms", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
+           "sample_terms", "sample_terms_reuse", "apply_terms", "apply_slots", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
 
@@ -64,7 +64,7 @@ class LayoutParams:
     last_iter: int = 0
     max_inflight_waves: int = 0
     flags: int = 0
-    schedule: int = 0           # 0 auto, 1 plain, 2 binned
+    schedule: int = 0           # 0 auto (= 3), 1 plain, 3 windowed
     reuse_factor: int = 1       # data-reuse variant: updates per sampled term (DRF)
     step_reduction: int = 1     # data-reuse variant: sampled terms divided by SRF
 
@@ -247,6 +247,19 @@ def apply_terms(g: Graph, coords, eta: float, i, j, f):
     _check_tensor(f, torch.uint8, i.numel(), "flags")
     check(lib().pgsgd_apply_terms(g.handle, float(eta), ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
                                   ctypes.c_void_p(f.data_ptr()), int(i.numel()), ctypes.c_void_p(coords.data_ptr()),
+                                  _stream(torch, coords.device)))
+    return coords
+
+
+def apply_slots(g: Graph, coords, iter: int, t_begin: int, mask, params: LayoutParams | None = None, **kw):
+    """Iteration `iter` of layout() with its own kernels and launch shape, applying only the terms
+    (windowed: slots) t_begin + k with mask[k] != 0 (mask: uint8 device tensor)."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    _check_tensor(mask, torch.uint8, None, "mask")
+    p = _params(params, kw)
+    check(lib().pgsgd_apply_slots(g.handle, ctypes.byref(p), int(iter), int(t_begin), int(mask.numel()),
+                                  ctypes.c_void_p(mask.data_ptr()), ctypes.c_void_p(coords.data_ptr()),
                                   _stream(torch, coords.device)))
     return coords
 

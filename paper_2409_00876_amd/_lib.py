@@ -18,7 +18,7 @@ ERR_RANGE = -2
 ERR_OOM = -3
 ERR_DEVICE = -4
 ERR_UNSUPPORTED = -5
-SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_BINNED, SCHEDULE_WINDOWED = 0, 1, 2, 3
+SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_WINDOWED = 0, 1, 3  # 2 is reserved
 PAIRS_UNIFORM, PAIRS_POWER_LAW, PAIRS_UNIFORM_WINDOWED = 0, 1, 2
 FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER = 1, 2
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "RANGE", -3: "OOM", -4: "DEVICE", -5: "UNSUPPORTED"}
@@ -117,6 +117,7 @@ SIGNATURES = {
     "pgsgd_sample_terms": ([_P, _P, _u32, _u64, _u64, _P, _P, _P, _P], _i32),
     "pgsgd_sample_terms_reuse": ([_P, _P, _u32, _u64, _u64, _P, _P, _P, _P, _P], _i32),
     "pgsgd_apply_terms": ([_P, _f32, _P, _P, _P, _u64, _P, _P], _i32),
+    "pgsgd_apply_slots": ([_P, _P, _u32, _u64, _u64, _P, _P, _P], _i32),
 }
 
 _lib = None

@@ -16,7 +16,7 @@
 
 namespace pgsgd {
 
-__global__ void k_layout_batch(BatchLaunch P) {
+__global__ __launch_bounds__(1024) void k_layout_batch(BatchLaunch P) {
   extern __shared__ __align__(16) char lds[];
   const uint32_t n_seg = P.phases * P.n_graphs;
   BatchGraph* hdr = reinterpret_cast<BatchGraph*>(lds);

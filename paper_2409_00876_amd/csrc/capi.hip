@@ -142,16 +142,6 @@ struct pgsgd_graph {
   size_t device_bytes = 0;
   std::unordered_map<void*, size_t> alloc_bytes;  // size of every lazily allocated buffer
   int layout_blocks_per_cu = 0;  // occupancy of k_layout_iter, filled on first use
-  int bin_blocks_per_cu = 0;     // occupancy of k_bin_layout, filled on first use
-  // binning scratch (allocated on first binned layout)
-  uint64_t bin_chunk = 0;
-  uint32_t bin_nwin = 0, bin_shift = 0, bin_xstride = 0;
-  uint16_t* d_tag = nullptr;
-  uint32_t* d_entries = nullptr;
-  uint32_t* d_wcount = nullptr;
-  uint32_t* d_woff = nullptr;
-  uint32_t* d_cursor = nullptr;
-  uint32_t* d_xitem = nullptr;
   // window-major scratch (allocated on first use)
   uint32_t loc_nwin = 0, loc_shift = 0, loc_xstride = 0, loc_streams = 0;
   uint32_t* d_lcount = nullptr;
@@ -184,9 +174,7 @@ struct pgsgd_graph {
     DeviceGuard g(device);
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
-                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_tag,
-                    (void*)d_entries, (void*)d_wcount, (void*)d_woff, (void*)d_cursor, (void*)d_xitem,
-                    (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
+                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
                     (void*)d_lsbeg, (void*)d_lwpath, (void*)d_sseg_start, (void*)d_sseg_path, (void*)d_swseg,
                     (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue,
                     (void*)d_lcount2, (void*)d_loff2, (void*)d_lxitem2, (void*)d_lqueue2})
@@ -260,9 +248,8 @@ pgsgd_status check_params(const pgsgd_params* p) {
   if ((p->flags & PGSGD_FLAG_COUNT_AHEAD) && (p->flags & PGSGD_FLAG_COUNT_IN_ORDER))
     return fail(PGSGD_ERR_INVALID_ARG, "params.flags: COUNT_AHEAD and COUNT_IN_ORDER exclude each other");
   if (p->reuse_factor > 16) return fail(PGSGD_ERR_INVALID_ARG, "reuse_factor must be at most 16");
-  if (p->schedule > PGSGD_SCHEDULE_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u", p->schedule);
-  if ((p->reuse_factor > 1 || p->step_reduction > 1) && p->schedule == PGSGD_SCHEDULE_BINNED)
-    return fail(PGSGD_ERR_INVALID_ARG, "the data-reuse variant runs with the plain or windowed schedule");
+  if (p->schedule > PGSGD_SCHEDULE_WINDOWED || p->schedule == 2)
+    return fail(PGSGD_ERR_INVALID_ARG, "unknown schedule %u (2 is reserved)", p->schedule);
   if (p->zipf_window < 1 || p->zipf_window > 65535)
     return fail(PGSGD_ERR_INVALID_ARG, "zipf_window %u outside [1, 65535]", p->zipf_window);
   if (!(p->zipf_theta >= 0.0) || !std::isfinite(p->zipf_theta))
@@ -614,41 +601,9 @@ namespace {
 
 // AUTO selects WINDOWED: on MI355X the window-major order keeps a window's
 // records and coordinates in the L2 and is about 3x faster than PLAIN at the
-// same layout quality.  BINNED orders the plain terms by window but its
-// binning passes cost more than they save.
+// same layout quality.
 uint32_t resolve_schedule(const pgsgd_params* p) {
   return p->schedule != PGSGD_SCHEDULE_AUTO ? p->schedule : (uint32_t)PGSGD_SCHEDULE_WINDOWED;
-}
-
-// Binning scratch for chunks of up to min(T, kBinChunk) terms: windows of
-// 2^shift steps (shift >= 16, at most kMaxBinWindows windows).
-pgsgd_status ensure_bins(pgsgd_graph* g, uint64_t n_terms, hipStream_t s) {
-  const uint64_t chunk = std::min<uint64_t>(((n_terms + 63) / 64) * 64, kBinChunk);
-  uint32_t shift = 16;
-  while (((g->S + (1ull << shift) - 1) >> shift) > kMaxBinWindows) ++shift;
-  const uint32_t nwin = (uint32_t)((g->S + (1ull << shift) - 1) >> shift);
-  if (g->d_tag && g->bin_chunk >= chunk && g->bin_nwin == nwin) return PGSGD_OK;
-  HIP_TRY(hipStreamSynchronize(s));
-  const auto set = {(void**)&g->d_tag, (void**)&g->d_entries, (void**)&g->d_wcount, (void**)&g->d_woff,
-                    (void**)&g->d_cursor, (void**)&g->d_xitem};
-  free_set(g, set);
-  g->bin_chunk = chunk;
-  g->bin_nwin = nwin;
-  g->bin_shift = shift;
-  g->bin_xstride = nwin / kXcds + 2;
-  const pgsgd_status st = [&]() -> pgsgd_status {
-    pgsgd_status e;
-    if ((e = dev_alloc(g, &g->d_tag, chunk))) return e;
-    if ((e = dev_alloc(g, &g->d_entries, chunk))) return e;
-    if ((e = dev_alloc(g, &g->d_wcount, nwin))) return e;
-    if ((e = dev_alloc(g, &g->d_woff, nwin + 1))) return e;
-    if ((e = dev_alloc(g, &g->d_cursor, nwin))) return e;
-    if ((e = dev_alloc(g, &g->d_xitem, (size_t)kXcds * g->bin_xstride))) return e;
-    HIP_TRY(launch_fill_u32(g->d_wcount, nwin, 0u, s));  // the histogram must start at zero
-    return PGSGD_OK;
-  }();
-  if (st) free_set(g, set);
-  return st;
 }
 
 // Window-major scratch: windows of 2^window_shift(S) steps, grouped into
@@ -864,26 +819,25 @@ hipError_t local_iteration(const LocalLaunch& W, uint32_t blocks, uint32_t threa
   return e;
 }
 
-pgsgd_status bin_blocks(pgsgd_graph* g, size_t lds, uint32_t* blocks) {
-  if (g->bin_blocks_per_cu <= 0) {
-    int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bin_layout_kernel(), 256, lds));
-    g->bin_blocks_per_cu = nb > 0 ? nb : 1;
-  }
-  *blocks = (uint32_t)g->n_cu * (uint32_t)g->bin_blocks_per_cu;
-  *blocks = std::max<uint32_t>(kXcds, *blocks / kXcds * kXcds);
-  return PGSGD_OK;
-}
-
 // The layout loop.  With iter_ms set, HIP events bracket every iteration and
 // every launch of the dominant kernel, and the durations are written out
-// (synchronising).  With trace set (binned schedule only), iteration
-// first_iter is recorded instead of applied.
+// (synchronising).  With trace_f set (windowed schedule), iteration first_iter
+// is recorded instead of applied; with apply_mask set (plain or windowed),
+// iteration first_iter applies only the terms of [sub_begin, sub_begin +
+// sub_count) that the mask selects.
+struct LayoutHook {
+  uint64_t* trace_i = nullptr;
+  uint64_t* trace_j = nullptr;
+  uint8_t* trace_f = nullptr;
+  uint8_t* trace_o = nullptr;
+  const uint8_t* apply_mask = nullptr;
+  uint64_t sub_begin = 0, sub_count = 0;
+};
+
 pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms, float* main_ms,
-                         uint32_t* main_launches, void* stream, uint64_t* trace_i = nullptr,
-                         uint64_t* trace_j = nullptr, uint8_t* trace_f = nullptr, uint64_t trace_begin = 0,
-                         uint64_t trace_count = 0, uint8_t* trace_o = nullptr) {
-  const bool tracing = trace_f != nullptr;
+                         uint32_t* main_launches, void* stream, const LayoutHook& hook = LayoutHook()) {
+  const bool tracing = hook.trace_f != nullptr;
+  const bool subset = tracing || hook.apply_mask != nullptr;
   if (!g || (!coords && !tracing)) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
   if (coords && ((uintptr_t)coords & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
   pgsgd_status st = check_params(p);
@@ -909,52 +863,32 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   L.g_begin = 0;
   L.g_end = L.n_groups;
   const bool reuse = p->reuse_factor > 1 || p->step_reduction > 1;
-  const uint32_t sched = resolve_schedule(p);
-  const bool windowed = sched == PGSGD_SCHEDULE_WINDOWED;
-  const bool binned = !windowed && (tracing || sched == PGSGD_SCHEDULE_BINNED);
+  const bool windowed = resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED;
+  if (tracing && !windowed) return fail(PGSGD_ERR_INVALID_ARG, "recording through the layout loop needs WINDOWED");
   uint32_t blocks = 0, threads = 256;
-  BinLaunch B{};
   LocalLaunch W{};
-  uint64_t n_chunks = 1;
   if (windowed) {
     if ((st = local_plan(g, p, lds, L, s, &W, &blocks, &threads))) return st;
-    L.trace_i = trace_i;
-    L.trace_j = trace_j;
-    L.trace_f = trace_f;
-    L.trace_o = trace_o;
-    if (tracing) {
-      L.t_begin = trace_begin;
-      L.t_end = trace_begin + trace_count;
-    }
-  } else if (binned) {
-    if ((st = ensure_bins(g, L.n_terms, s))) return st;
-    if ((st = bin_blocks(g, lds, &blocks))) return st;
-    B.n_win = g->bin_nwin;
-    B.win_shift = g->bin_shift;
-    B.count_blocks = (uint32_t)g->n_cu * 2;
-    B.xstride = g->bin_xstride;
-    B.tag = g->d_tag;
-    B.entries = g->d_entries;
-    B.wcount = g->d_wcount;
-    B.woff = g->d_woff;
-    B.cursor = g->d_cursor;
-    B.xitem = g->d_xitem;
-    n_chunks = (L.n_terms + g->bin_chunk - 1) / g->bin_chunk;
-    L.wave_stride = 0;
-    L.trace_i = trace_i;
-    L.trace_j = trace_j;
-    L.trace_f = trace_f;
-    if (tracing) {
-      L.t_begin = trace_begin;
-      L.t_end = trace_begin + trace_count;
-    }
   } else {
     if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
     L.wave_stride = (uint64_t)blocks * (threads / 64);
   }
-  if (main_launches) *main_launches = (uint32_t)n_chunks;
+  L.trace_i = hook.trace_i;
+  L.trace_j = hook.trace_j;
+  L.trace_f = hook.trace_f;
+  L.trace_o = hook.trace_o;
+  L.apply_mask = hook.apply_mask;
+  if (subset) {
+    L.t_begin = hook.sub_begin;
+    L.t_end = hook.sub_begin + hook.sub_count;
+    if (!windowed) {  // the plain kernel walks the groups of the range only
+      L.g_begin = L.t_begin >> 6;
+      L.g_end = (L.t_end + 63) >> 6;
+    }
+  }
+  if (main_launches) *main_launches = 1;
   std::vector<hipEvent_t> ev;
-  const size_t ev_per_iter = 1 + 2 * n_chunks;
+  const size_t ev_per_iter = 3;
   if (iter_ms) {
     ev.resize(n_run * ev_per_iter + 1);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
@@ -975,7 +909,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   // order there.
   const bool ahead = (p->flags & PGSGD_FLAG_COUNT_AHEAD) ||
                      (!(p->flags & PGSGD_FLAG_COUNT_IN_ORDER) && W.L.n_terms >= kOverlapMinTerms);
-  const bool overlap = windowed && !tracing && n_run > 1 && ahead;
+  const bool overlap = windowed && !subset && n_run > 1 && ahead;
   LocalLaunch Wset[2] = {W, W};
   hipStream_t s2 = nullptr;
   bool set_used[2] = {false, false};
@@ -1019,23 +953,13 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
       W.L = L;
       HIP_TRY(local_iteration(W, blocks, threads, s, iter_ms ? ev[e0 + 1] : nullptr));
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
-    } else if (binned) {
-      for (uint64_t c = 0; c < n_chunks; ++c) {
-        B.L = L;
-        B.c0 = c * g->bin_chunk;
-        B.c1 = std::min(L.n_terms, B.c0 + g->bin_chunk);
-        HIP_TRY(launch_bin_count_scan_scatter(B, s));
-        if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1 + 2 * c], s));
-        HIP_TRY(launch_bin_layout(B, blocks, s));
-        if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2 + 2 * c], s));
-      }
     } else {
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1], s));
       if (reuse) HIP_TRY(launch_layout_reuse(L, blocks, threads, s));
       else HIP_TRY(launch_layout_iter(L, blocks, threads, s));
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
     }
-    if (tracing) break;
+    if (subset) break;
   }
   if (iter_ms) HIP_TRY(hipEventRecord(ev.back(), s));
   if (!tracing) HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
@@ -1045,12 +969,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
       const size_t e0 = (size_t)k * ev_per_iter;
       const hipEvent_t end = (k + 1 < n_run) ? ev[e0 + ev_per_iter] : ev.back();
       HIP_TRY(hipEventElapsedTime(&iter_ms[k], ev[e0], end));
-      if (main_ms)
-        for (uint64_t c = 0; c < n_chunks; ++c) {
-          float ms = 0.0f;
-          HIP_TRY(hipEventElapsedTime(&ms, ev[e0 + 1 + 2 * c], ev[e0 + 2 + 2 * c]));
-          main_ms[k] += ms;
-        }
+      if (main_ms) HIP_TRY(hipEventElapsedTime(&main_ms[k], ev[e0 + 1], ev[e0 + 2]));
     }
   }
   return ok();
@@ -1101,8 +1020,14 @@ pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph* g, const pgsgd_params* p, uin
     q.first_iter = iter;
     q.last_iter = iter + 1;
     q.schedule = PGSGD_SCHEDULE_WINDOWED;
-    return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, i_out, j_out, flags_out, t_begin, count,
-                       p->reuse_factor > 1 ? offsets_out : nullptr);
+    LayoutHook h;
+    h.trace_i = i_out;
+    h.trace_j = j_out;
+    h.trace_f = flags_out;
+    h.trace_o = p->reuse_factor > 1 ? offsets_out : nullptr;
+    h.sub_begin = t_begin;
+    h.sub_count = count;
+    return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, h);
   }
   if (t_begin % 64) return fail(PGSGD_ERR_INVALID_ARG, "t_begin must be a multiple of 64");
   DeviceGuard guard(g->device);
@@ -1133,10 +1058,10 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t 
   if (t_begin + count < t_begin || t_begin + count >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term range too large");
   if (count == 0 || g->S == 0) return ok();
   const uint32_t sched = resolve_schedule(p);
-  if (sched == PGSGD_SCHEDULE_BINNED || sched == PGSGD_SCHEDULE_WINDOWED) {
-    // the binning (window count) kernels and the layout kernel process the
-    // whole iteration; the terms (window-major slots) of [t_begin, t_begin +
-    // count) are recorded
+  if (sched == PGSGD_SCHEDULE_WINDOWED) {
+    // the window counting kernels and the layout kernel process the whole
+    // iteration; the window-major slots of [t_begin, t_begin + count) are
+    // recorded
     const uint64_t srf = p->step_reduction > 1 ? p->step_reduction : 1;
     if (t_begin + count > ((uint64_t)p->terms_per_step * g->S + srf - 1) / srf)
       return fail(PGSGD_ERR_INVALID_ARG, "this schedule records terms of the iteration only (t < T)");
@@ -1144,7 +1069,13 @@ pgsgd_status pgsgd_sample_terms(pgsgd_graph* g, const pgsgd_params* p, uint32_t 
     q.first_iter = iter;
     q.last_iter = iter + 1;
     q.schedule = sched;
-    return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, i_out, j_out, flags_out, t_begin, count);
+    LayoutHook h;
+    h.trace_i = i_out;
+    h.trace_j = j_out;
+    h.trace_f = flags_out;
+    h.sub_begin = t_begin;
+    h.sub_count = count;
+    return layout_impl(g, &q, nullptr, nullptr, nullptr, nullptr, stream, h);
   }
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
@@ -1184,6 +1115,27 @@ pgsgd_status pgsgd_apply_terms(pgsgd_graph* g, float eta, const uint64_t* i, con
   HIP_TRY(launch_apply_terms(g->d_rec, g->d_work, eta, i, j, flags, count, s));
   HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
   return ok();
+}
+
+pgsgd_status pgsgd_apply_slots(pgsgd_graph* g, const pgsgd_params* p, uint32_t iter, uint64_t t_begin,
+                               uint64_t count, const uint8_t* mask, float* coords, void* stream) {
+  if (!g || !mask || !coords) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  pgsgd_status st = check_params(p);
+  if (st) return st;
+  if (p->reuse_factor > 1 || p->step_reduction > 1)
+    return fail(PGSGD_ERR_INVALID_ARG, "the data-reuse variant pairs lanes across terms: no subset can be applied");
+  if (iter >= p->n_iters) return fail(PGSGD_ERR_INVALID_ARG, "iter %u >= n_iters %u", iter, p->n_iters);
+  if (t_begin + count < t_begin || t_begin + count > (uint64_t)p->terms_per_step * g->S)
+    return fail(PGSGD_ERR_INVALID_ARG, "the range must lie inside the iteration's terms");
+  if (count == 0) return ok();
+  pgsgd_params q = *p;
+  q.first_iter = iter;
+  q.last_iter = iter + 1;
+  LayoutHook h;
+  h.apply_mask = mask;
+  h.sub_begin = t_begin;
+  h.sub_count = count;
+  return layout_impl(g, &q, coords, nullptr, nullptr, nullptr, stream, h);
 }
 
 pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed,
@@ -1480,6 +1432,26 @@ pgsgd_status batch_build_windowed(pgsgd_graph* const* graphs, uint32_t n, const 
     b->coords.push_back(coords[k]);
     b->total_terms += L.n_terms;
   }
+  // the batch keeps its own power-law table: the graphs' cached tables are
+  // rebuilt in place by later calls with another theta or window
+  if (!st) {
+    std::vector<uint32_t> C;
+    std::vector<uint16_t> guide;
+    build_zipf(p->zipf_theta, p->zipf_window, C, guide);
+    e = hipMalloc((void**)&b->d_zipf, sizeof(uint32_t) * C.size());
+    if (!e) e = hipMalloc((void**)&b->d_guide, sizeof(uint16_t) * guide.size());
+    if (!e) e = hipMemcpy(b->d_zipf, C.data(), sizeof(uint32_t) * C.size(), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(b->d_guide, guide.data(), sizeof(uint16_t) * guide.size(), hipMemcpyHostToDevice);
+    if (e) {
+      (void)hipGetLastError();
+      st = fail(e == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE, "batch power-law table: %s",
+                hipGetErrorString(e));
+    }
+    for (LocalLaunch& W : b->wl) {
+      W.L.zipf = b->d_zipf;
+      W.L.guide = b->d_guide;
+    }
+  }
   if (st) {
     (void)hipStreamDestroy(cs);
     delete b;
@@ -1576,14 +1548,14 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
     if ((uint64_t)p->terms_per_step * graphs[k]->S >= kMaxTerms) return fail(PGSGD_ERR_RANGE, "term count >= 2^48");
     slots_total += graphs[k]->path_slots;
   }
+  if (p->reuse_factor > 1 || p->step_reduction > 1)
+    return fail(PGSGD_ERR_INVALID_ARG, "the batched form does not run the data-reuse variant");
   if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
     if (trace_f) return fail(PGSGD_ERR_INVALID_ARG, "internal: windowed batches record through the graph path");
     return batch_build_windowed(graphs, n, p, coords, t, capture, out);
   }
   if (resolve_schedule(p) != PGSGD_SCHEDULE_PLAIN)
     return fail(PGSGD_ERR_INVALID_ARG, "the batched form runs the windowed or the plain schedule");
-  if (p->reuse_factor > 1 || p->step_reduction > 1)
-    return fail(PGSGD_ERR_INVALID_ARG, "the batched form does not run the data-reuse variant");
   const size_t lds = batch_lds_bytes(n, t.phases, slots_total, p->zipf_window);
   if (lds > graphs[0]->lds_limit)
     return fail(PGSGD_ERR_UNSUPPORTED, "batched LDS image of %zu bytes exceeds the %zu-byte block limit", lds,
@@ -1768,9 +1740,12 @@ pgsgd_status pgsgd_batch_sample_terms(pgsgd_graph* const* graphs, uint32_t n, co
       q.last_iter = iter + 1;
       const uint64_t T = (uint64_t)p->terms_per_step * graphs[k]->S;
       if (T == 0) continue;
-      if ((st = layout_impl(graphs[k], &q, nullptr, nullptr, nullptr, nullptr, stream, i_out[k], j_out[k],
-                            flags_out[k], 0, T)))
-        return st;
+      LayoutHook h;
+      h.trace_i = i_out[k];
+      h.trace_j = j_out[k];
+      h.trace_f = flags_out[k];
+      h.sub_count = T;
+      if ((st = layout_impl(graphs[k], &q, nullptr, nullptr, nullptr, nullptr, stream, h))) return st;
     }
     return ok();
   }

@@ -150,21 +150,31 @@ __device__ __forceinline__ bool resolve_term(const StepRec* __restrict__ rec, co
 
 // The clamped SGD step for one pair of points a, b with reference distance d
 // (Zheng et al.'s update, which the paper follows for "move against the
-// gradient"): mu = min(eta / d^2, 1), r = mu (mag - d) / (2 mag), a -= r delta,
-// b += r delta.  FP32 throughout; unlocked loads and stores (Hogwild).
-//
-// W is the interleaved working copy of the coordinates: W[2n+e] = (x, y) of
-// endpoint e of node n, so each endpoint is one 8-byte access (one cache line)
-// and a node's two endpoints share 16 bytes.
-__device__ __forceinline__ void apply_update(float2* __restrict__ W, uint64_t a, uint64_t b, float d, float eta) {
-  const float2 pa = W[a], pb = W[b];
+// gradient"): mu = min(eta / d^2, 1), r = mu (mag - d) / (2 mag) and disp =
+// r (a - b); a moves by -disp and b by +disp.  Returns false (disp unset)
+// when the points coincide.  FP32 throughout.  Every layout kernel (plain,
+// window-major, data reuse, batched, the parity hook) takes its updates from
+// this one function.
+__device__ __forceinline__ bool clamped_step(float2 pa, float2 pb, float d, float eta, float2& disp) {
   const float dx = pa.x - pb.x, dy = pa.y - pb.y;
   const float mag = sqrtf(dx * dx + dy * dy);
-  if (mag == 0.0f) return;
+  if (mag == 0.0f) return false;
   const float mu = fminf(eta / (d * d), 1.0f);
   const float r = mu * (mag - d) / (2.0f * mag);
-  W[a] = make_float2(pa.x - r * dx, pa.y - r * dy);
-  W[b] = make_float2(pb.x + r * dx, pb.y + r * dy);
+  disp = make_float2(r * dx, r * dy);
+  return true;
+}
+
+// One term's update on the interleaved working copy of the coordinates, with
+// unlocked loads and stores (Hogwild).  W[2n+e] = (x, y) of endpoint e of node
+// n, so each endpoint is one 8-byte access (one cache line) and a node's two
+// endpoints share 16 bytes.
+__device__ __forceinline__ void apply_update(float2* __restrict__ W, uint64_t a, uint64_t b, float d, float eta) {
+  const float2 pa = W[a], pb = W[b];
+  float2 m;
+  if (!clamped_step(pa, pb, d, eta, m)) return;
+  W[a] = make_float2(pa.x - m.x, pa.y - m.y);
+  W[b] = make_float2(pb.x + m.x, pb.y + m.y);
 }
 
 // LDS image shared by the layout kernels: padded path offsets, then the

@@ -39,29 +39,13 @@ struct LayoutLaunch {
   uint64_t* trace_j;
   uint8_t* trace_f;
   uint8_t* trace_o;        // data reuse: offsets o_1..o_{drf-1} per group
+  // parity hook: when apply_mask is set (trace_f unset) only the terms t of
+  // [t_begin, t_end) with apply_mask[t - t_begin] != 0 are applied
+  const uint8_t* apply_mask;
 };
 
-// Binned processing of one iteration (binned_kernels.hip): terms are binned by
-// the window of 2^win_shift consecutive steps holding their step i and the
-// windows are processed XCD by XCD.
-constexpr uint32_t kXcds = 8;                 // gfx950: 8 XCDs, blocks dispatched round-robin
-constexpr uint32_t kMaxBinWindows = 8192;     // LDS histogram of 32 KB
-constexpr uint64_t kBinChunk = 1ull << 30;    // terms per binning pass (4-byte offsets, bit 31 = coin)
-
-struct BinLaunch {
-  LayoutLaunch L;          // sampling parameters, coordinates, trace pointers
-  uint64_t c0, c1;         // term chunk [c0, c1), c0 a multiple of 64
-  uint32_t n_win;          // ceil(S / 2^win_shift)
-  uint32_t win_shift;
-  uint32_t count_blocks;   // grid of the count and scatter kernels
-  uint32_t xstride;        // row length of xitem
-  uint16_t* tag;           // [chunk] window | coin << 15
-  uint32_t* entries;       // [chunk] term offset | coin << 31, window-contiguous
-  uint32_t* wcount;        // [n_win] histogram (zero between chunks)
-  uint32_t* woff;          // [n_win + 1] window offsets
-  uint32_t* cursor;        // [n_win] scatter cursors
-  uint32_t* xitem;         // [kXcds][xstride] prefix of 64-term items over the windows of each XCD
-};
+// gfx950: 8 XCDs; blocks are dispatched to them round-robin (block b on XCD b mod 8).
+constexpr uint32_t kXcds = 8;
 
 size_t layout_lds_bytes(uint32_t path_slots, uint32_t W);
 hipError_t launch_layout_iter(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
@@ -72,9 +56,6 @@ hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const
 hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s);
 hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s);
 const void* layout_iter_kernel();
-hipError_t launch_bin_count_scan_scatter(const BinLaunch& B, hipStream_t s);
-hipError_t launch_bin_layout(const BinLaunch& B, uint32_t blocks, hipStream_t s);
-const void* bin_layout_kernel();
 // fill kernel (stress_kernels.hip): p[0..n) = v, also inside captured HIP graphs
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 

@@ -3,7 +3,7 @@
 //   k_layout_iter   all terms of one iteration, fused: draw, sample, gather,
 //                   update, scatter (the hot path); with trace pointers set it
 //                   records the sampled terms instead (parity checks)
-//   k_apply_terms   the update alone on given terms
+//   k_apply_terms   the update alone on given terms (grid-stride)
 //   k_layout_reuse  the data-reuse variant (shared group path, reuse rounds in registers)
 //
 // Work mapping: a wavefront owns aligned groups of 64 consecutive terms, lane
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void k_layout_iter(LayoutLaunch P) {
       continue;
     }
     if (T.flags & 8u) continue;
+    if (P.apply_mask && !P.apply_mask[t - P.t_begin]) continue;  // parity hook: a chosen subset
     uint64_t a, b;
     float d;
     if (!resolve_term(P.rec, T, a, b, d)) continue;
@@ -124,13 +125,10 @@ __global__ __launch_bounds__(256) void k_layout_reuse(LayoutLaunch P) {
       A = Wc[a];
       B = Wc[b];
       const float d = (float)(pa < pb ? pb - pa : pa - pb);
-      const float dx = A.x - B.x, dy = A.y - B.y;
-      const float mag = sqrtf(dx * dx + dy * dy);
-      if (mag != 0.0f) {
-        const float mu = fminf(P.eta / (d * d), 1.0f);
-        const float rr = mu * (mag - d) / (2.0f * mag);
-        A = make_float2(A.x - rr * dx, A.y - rr * dy);
-        B = make_float2(B.x + rr * dx, B.y + rr * dy);
+      float2 m;
+      if (clamped_step(A, B, d, P.eta, m)) {
+        A = make_float2(A.x - m.x, A.y - m.y);
+        B = make_float2(B.x + m.x, B.y + m.y);
       }
     }
     if (P.drf > 1) {
@@ -147,14 +145,7 @@ __global__ __launch_bounds__(256) void k_layout_reuse(LayoutLaunch P) {
         float2 disp = make_float2(0.0f, 0.0f);
         if (valid && vm && a != bm && pa != pbm) {
           const float d = (float)(pa < pbm ? pbm - pa : pa - pbm);
-          const float dx = A.x - Bm.x, dy = A.y - Bm.y;
-          const float mag = sqrtf(dx * dx + dy * dy);
-          if (mag != 0.0f) {
-            const float mu = fminf(P.eta / (d * d), 1.0f);
-            const float rr = mu * (mag - d) / (2.0f * mag);
-            A = make_float2(A.x - rr * dx, A.y - rr * dy);
-            disp = make_float2(rr * dx, rr * dy);
-          }
+          if (clamped_step(A, Bm, d, P.eta, disp)) A = make_float2(A.x - disp.x, A.y - disp.y);
         }
         const float2 back = shfl_f2(disp, dst);
         B = make_float2(B.x + back.x, B.y + back.y);
@@ -171,17 +162,18 @@ __global__ __launch_bounds__(256) void k_apply_terms(const StepRec* __restrict__
                                                      float eta, const uint64_t* __restrict__ ti,
                                                      const uint64_t* __restrict__ tj,
                                                      const uint8_t* __restrict__ tf, uint64_t count) {
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  Term T;
-  T.i = ti[k];
-  T.j = tj[k];
-  T.flags = tf[k];
-  if (T.flags & 8u) return;
-  uint64_t a, b;
-  float d;
-  if (!resolve_term(rec, T, a, b, d)) return;
-  apply_update(work, a, b, d, eta);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
+    Term T;
+    T.i = ti[k];
+    T.j = tj[k];
+    T.flags = tf[k];
+    if (T.flags & 8u) continue;
+    uint64_t a, b;
+    float d;
+    if (!resolve_term(rec, T, a, b, d)) continue;
+    apply_update(work, a, b, d, eta);
+  }
 }
 
 // Boundary layout [2][n][2] (X plane, Y plane) <-> working copy W[2n+e] = (x, y).
@@ -219,16 +211,15 @@ hipError_t launch_layout_reuse(const LayoutLaunch& P, uint32_t blocks, uint32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const uint64_t* i, const uint64_t* j,
-                              const uint8_t* f, uint64_t count, hipStream_t s) {
-  const uint64_t blocks = (count + 255) / 256;
-  hipLaunchKernelGGL(k_apply_terms, dim3((uint32_t)blocks), dim3(256), 0, s, rec, work, eta, i, j, f, count);
-  return hipGetLastError();
-}
-
 static uint32_t elementwise_grid(uint64_t n) {
   const uint64_t b = (n + 255) / 256;
   return (uint32_t)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const uint64_t* i, const uint64_t* j,
+                              const uint8_t* f, uint64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_terms, dim3(elementwise_grid(count)), dim3(256), 0, s, rec, work, eta, i, j, f, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s) {

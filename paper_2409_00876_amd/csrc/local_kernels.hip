@@ -109,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_local_scan(LocalLaunch P) {
 // which a concurrent update of a (a node of the active window, where the
 // in-flight terms concentrate) can be lost is one L2 round trip instead of a
 // far memory access.  The empty asm makes the address of a depend on the
-// loaded b (no instruction is emitted).  Same arithmetic as apply_update.
+// loaded b (no instruction is emitted).  The step is clamped_step's.
 __device__ __forceinline__ void apply_update_far_first(float2* __restrict__ W, uint64_t a, uint64_t b, float d,
                                                        float eta) {
   const float2 pb = W[b];
@@ -117,13 +117,10 @@ __device__ __forceinline__ void apply_update_far_first(float2* __restrict__ W, u
   asm volatile("" : "+v"(lo) : "v"(pb.x), "v"(pb.y));
   a = (a & ~0xFFFFFFFFull) | lo;
   const float2 pa = W[a];
-  const float dx = pa.x - pb.x, dy = pa.y - pb.y;
-  const float mag = sqrtf(dx * dx + dy * dy);
-  if (mag == 0.0f) return;
-  const float mu = fminf(eta / (d * d), 1.0f);
-  const float r = mu * (mag - d) / (2.0f * mag);
-  W[a] = make_float2(pa.x - r * dx, pa.y - r * dy);
-  W[b] = make_float2(pb.x + r * dx, pb.y + r * dy);
+  float2 m;
+  if (!clamped_step(pa, pb, d, eta, m)) return;
+  W[a] = make_float2(pa.x - m.x, pa.y - m.y);
+  W[b] = make_float2(pb.x + m.x, pb.y + m.y);
 }
 
 // The 64 slots of item m of a run (windows worder[wb], worder[wb + 1], ...);
@@ -170,6 +167,8 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
     return;
   }
   if (T.flags & 8u) return;
+  // parity hook: only a chosen subset of the slots of [t_begin, t_end)
+  if (L.apply_mask && (s < L.t_begin || s >= L.t_end || !L.apply_mask[s - L.t_begin])) return;
   uint64_t a, b;
   float d;
   if (!resolve_term(L.rec, T, a, b, d)) return;
@@ -259,13 +258,10 @@ __device__ __forceinline__ void local_item_reuse(const LocalLaunch& P, const Lds
       A = Wc[(a & ~0xFFFFFFFFull) | lo];
     }
     const float d = (float)(pa < pb ? pb - pa : pa - pb);
-    const float dx = A.x - B.x, dy = A.y - B.y;
-    const float mag = sqrtf(dx * dx + dy * dy);
-    if (mag != 0.0f) {
-      const float mu = fminf(L.eta / (d * d), 1.0f);
-      const float rr = mu * (mag - d) / (2.0f * mag);
-      A = make_float2(A.x - rr * dx, A.y - rr * dy);
-      B = make_float2(B.x + rr * dx, B.y + rr * dy);
+    float2 m;
+    if (clamped_step(A, B, d, L.eta, m)) {
+      A = make_float2(A.x - m.x, A.y - m.y);
+      B = make_float2(B.x + m.x, B.y + m.y);
     }
   }
   for (uint32_t kk = 1; kk < L.drf; ++kk) {
@@ -280,14 +276,7 @@ __device__ __forceinline__ void local_item_reuse(const LocalLaunch& P, const Lds
     float2 disp = make_float2(0.0f, 0.0f);
     if (valid && vm && pm == p && a != bm && pa != pbm) {
       const float d = (float)(pa < pbm ? pbm - pa : pa - pbm);
-      const float dx = A.x - Bm.x, dy = A.y - Bm.y;
-      const float mag = sqrtf(dx * dx + dy * dy);
-      if (mag != 0.0f) {
-        const float mu = fminf(L.eta / (d * d), 1.0f);
-        const float rr = mu * (mag - d) / (2.0f * mag);
-        A = make_float2(A.x - rr * dx, A.y - rr * dy);
-        disp = make_float2(rr * dx, rr * dy);
-      }
+      if (clamped_step(A, Bm, d, L.eta, disp)) A = make_float2(A.x - disp.x, A.y - disp.y);
     }
     const float2 back = shfl_f2(disp, dst);
     B = make_float2(B.x + back.x, B.y + back.y);

@@ -39,7 +39,7 @@ def test_binding_constants_match_the_header():
                "PGSGD_ERR_OOM": _lib.ERR_OOM, "PGSGD_ERR_DEVICE": _lib.ERR_DEVICE,
                "PGSGD_ERR_UNSUPPORTED": _lib.ERR_UNSUPPORTED,
                "PGSGD_SCHEDULE_AUTO": _lib.SCHEDULE_AUTO, "PGSGD_SCHEDULE_PLAIN": _lib.SCHEDULE_PLAIN,
-               "PGSGD_SCHEDULE_BINNED": _lib.SCHEDULE_BINNED, "PGSGD_SCHEDULE_WINDOWED": _lib.SCHEDULE_WINDOWED,
+               "PGSGD_SCHEDULE_WINDOWED": _lib.SCHEDULE_WINDOWED,
                "PGSGD_PAIRS_UNIFORM": _lib.PAIRS_UNIFORM, "PGSGD_PAIRS_POWER_LAW": _lib.PAIRS_POWER_LAW,
                "PGSGD_PAIRS_UNIFORM_WINDOWED": _lib.PAIRS_UNIFORM_WINDOWED,
                "PGSGD_FLAG_COUNT_AHEAD": _lib.FLAG_COUNT_AHEAD, "PGSGD_FLAG_COUNT_IN_ORDER": _lib.FLAG_COUNT_IN_ORDER}

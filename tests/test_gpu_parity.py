@@ -3,8 +3,9 @@
 Bars (from the method's definition):
   - sampled terms (i, j, flags) bit-exact, recorded by the production layout
     kernel with the production launch shape;
-  - one collision-free batch of updates within 1e-5 (relative to max(|x|, 1))
-    of the pure-FP64 oracle;
+  - one collision-free batch of updates within 1e-5 of the displacement of the
+    pure-FP64 oracle, plus FP32 storage and evaluation rounding
+    (batch_check.py), for the update kernel and for the layout kernels;
   - sampled path stress of the same layout: identical pair counts, sums within
     1e-9 relative (FP64 terms, different summation order);
   - full Hogwild layouts: sampled path stress within 3% of the oracle's (several
@@ -22,6 +23,7 @@ import os
 import numpy as np
 import pytest
 
+import batch_check as B
 import oracle as O
 import synth
 
@@ -139,37 +141,10 @@ def test_sampling_bitexact_large_range(P, mid):
     _compare_terms(P, g, og, 0, 123456789, 1 << 22)
 
 
-# ---------------------------------------------------------------------------
-# The binned schedule: the same terms, recorded by its own kernels
-# ---------------------------------------------------------------------------
-@pytest.mark.parametrize("it", [0, 15])
-def test_binned_sampling_bitexact_mid(P, mid, it):
-    import torch
-    sg, og, g = mid
-    T = 10 * og.S
-    for t0, n in ((0, 1 << 20), (T // 3 + 17, 1 << 18), (T - (1 << 18) - 3, (1 << 18) + 3)):
-        _compare_terms(P, g, og, it, t0, n, schedule=2)
-    # the whole iteration: every term recorded once, equal to the plain kernel's record
-    bi, bj, bf = P.sample_terms(g, it, 0, T, schedule=2)
-    assert not bool((bf == 255).any()), "a term was not processed by the binned schedule"
-    pi, pj, pf = P.sample_terms(g, it, 0, T, schedule=1)
-    assert torch.equal(bi, pi) and torch.equal(bj, pj) and torch.equal(bf, pf)
-
-
 @pytest.fixture(scope="module")
 def chromosome(P):
     sg = synth.config_graph("chromosome")
     return sg, O.Graph.from_synth(sg), P.Graph.from_synth(sg)
-
-
-@pytest.mark.parametrize("it", [0, 29])
-def test_binned_sampling_bitexact_chromosome(P, chromosome, it):
-    # full size, in the launch shape the benchmark times (binned, 4 chunks)
-    sg, og, g = chromosome
-    T = 10 * og.S
-    for t0, n in ((0, 1 << 20), ((1 << 30) - (1 << 19), 1 << 20), (T - (1 << 20) - 5, (1 << 20) + 5)):
-        f = _compare_terms(P, g, og, it, t0, n, schedule=2)
-        assert not np.any(f == 255)
 
 
 # ---------------------------------------------------------------------------
@@ -350,67 +325,62 @@ def test_windowed_reuse_sampling_bitexact(P, which, it, request):
 # ---------------------------------------------------------------------------
 # T6b: one collision-free deterministic batch
 # ---------------------------------------------------------------------------
-def _collision_free(og, i, j, f, limit):
-    step_node = og.step_node
-    a = 2 * (step_node[i.astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + (f & 1)
-    b = 2 * (step_node[j.astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + ((f >> 1) & 1)
-    seen = set()
-    keep = []
-    for k in range(len(i)):
-        if f[k] & 8:
-            continue
-        if a[k] in seen or b[k] in seen:
-            continue
-        seen.add(int(a[k]))
-        seen.add(int(b[k]))
-        keep.append(k)
-        if len(keep) >= limit:
-            break
-    return np.array(keep, np.int64)
+def _batch_and_check(og, it, i, j, f, got_fn):
+    """Keeps a collision-free subset of the sampled terms (i, j, f), lets
+    got_fn(keep, start, eta) apply it on the GPU and checks the result against
+    the oracle's FP64 batch (batch_check.check)."""
+    keep = B.collision_free(og, i, j, f)
+    assert keep.size > 2000
+    eta = float(O.schedule(30, float(og.d_max) ** 2, 0.01).astype(np.float32)[it])
+    start = B.start_coords(og, it)
+    got = got_fn(keep, start, eta)
+    ref, applied = B.fp64_result(og, eta, i[keep], j[keep], f[keep], start)
+    assert applied == keep.size
+    worst, untouched = B.check(og, og.pos, i[keep], j[keep], f[keep], eta, start, got, ref)
+    assert worst <= 1.0, f"worst error / bound = {worst:.3f}"
+    assert untouched, "a coordinate outside the batch changed"
+    assert np.count_nonzero(got != start.astype(np.float64)) >= keep.size  # the batch really moved points
 
 
 @pytest.mark.parametrize("which", ["tiny", "mid"])
 @pytest.mark.parametrize("it", [0, 25])
 def test_collision_free_batch_matches_fp64(P, which, it, request):
+    # the update kernel on given terms (k_apply_terms)
     import torch
     sg, og, g = request.getfixturevalue(which)
-    K = 65536
-    i, j, f = P.sample_terms(g, it, 0, K, schedule=1)
+    i, j, f = P.sample_terms(g, it, 0, B.K_TERMS, schedule=1)
     gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
-    keep = _collision_free(og, gi, gj, gf, K)
-    assert keep.size > 1000
-    eta = float(P.schedule(d_max=og.d_max)[it])
-    rng = np.random.default_rng(it)
-    start = O.init_coords(og)
-    start = (start + rng.normal(scale=20.0, size=start.shape)).astype(np.float32)
-    c = torch.from_numpy(start).cuda()
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
-    P.apply_terms(g, c, eta, dev(gi[keep].astype(np.int64)), dev(gj[keep].astype(np.int64)), dev(gf[keep]))
-    got = c.cpu().numpy().astype(np.float64)
-    ref = start.astype(np.float64)
-    applied = O.apply_terms_f64(og, eta, gi[keep], gj[keep], gf[keep], ref)
-    assert applied > 0.9 * keep.size
-    # Relative error per coordinate, relative to the magnitude of the update's
-    # operands: the two points' coordinates on that axis before and after (FP32
-    # inputs carry an absolute rounding proportional to them, so a coordinate
-    # that cancels to ~0 cannot be more accurate than that).
-    n2 = 2 * og.n_nodes
-    ki = keep
-    a = 2 * (og.step_node[gi[ki].astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + (gf[ki] & 1)
-    b = 2 * (og.step_node[gj[ki].astype(np.int64)] & 0x7FFFFFFF).astype(np.int64) + ((gf[ki] >> 1) & 1)
-    scale = np.ones_like(ref)
-    for off in (0, n2):
-        m = np.maximum.reduce([np.abs(start[off + a]), np.abs(start[off + b]), np.abs(ref[off + a]),
-                               np.abs(ref[off + b]), np.ones(a.size)])
-        scale[off + a] = np.maximum(scale[off + a], m)
-        scale[off + b] = np.maximum(scale[off + b], m)
-    err = np.abs(got - ref) / scale
-    assert err.max() <= 1e-5, f"max relative error {err.max():.3e}"
-    touched = np.zeros(ref.size, bool)
-    touched[a] = touched[b] = touched[n2 + a] = touched[n2 + b] = True
-    assert np.array_equal(got[~touched], start[~touched].astype(np.float64)), "untouched coordinates changed"
-    moved = np.abs(ref - start) > 0
-    assert moved.sum() >= applied  # the batch really moved points
+    oi, oj, of = O.sample_terms(og, it, 0, B.K_TERMS)
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj) and np.array_equal(gf, of)
+
+    def run(keep, start, eta):
+        c = torch.from_numpy(start).cuda()
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+        P.apply_terms(g, c, eta, dev(gi[keep].astype(np.int64)), dev(gj[keep].astype(np.int64)), dev(gf[keep]))
+        return c.cpu().numpy().astype(np.float64)
+
+    _batch_and_check(og, it, gi, gj, gf, run)
+
+
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+@pytest.mark.parametrize("it", [0, 25])
+@pytest.mark.parametrize("schedule", [1, 3])
+def test_collision_free_batch_in_the_layout_kernel(P, which, it, schedule, request):
+    # the layout kernels themselves (plain k_layout_iter, windowed k_layout_local with
+    # its far-first loads), in the layout's launch shape, applying only the batch
+    import torch
+    sg, og, g = request.getfixturevalue(which)
+    i, j, f = P.sample_terms(g, it, 0, B.K_TERMS, schedule=schedule)
+    gi, gj, gf = _to_np_u64(i), _to_np_u64(j), f.cpu().numpy()
+
+    def run(keep, start, eta):
+        c = torch.from_numpy(start).cuda()
+        mask = np.zeros(B.K_TERMS, np.uint8)
+        mask[keep] = 1
+        P.apply_slots(g, c, it, 0, torch.from_numpy(mask).cuda(), schedule=schedule)
+        return c.cpu().numpy().astype(np.float64)
+
+    _batch_and_check(og, it, gi, gj, gf, run)
 
 
 # ---------------------------------------------------------------------------
