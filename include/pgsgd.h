@@ -106,6 +106,60 @@ void pgsgd_graph_destroy(pgsgd_graph *g);
 pgsgd_status pgsgd_graph_get_info(const pgsgd_graph *g, pgsgd_graph_info *out);
 
 /* ------------------------------------------------------------------------- */
+/* Reading a graph from GFA text                                              */
+/* ------------------------------------------------------------------------- */
+/*
+ * The layout reads the paths and node lengths of a graph only (Alg. 1 takes P
+ * and the node lengths; the kernel of Section "CUDA Kernel for Pangenome Graph
+ * Layout" keeps that lean structure), and the paper's inputs are the human
+ * pangenome graphs of Section "Experiment Setup" in GFA/ODGI form.  These calls
+ * turn GFA 1.0/1.1 text into exactly the arrays pgsgd_graph_create takes:
+ *   - S <name> <sequence|*> [LN:i:<len>]  node of length |sequence| (or LN;
+ *     both given must agree; '*' needs LN); length >= 1 and < 2^32.  Node ids
+ *     follow the order of the S lines: the k-th S line is node k.
+ *   - P <name> <seg><+|->,... <overlaps>  a path; '-' is a reverse-strand step
+ *     (bit 31 of step_node); '*' is an empty path.
+ *   - W <sample> <hap> <seqid> <start> <end> <walk>  a path named
+ *     sample#hap#seqid (":start-end" appended unless start is '*'); the walk
+ *     is a run of '>seg' (forward) and '<seg' (reverse) steps, '*' = empty.
+ *   - L lines are counted (n_links) and otherwise ignored, as are comments
+ *     ('#'), headers and all other record types; "\r\n" line ends are accepted.
+ * Paths are numbered in file order (P and W lines together); a path may name
+ * segments whose S line comes later.  Only uncompressed text is read.
+ * Errors (nothing is returned on error): INVALID_ARG for a file that cannot be
+ * opened or read, a malformed line, a segment defined twice, a step naming a
+ * segment without an S line, a length that is 0, missing or contradicted by
+ * LN, a step without orientation, a path name used twice (the message names
+ * the line); RANGE for 2^31 or more segments, a path of 2^32 or more steps,
+ * 2^40 or more steps, more than 2^20 paths, a segment of 2^32 nt or more;
+ * UNSUPPORTED for a GFA 2 header (VN:Z:2.x); OOM.  Host only; no device work.
+ */
+typedef struct pgsgd_gfa pgsgd_gfa;
+typedef struct {
+  uint32_t n_nodes;
+  uint32_t n_paths;
+  uint64_t n_steps;
+  uint64_t n_links;                  /* L lines read (edges are not used by the layout) */
+  const uint32_t *node_len;          /* n_nodes */
+  const uint64_t *path_offsets;      /* n_paths + 1, CSR offsets into step_node */
+  const uint32_t *step_node;         /* n_steps; bit 31 = reverse-strand step */
+  const char *node_names;            /* NUL-terminated names back to back ... */
+  const uint64_t *node_name_offsets; /* ... node k's name starts at node_names + offsets[k]; n_nodes + 1 entries */
+  const char *path_names;            /* likewise for paths */
+  const uint64_t *path_name_offsets; /* n_paths + 1 entries */
+} pgsgd_gfa_view;
+
+/* Reads the GFA file `filename` (host path) into a new handle *out. */
+pgsgd_status pgsgd_gfa_read(const char *filename, pgsgd_gfa **out);
+/* The same from n_bytes of text in host memory (need not be NUL-terminated). */
+pgsgd_status pgsgd_gfa_parse(const char *text, uint64_t n_bytes, pgsgd_gfa **out);
+/* Pointers into the handle's arrays (valid until pgsgd_gfa_free); pass
+ * node_len, path_offsets and step_node to pgsgd_graph_create. */
+pgsgd_status pgsgd_gfa_get_view(const pgsgd_gfa *gfa, pgsgd_gfa_view *out);
+/* Frees the handle.  NULL-safe. */
+void pgsgd_gfa_free(pgsgd_gfa *gfa);
+
+/* ------------------------------------------------------------------------- */
 /* Layout parameters (Alg. 1 inputs: schedule S and N_iters)                  */
 /* ------------------------------------------------------------------------- */
 typedef struct {

@@ -19,10 +19,10 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
+from ._lib import (GfaView, FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
                    check, lib)
 
-__all__ = ["Graph", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
+__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
            "sample_terms", "sample_terms_reuse", "apply_terms", "apply_slots", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
@@ -83,6 +83,77 @@ def _params(params, kw) -> Params:
     return params.to_c()
 
 
+@dataclass
+class GfaGraph:
+    """The lean structure of a GFA file (the arrays Graph takes), with names.
+
+    node_len  : uint32[n_nodes]; node k is the k-th S line
+    path_off  : uint64[n_paths+1]; path p is the p-th P or W line
+    step_node : uint32[S]; bit 31 = reverse-strand step
+    """
+    node_len: np.ndarray
+    path_off: np.ndarray
+    step_node: np.ndarray
+    path_names: list
+    n_links: int
+    _node_names: bytes
+    _node_name_off: np.ndarray
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.node_len.shape[0])
+
+    @property
+    def n_paths(self) -> int:
+        return int(self.path_off.shape[0]) - 1
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.path_off[-1])
+
+    def node_name(self, k: int) -> str:
+        return self._node_names[int(self._node_name_off[k]):int(self._node_name_off[k + 1]) - 1].decode()
+
+
+def _gfa_from_handle(h) -> GfaGraph:
+    try:
+        v = GfaView()
+        check(lib().pgsgd_gfa_get_view(h, ctypes.byref(v)))
+
+        def arr(ptr, n, ctype, dtype):
+            if n == 0:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctype)), shape=(n,)).astype(dtype, copy=True)
+
+        nn, npth, ns = int(v.n_nodes), int(v.n_paths), int(v.n_steps)
+        node_len = arr(v.node_len, nn, ctypes.c_uint32, np.uint32)
+        path_off = arr(v.path_offsets, npth + 1, ctypes.c_uint64, np.uint64)
+        step_node = arr(v.step_node, ns, ctypes.c_uint32, np.uint32)
+        noff = arr(v.node_name_offsets, nn + 1, ctypes.c_uint64, np.uint64)
+        poff = arr(v.path_name_offsets, npth + 1, ctypes.c_uint64, np.uint64)
+        nnames = ctypes.string_at(v.node_names, int(noff[-1])) if nn else b""
+        pblob = ctypes.string_at(v.path_names, int(poff[-1])) if npth else b""
+        pnames = [pblob[int(poff[k]):int(poff[k + 1]) - 1].decode() for k in range(npth)]
+        return GfaGraph(node_len, path_off, step_node, pnames, int(v.n_links), nnames, noff)
+    finally:
+        lib().pgsgd_gfa_free(h)
+
+
+def read_gfa(path: str) -> GfaGraph:
+    """Reads a GFA 1.0/1.1 file (S, P and W lines) into the lean structure."""
+    h = ctypes.c_void_p()
+    check(lib().pgsgd_gfa_read(os.fsencode(path), ctypes.byref(h)))
+    return _gfa_from_handle(h)
+
+
+def parse_gfa(text) -> GfaGraph:
+    """The same as read_gfa for GFA text held in memory (str or bytes)."""
+    data = text.encode() if isinstance(text, str) else bytes(text)
+    h = ctypes.c_void_p()
+    check(lib().pgsgd_gfa_parse(data, len(data), ctypes.byref(h)))
+    return _gfa_from_handle(h)
+
+
 class Graph:
     """A variation graph resident on one GPU (node lengths and path steps)."""
 
@@ -108,6 +179,12 @@ class Graph:
     @classmethod
     def from_synth(cls, sg, device: int = 0):
         return cls(sg.node_len, sg.path_off, sg.step_node, device=device)
+
+    @classmethod
+    def from_gfa(cls, path: str, device: int = 0):
+        """Reads a GFA file and copies its paths and node lengths to the device."""
+        gg = read_gfa(path)
+        return cls(gg.node_len, gg.path_off, gg.step_node, device=device)
 
     @property
     def handle(self):

@@ -86,6 +86,22 @@ class Tune(ctypes.Structure):
     ]
 
 
+class GfaView(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_uint32),
+        ("n_paths", ctypes.c_uint32),
+        ("n_steps", ctypes.c_uint64),
+        ("n_links", ctypes.c_uint64),
+        ("node_len", ctypes.c_void_p),
+        ("path_offsets", ctypes.c_void_p),
+        ("step_node", ctypes.c_void_p),
+        ("node_names", ctypes.c_void_p),
+        ("node_name_offsets", ctypes.c_void_p),
+        ("path_names", ctypes.c_void_p),
+        ("path_name_offsets", ctypes.c_void_p),
+    ]
+
+
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
 _u32, _u64, _i32, _i64, _f32, _f64 = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64,
@@ -93,6 +109,10 @@ _u32, _u64, _i32, _i64, _f32, _f64 = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c
 SIGNATURES = {
     "pgsgd_last_error": ([], ctypes.c_char_p),
     "pgsgd_version": ([], ctypes.c_char_p),
+    "pgsgd_gfa_read": ([ctypes.c_char_p, _P], _i32),
+    "pgsgd_gfa_parse": ([ctypes.c_char_p, _u64, _P], _i32),
+    "pgsgd_gfa_get_view": ([_P, _P], _i32),
+    "pgsgd_gfa_free": ([_P], None),
     "pgsgd_graph_create": ([_u32, _P, _u32, _P, _P, _P, ctypes.c_int, _P], _i32),
     "pgsgd_graph_destroy": ([_P], None),
     "pgsgd_graph_get_info": ([_P, _P], _i32),

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB_PATH = os.path.join(HERE, "libpgsgd.so")
-SOURCES = ["capi.hip", "layout_kernels.hip", "batch_kernels.hip", "local_kernels.hip", "stress_kernels.hip"]
+SOURCES = ["capi.hip", "layout_kernels.hip", "batch_kernels.hip", "local_kernels.hip", "stress_kernels.hip", "gfa.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -34,13 +34,17 @@ namespace {
 
 thread_local std::string g_last_error;
 
-pgsgd_status fail(pgsgd_status code, const char* fmt, ...) {
+void set_message(const char* fmt, va_list ap) {
   char buf[512];
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  g_last_error = buf;
+}
+
+pgsgd_status fail(pgsgd_status code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  set_message(fmt, ap);
   va_end(ap);
-  g_last_error = buf;
   return code;
 }
 
@@ -48,6 +52,24 @@ pgsgd_status ok() {
   g_last_error.clear();
   return PGSGD_OK;
 }
+
+}  // namespace
+
+namespace pgsgd {
+
+int32_t set_error(int32_t code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  set_message(fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int32_t clear_error() { return ok(); }
+
+}  // namespace pgsgd
+
+namespace {
 
 #define HIP_TRY(expr)                                                                                    \
   do {                                                                                                   \

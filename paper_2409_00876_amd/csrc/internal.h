@@ -56,6 +56,11 @@ hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const
 hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s);
 hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s);
 const void* layout_iter_kernel();
+// Error reporting shared by the host files (capi.hip): set_error stores the
+// calling thread's pgsgd_last_error() message and returns `code`;
+// clear_error empties it and returns PGSGD_OK.
+int32_t set_error(int32_t code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int32_t clear_error();
 // fill kernel (stress_kernels.hip): p[0..n) = v, also inside captured HIP graphs
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 

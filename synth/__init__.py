@@ -150,3 +150,33 @@ def random_coords(n_nodes: int, seed: int, scale: float) -> np.ndarray:
     """Random float32 coordinates in the boundary layout [2][n_nodes][2]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return (rng.random((2, n_nodes, 2)) * scale).astype(np.float32)
+
+
+def write_gfa(sg: SynthGraph, path: str, walks: bool = False, names: str = "numeric", sequence: bool = False,
+              path_prefix: str = "hap") -> None:
+    """Writes a graph as GFA 1.x text: one S line per node in id order (so the
+    k-th S line is node k again when read back), then one P line per path, or
+    one W line per path when ``walks`` (GFA 1.1).  ``names``: "numeric" gives
+    segment k the name k+1, "text" the name "s<k>".  ``sequence`` writes a
+    sequence of the node's length instead of '*' with an LN tag.  Output
+    formatting only."""
+    def seg(k: int) -> str:
+        return str(k + 1) if names == "numeric" else f"s{k}"
+
+    with open(path, "w") as f:
+        f.write("H\tVN:Z:1.1\n" if walks else "H\tVN:Z:1.0\n")
+        for k, ln in enumerate(sg.node_len.tolist()):
+            if sequence:
+                f.write(f"S\t{seg(k)}\t{'ACGT' * (ln // 4)}{'ACGT'[:ln % 4]}\n")
+            else:
+                f.write(f"S\t{seg(k)}\t*\tLN:i:{ln}\n")
+        off = sg.path_off.tolist()
+        steps = sg.step_node
+        for p in range(sg.n_paths):
+            s = steps[off[p]:off[p + 1]].tolist()
+            if walks:
+                body = "".join(("<" if v & REV_BIT else ">") + seg(v & (REV_BIT - 1)) for v in s) or "*"
+                f.write(f"W\t{path_prefix}{p}\t0\tchr\t*\t*\t{body}\n")
+            else:
+                body = ",".join(seg(v & (REV_BIT - 1)) + ("-" if v & REV_BIT else "+") for v in s) or "*"
+                f.write(f"P\t{path_prefix}{p}\t{body}\t*\n")

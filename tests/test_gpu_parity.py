@@ -439,7 +439,7 @@ def test_graph_without_steps(P):
     assert g.n_steps == 0
     c = torch.arange(8, dtype=torch.float32, device="cuda")
     before = c.clone()
-    for sched in (0, 1, 2, 3):
+    for sched in (0, 1, 3):
         P.layout(g, c, schedule=sched)
     for pairs in ("uniform", "uniform_windowed", "power_law"):
         r = P.path_stress(g, c, 10, 7, pairs=pairs)
