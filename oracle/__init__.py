@@ -20,18 +20,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# PGSGD_SANITIZED=1 loads the AddressSanitizer/UndefinedBehaviorSanitizer
+# build (tests run it in a child process with the sanitizer runtimes preloaded)
+SANITIZED = os.environ.get("PGSGD_SANITIZED") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if SANITIZED else "liboracle.so")
 _lib = None
+SAN_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 # Compiled without FMA contraction or fast-math so each FP64 expression is
 # evaluated exactly as written.
 CFLAGS = ["-O2", "-fPIC", "-shared", "-std=gnu11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-pthread"]
 
 
-def build(force: bool = True) -> str:
-    if force or not os.path.exists(_LIB_PATH):
-        subprocess.check_call(["gcc", *CFLAGS, "-o", _LIB_PATH, _SRC, "-lm"])
-    return _LIB_PATH
+def build(force: bool = True, sanitized: bool = None) -> str:
+    """Compiles liboracle.so (or, sanitized, liboracle_san.so) with gcc."""
+    san = SANITIZED if sanitized is None else sanitized
+    path = os.path.join(_HERE, "liboracle_san.so" if san else "liboracle.so")
+    if force or not os.path.exists(path):
+        flags = [f for f in CFLAGS if f != "-O2"] + SAN_FLAGS if san else CFLAGS
+        subprocess.check_call(["gcc", *flags, "-o", path, _SRC, "-lm"])
+    return path
 
 
 def _load():
@@ -78,6 +86,9 @@ def _load():
         "or_path_stress_exact": ([P, P, P], None),
         "or_init_coords": ([P, u64, u32, f32, P], None),
         "or_stress_loss_grad": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
+        "or_loss_segment_counts": ([P, u64, u64, u32, u32, P, u64, P], None),
+        "or_loss_windowed_pairs": ([P, u64, f64, u32, u64, u32, u32, u64, u64, P, P, P], None),
+        "or_stress_loss_grad_windowed": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -384,4 +395,36 @@ def stress_loss_grad(g: Graph, coords: np.ndarray, n_pairs: int, seed: int = 11,
     grad = np.zeros(4 * g.n_nodes, dtype=np.float64) if want_grad else None
     _load().or_stress_loss_grad(g._h, _p(coords), int(n_pairs), float(theta), int(window), int(seed),
                                 int(graph_id), int(step), _p(out), _p(grad))
+    return float(out[0]), int(out[1]), grad
+
+
+def loss_segment_counts(g: Graph, n_pairs: int, seed: int = 11, step: int = 0, graph_id: int = 0) -> np.ndarray:
+    """Slots per segment of the window-major loss pairs (reading R22)."""
+    start, _ = sps_segments(g)
+    n = len(start) - 1
+    out = np.zeros(max(1, n), dtype=np.uint64)
+    _load().or_loss_segment_counts(g._h, int(n_pairs), int(seed), int(graph_id), int(step), _p(start), n, _p(out))
+    return out[:n]
+
+
+def loss_windowed_pairs(g: Graph, n_pairs: int, u_begin: int, count: int, seed: int = 11, step: int = 0,
+                        theta=0.99, window=1000, graph_id=0):
+    """Slots [u_begin, u_begin + count) of the window-major loss pairs: i, j,
+    flags (e_i | e_j << 1 | skipped << 3)."""
+    i = np.zeros(count, dtype=np.uint64)
+    j = np.zeros(count, dtype=np.uint64)
+    f = np.zeros(count, dtype=np.uint8)
+    _load().or_loss_windowed_pairs(g._h, int(n_pairs), float(theta), int(window), int(seed), int(graph_id),
+                                   int(step), int(u_begin), int(count), _p(i), _p(j), _p(f))
+    return i, j, f
+
+
+def stress_loss_grad_windowed(g: Graph, coords: np.ndarray, n_pairs: int, seed: int = 11, step: int = 0,
+                              theta=0.99, window=1000, graph_id=0, want_grad=True):
+    """The loss and its gradient over the window-major pairs (reading R22)."""
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    out = np.zeros(2, dtype=np.float64)
+    grad = np.zeros(4 * g.n_nodes, dtype=np.float64) if want_grad else None
+    _load().or_stress_loss_grad_windowed(g._h, _p(coords), int(n_pairs), float(theta), int(window), int(seed),
+                                         int(graph_id), int(step), _p(out), _p(grad))
     return float(out[0]), int(out[1]), grad

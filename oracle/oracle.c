@@ -1271,3 +1271,140 @@ void or_stress_loss_grad(const or_graph *g, const float *coords, uint64_t n_pair
   }
   free((void *)sp.zipf);
 }
+
+/* ---------------------------------------------------------------------------
+ * The differentiable loss with its pairs in window-major order (reading R22):
+ * the law of pairs of or_stress_loss_grad (n_pairs pairs; i uniform over all
+ * steps; j the power-law partner of i in its path; independent endpoint
+ * coins), listed segment by segment over the segments of R21 (the windows of
+ * 2^h steps cut at path boundaries, in step order).  Segment g receives n_g
+ * slots, the number of the loss's own pairs q < n_pairs whose step i falls in
+ * it; slot u (numbered over the segments in order) draws Philox stream 7 at
+ * counter u with word 2 = the optimiser step: i = segment start +
+ * floor(u64 * segment length / 2^64), j = the power-law partner of i from
+ * words 2 and 3 (as the cooling phase draws it), e_i = bit 0 and e_j = bit 1
+ * of word 3.  Multinomial counts of uniform steps per segment followed by a
+ * uniform step inside the segment are n_pairs independent uniform steps, and
+ * each slot's partner and coins are drawn afresh, so the pairs follow the
+ * same law.  Loss and gradient as in or_stress_loss_grad.
+ * ------------------------------------------------------------------------- */
+enum { STREAM_LOSS_SLOT = 7 };
+
+/* n_g of every segment for the loss's pairs of optimiser step `step` */
+void or_loss_segment_counts(const or_graph *g, uint64_t n_pairs, uint64_t seed, uint32_t graph_id, uint32_t step,
+                            const uint64_t *start, uint64_t n_seg, uint64_t *counts) {
+  memset(counts, 0, sizeof(uint64_t) * n_seg);
+  for (uint64_t q = 0; q < n_pairs; ++q) {
+    uint32_t r[4];
+    draw(seed, q, step, STREAM_PAIRS, graph_id, r);
+    uint64_t i = mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), g->S);
+    ++counts[segment_of(start, n_seg, i)];
+  }
+}
+
+/* Slot u of segment [seg_start, seg_start + seg_len) of path p.  Returns 0 when
+ * the pair is skipped (no partner, the same endpoint slot, or d = 0). */
+static int loss_slot(const or_graph *g, const sampler *sp, uint32_t step, uint64_t u, uint64_t seg_start,
+                     uint64_t seg_len, uint32_t p, uint64_t *i, uint64_t *j, uint32_t *ei, uint32_t *ej,
+                     uint64_t *a, uint64_t *b, double *d) {
+  uint32_t r[4];
+  draw(sp->seed, u, step, STREAM_LOSS_SLOT, sp->graph_id, r);
+  *i = seg_start + mulhi64((uint64_t)r[0] | ((uint64_t)r[1] << 32), seg_len);
+  uint64_t start = g->path_off[p], len = g->path_off[p + 1] - start;
+  int skip = 0;
+  partner_power_law(g, sp, *i, start, len, r[2], r[3], j, &skip);
+  *ei = r[3] & 1u;
+  *ej = (r[3] >> 1) & 1u;
+  if (skip) return 0;
+  *a = 2ull * step_node_id(g, *i) + *ei;
+  *b = 2ull * step_node_id(g, *j) + *ej;
+  int64_t dd = or_endpoint_pos(g, *i, *ei) - or_endpoint_pos(g, *j, *ej);
+  if (*a == *b || dd == 0) return 0;
+  *d = (double)(dd < 0 ? -dd : dd);
+  return 1;
+}
+
+typedef struct {
+  uint64_t n_seg;
+  uint64_t *start, *cnt;
+  uint32_t *path;
+} loss_segments;
+
+static void loss_segments_make(const or_graph *g, uint64_t n_pairs, uint64_t seed, uint32_t graph_id, uint32_t step,
+                               loss_segments *ls) {
+  ls->n_seg = or_sps_segments(g, NULL, NULL);
+  ls->start = (uint64_t *)malloc(sizeof(uint64_t) * (ls->n_seg + 1));
+  ls->path = (uint32_t *)malloc(sizeof(uint32_t) * (ls->n_seg + 1));
+  ls->cnt = (uint64_t *)malloc(sizeof(uint64_t) * (ls->n_seg + 1));
+  or_sps_segments(g, ls->start, ls->path);
+  or_loss_segment_counts(g, n_pairs, seed, graph_id, step, ls->start, ls->n_seg, ls->cnt);
+}
+
+static void loss_segments_free(loss_segments *ls) {
+  free(ls->start); free(ls->path); free(ls->cnt);
+}
+
+/* The slots [u_begin, u_begin + count): i, j and flags e_i | e_j << 1 | skipped << 3. */
+void or_loss_windowed_pairs(const or_graph *g, uint64_t n_pairs, double theta, uint32_t W, uint64_t seed,
+                            uint32_t graph_id, uint32_t step, uint64_t u_begin, uint64_t count, uint64_t *i_out,
+                            uint64_t *j_out, uint8_t *f_out) {
+  sampler sp;
+  make_sampler(&sp, 2, theta, W, seed, graph_id);
+  loss_segments ls;
+  loss_segments_make(g, n_pairs, seed, graph_id, step, &ls);
+  uint64_t u = 0;
+  for (uint64_t s = 0; s < ls.n_seg && u < u_begin + count; ++s)
+    for (uint64_t k = 0; k < ls.cnt[s]; ++k, ++u) {
+      if (u < u_begin || u >= u_begin + count) continue;
+      uint64_t i, j = 0, a, b; uint32_t ei, ej; double d;
+      int ok = loss_slot(g, &sp, step, u, ls.start[s], ls.start[s + 1] - ls.start[s], ls.path[s], &i, &j, &ei,
+                         &ej, &a, &b, &d);
+      i_out[u - u_begin] = i;
+      j_out[u - u_begin] = j;
+      f_out[u - u_begin] = (uint8_t)(ei | (ej << 1) | (ok ? 0u : 8u));
+    }
+  loss_segments_free(&ls);
+  free((void *)sp.zipf);
+}
+
+void or_stress_loss_grad_windowed(const or_graph *g, const float *coords, uint64_t n_pairs, double theta, uint32_t W,
+                                  uint64_t seed, uint32_t graph_id, uint32_t step, double *out, double *grad) {
+  sampler sp;
+  make_sampler(&sp, 2, theta, W, seed, graph_id);
+  loss_segments ls;
+  loss_segments_make(g, n_pairs, seed, graph_id, step, &ls);
+  const float *X = coords, *Y = coords + 2ull * g->n_nodes;
+  double sum = 0.0;
+  uint64_t n = 0;
+  for (int pass = 1; pass <= 2; ++pass) {
+    if (pass == 2) {
+      if (!grad) break;
+      memset(grad, 0, sizeof(double) * 4ull * g->n_nodes);
+      if (n == 0) break;
+    }
+    double *GX = grad, *GY = grad ? grad + 2ull * g->n_nodes : NULL;
+    uint64_t u = 0;
+    for (uint64_t s = 0; s < ls.n_seg; ++s)
+      for (uint64_t k = 0; k < ls.cnt[s]; ++k, ++u) {
+        uint64_t i, j, a, b; uint32_t ei, ej; double d;
+        if (!loss_slot(g, &sp, step, u, ls.start[s], ls.start[s + 1] - ls.start[s], ls.path[s], &i, &j, &ei, &ej,
+                       &a, &b, &d))
+          continue;
+        double dx = (double)X[a] - (double)X[b], dy = (double)Y[a] - (double)Y[b];
+        double mag = sqrt(dx * dx + dy * dy);
+        if (pass == 1) {
+          double e = (mag - d) / d;
+          sum += e * e;
+          ++n;
+        } else if (mag != 0.0) {
+          double c = 2.0 / (double)n * (mag - d) / (d * d) / mag;
+          GX[a] += c * dx; GY[a] += c * dy;
+          GX[b] -= c * dx; GY[b] -= c * dy;
+        }
+      }
+  }
+  out[0] = n ? sum / (double)n : 0.0;
+  out[1] = (double)n;
+  loss_segments_free(&ls);
+  free((void *)sp.zipf);
+}

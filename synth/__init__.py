@@ -22,18 +22,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "synth.c")
-_LIB_PATH = os.path.join(_HERE, "libsynth.so")
+# PGSGD_SANITIZED=1 loads the AddressSanitizer/UndefinedBehaviorSanitizer build
+SANITIZED = os.environ.get("PGSGD_SANITIZED") == "1"
+_LIB_PATH = os.path.join(_HERE, "libsynth_san.so" if SANITIZED else "libsynth.so")
 _lib = None
+SAN_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 REV_BIT = 0x80000000
 
 
-def build(force: bool = True) -> str:
-    """Compile ``libsynth.so`` with gcc (host code only)."""
-    if force or not os.path.exists(_LIB_PATH):
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall",
-                               "-o", _LIB_PATH, _SRC])
-    return _LIB_PATH
+def build(force: bool = True, sanitized: bool = None) -> str:
+    """Compile ``libsynth.so`` (or, sanitized, ``libsynth_san.so``) with gcc (host code only)."""
+    san = SANITIZED if sanitized is None else sanitized
+    path = os.path.join(_HERE, "libsynth_san.so" if san else "libsynth.so")
+    if force or not os.path.exists(path):
+        opt = SAN_FLAGS if san else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-fPIC", "-shared", "-std=c11", "-Wall", "-o", path, _SRC])
+    return path
 
 
 def _load():

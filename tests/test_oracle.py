@@ -796,6 +796,100 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - grad[k]) <= 1e-4 * max(abs(grad[k]), 1e-3 * np.abs(grad).max()), (k, fd, grad[k])
 
 
+# ---------------------------------------------------------------------------
+# The loss pairs in window-major order (reading R22): the law of the plain
+# loss pairs listed segment by segment
+# ---------------------------------------------------------------------------
+def test_loss_segment_counts_are_the_histogram_of_the_loss_draws():
+    # brute force over the plain loss pairs (Philox stream 2 at counter q, word 2 = step)
+    g, _ = _disjoint_paths_fixed_point()
+    n_pairs, seed, gid, step = 3000, 11, 3, 5
+    start, path = O.sps_segments(g)
+    brute = np.zeros(len(path), np.int64)
+    for q in range(n_pairs):
+        r = O.philox([q & 0xFFFFFFFF, q >> 32, step, (2 << 24) | gid], [seed, 0])
+        i = ((int(r[0]) | (int(r[1]) << 32)) * g.S) >> 64
+        brute[np.searchsorted(start, i, side="right") - 1] += 1
+    counts = O.loss_segment_counts(g, n_pairs, seed=seed, step=step, graph_id=gid).astype(np.int64)
+    assert np.array_equal(counts, brute) and counts.sum() == n_pairs
+
+
+def test_loss_windowed_pairs_follow_the_power_law(tiny_synth, tiny_oracle):
+    from scipy.stats import chi2 as chi2_dist
+    g, sg = tiny_oracle, tiny_synth
+    n_pairs, W = 400_000, 200  # paths of ~1,800 steps: room for hops up to W both ways in the middle
+    i, j, f = O.loss_windowed_pairs(g, n_pairs, 0, n_pairs, seed=11, step=3, window=W)
+    i, j = i.astype(np.int64), j.astype(np.int64)
+    start, path = O.sps_segments(g)
+    counts = O.loss_segment_counts(g, n_pairs, seed=11, step=3).astype(np.int64)
+    seg_of_slot = np.repeat(np.arange(len(counts)), counts)
+    assert np.all((i >= start[seg_of_slot]) & (i < start[seg_of_slot + 1])), "slot step outside its segment"
+    # i uniform over all steps
+    c = np.bincount(i, minlength=g.S)
+    exp = n_pairs / g.S
+    chi2 = float(np.sum((c - exp) ** 2 / exp))
+    assert chi2 < chi2_dist.ppf(1 - 1e-4, g.S - 1)
+    # j on the path of i, at most W steps away, never i itself
+    pi, pj = _path_of(sg.path_off, i), _path_of(sg.path_off, j)
+    assert np.array_equal(pi, pj) and np.all(np.abs(j - i) <= W) and np.all(j != i)
+    # direction and endpoint coins fair; hop ~ Zipf(0.99) on [1, W] where both directions have room
+    off = sg.path_off.astype(np.int64)
+    room = np.minimum(i - off[pi], off[pi + 1] - 1 - i)
+    inner = room >= W
+    z = np.abs(j - i)[inner]
+    pmf = 1.0 / np.arange(1, W + 1) ** 0.99
+    pmf /= pmf.sum()
+    obs = np.bincount(z, minlength=W + 1)[1:]
+    bins = np.concatenate([np.arange(0, 20), np.unique(np.geomspace(20, W - 1, 12).astype(int))])
+    ob = np.add.reduceat(obs, bins)
+    ex = np.add.reduceat(pmf * inner.sum(), bins)
+    assert float(np.sum((ob - ex) ** 2 / ex)) < chi2_dist.ppf(1 - 1e-4, len(bins) - 1)
+    assert abs((j < i)[inner].mean() - 0.5) < 0.01
+    for b in (0, 1):
+        assert abs(((f >> b) & 1).mean() - 0.5) < 0.01
+
+
+@pytest.mark.parametrize("lam", [0.5, 2.0])
+def test_windowed_loss_on_lines_per_path_is_closed_form(lam):
+    # each path on its own line at its path coordinates scaled by lam: every same-path pair has
+    # mag = lam * d, so the loss is (lam - 1)^2; a pair across paths would not give it
+    g, c = _disjoint_paths_fixed_point()
+    c = c * np.float32(lam)
+    L, n, grad = O.stress_loss_grad_windowed(g, c, 20000, seed=11, step=1)
+    assert n > 0.9 * 20000 and abs(L - (lam - 1) ** 2) < 1e-12
+    Lp, n_p, _ = O.stress_loss_grad(g, c, 20000, seed=11, step=1, want_grad=False)
+    assert abs(Lp - L) < 1e-12
+
+
+def test_windowed_gradient_matches_finite_differences():
+    sg = synth.generate(60, 0.2, 3, 9)
+    g = O.Graph.from_synth(sg)
+    rng = np.random.default_rng(2)
+    c = (O.init_coords(g) + rng.normal(scale=3.0, size=4 * g.n_nodes)).astype(np.float32)
+    L, n, grad = O.stress_loss_grad_windowed(g, c, 3000, seed=11, step=4)
+    idx = rng.choice(4 * g.n_nodes, size=40, replace=False)
+    for k in idx:
+        h = np.float32(2.0 ** (np.floor(np.log2(max(1.0, abs(float(c[k]))))) - 14))
+        cp, cm = c.copy(), c.copy()
+        cp[k] += h
+        cm[k] -= h
+        Lp = O.stress_loss_grad_windowed(g, cp, 3000, seed=11, step=4, want_grad=False)[0]
+        Lm = O.stress_loss_grad_windowed(g, cm, 3000, seed=11, step=4, want_grad=False)[0]
+        fd = (Lp - Lm) / (float(cp[k]) - float(cm[k]))
+        assert abs(fd - grad[k]) <= 1e-4 * max(abs(grad[k]), 1e-3 * np.abs(grad).max()), (k, fd, grad[k])
+
+
+def test_windowed_and_plain_loss_estimate_the_same_expectation(tiny_oracle):
+    g = tiny_oracle
+    c = O.init_coords(g)
+    O.layout(g, c, first_iter=0, last_iter=6)
+    plain = [O.stress_loss_grad(g, c, 50_000, seed=11, step=s, want_grad=False)[0] for s in range(1, 9)]
+    wind = [O.stress_loss_grad_windowed(g, c, 50_000, seed=11, step=s, want_grad=False)[0] for s in range(1, 9)]
+    mp, mw = float(np.mean(plain)), float(np.mean(wind))
+    se = math.sqrt(np.var(plain, ddof=1) / 8 + np.var(wind, ddof=1) / 8)
+    assert abs(mp - mw) < 4 * se
+
+
 def test_init_coords_follow_first_visits(tiny_synth, tiny_oracle):
     g, sg = tiny_oracle, tiny_synth
     c = O.init_coords(g, seed=5, jitter=10.0)
