@@ -282,8 +282,19 @@ def form_autograd(workload: str = "mid", n_pairs: int = 10_000_000, budget: int 
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     target = P.path_stress(g, c, 10, 7)["mean"]
+    # the plain loop's stress after every iteration (a split run samples the same terms as a full one);
+    # the sampled path stress is measured outside the timed region
     P.init_coords(g, c)
     init_sps = P.path_stress(g, c, 10, 7)["mean"]
+    plain_curve = []
+    elapsed = 0.0
+    for it in range(30):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.layout(g, c, first_iter=it, last_iter=it + 1)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        plain_curve.append((it + 1, elapsed, P.path_stress(g, c, 10, 7)["mean"]))
     runs = []
     one = torch.ones(1, device=c.device)
     for lr in lrs:
@@ -310,9 +321,18 @@ def form_autograd(workload: str = "mid", n_pairs: int = 10_000_000, budget: int 
                     break
         runs.append({"lr": lr, "best_sps": min(h[2] for h in hist), "steps_run": hist[-1][0],
                      "seconds": elapsed, "reached_plain_sps_at": reached,
-                     "ms_per_step": elapsed / hist[-1][0] * 1e3})
+                     "ms_per_step": elapsed / hist[-1][0] * 1e3, "curve": hist})
+    # a stress level both reach: the best one any Adam run reaches; time to reach it on each side
+    shared = min(r["best_sps"] for r in runs)
+    best = min(runs, key=lambda r: r["best_sps"])
+    adam_t = next(t for st, t, sps in best["curve"] if sps <= shared)
+    plain_hit = next(((it, t) for it, t, sps in plain_curve if sps <= shared), None)
     return {"workload": workload, "n_pairs": n_pairs, "plain_seconds": plain_s, "plain_sps": target,
-            "initial_sps": init_sps, "adam": runs}
+            "initial_sps": init_sps, "adam": runs, "plain_curve": plain_curve,
+            "equal_stress": {"sps": shared, "adam_lr": best["lr"], "adam_seconds": adam_t,
+                             "plain_iterations": plain_hit[0] if plain_hit else None,
+                             "plain_seconds": plain_hit[1] if plain_hit else None,
+                             "plain_speedup": adam_t / plain_hit[1] if plain_hit else None}}
 
 
 def sps_vs_ps_layouts(n_graphs: int = 24, stages=(0, 1, 2, 4, 7, 11, 16, 30), m: int = 100):
@@ -420,23 +440,140 @@ def form_reuse(workload: str = "chromosome", schemes=((1, 1), (2, 1), (2, 2), (4
     return {"workload": workload, "schemes": out}
 
 
-def cpu_baseline(sg, seconds_target: float = 12.0) -> dict:
+def _host_record() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def form_tail(workload: str = "chromosome", thresholds=(1.0, 10.0, 100.0, 1000.0, 10000.0), top: int = 40) -> dict:
+    """The pairs behind the sampled path stress of the default layout: for the
+    estimator the benchmark compares (uniform order, m = 10, seed 7) and for a
+    larger window-major sample (m = 100), the number of pairs above stress
+    thresholds and their share of the sum, and the largest pairs with their
+    reference distance, layout distance, coordinate magnitude, node lengths and
+    the path structure between their two steps."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2409_00876_amd as P
+    sg = synth.config_graph(workload)
+    g = P.Graph.from_synth(sg)
+    c = g.new_coords()
+    P.init_coords(g, c)
+    P.layout(g, c)
+    torch.cuda.synchronize()
+    X = c[: 2 * g.n_nodes].cpu().numpy().astype(np.float64)
+    Y = c[2 * g.n_nodes:].cpu().numpy().astype(np.float64)
+    off = sg.path_off.astype(np.int64)
+    mask = 0x7FFFFFFF
+
+    def pos_of(p, s):
+        return int(np.sum(sg.node_len[sg.step_node[off[p]:s] & mask], dtype=np.int64))
+
+    def describe(i, j, e, st):
+        p = int(np.searchsorted(off, i, side="right") - 1)
+        lo, hi = min(i, j), max(i, j)
+        ni, nj = int(sg.step_node[i]), int(sg.step_node[j])
+        ei, ej = e & 1, (e >> 1) & 1
+        li, lj = int(sg.node_len[ni & mask]), int(sg.node_len[nj & mask])
+        xi = pos_of(p, i) + li * (ei ^ (ni >> 31))
+        xj = pos_of(p, j) + lj * (ej ^ (nj >> 31))
+        a, b = 2 * (ni & mask) + ei, 2 * (nj & mask) + ej
+        mag = float(np.hypot(X[a] - X[b], Y[a] - Y[b]))
+        between = sg.step_node[lo:hi + 1]
+        ids = (between & mask).astype(np.int64)
+        labels = []
+        if np.any(between >> 31):
+            labels.append("reverse-strand steps")
+        if hi - lo > 0 and np.any(np.diff(ids) > 2):
+            labels.append("skipped backbone")
+        if hi - lo > 0 and np.any(np.diff(ids) < 0):
+            labels.append("ids decreasing")
+        return {"path": p, "i": int(i), "j": int(j), "steps_apart": hi - lo, "d": abs(xi - xj), "mag": mag,
+                "stress": float(st), "x_max": float(max(abs(X[a]), abs(X[b]))), "len_i": li, "len_j": lj,
+                "structure": labels or ["plain"]}
+
+    out = {}
+    for name, m, pairs in (("uniform m=10 (the compared estimator)", 10, "uniform"),
+                           ("window-major m=100", 100, "uniform_windowed")):
+        rows = []
+        res = None
+        for thr in thresholds:
+            n, i, j, e, st, res = P.path_stress_outliers(g, c, m, thr, max_out=1 << 16, seed=7, pairs=pairs)
+            share = float(st.sum().item()) / res["sum"] if n <= (1 << 16) else None
+            rows.append({"threshold": thr, "pairs": n, "share_of_sum": share})
+            print(f"[tail] {name}: stress > {thr:g}: {n} pairs, share {share}", file=sys.stderr, flush=True)
+        n, i, j, e, st, res = P.path_stress_outliers(g, c, m, thresholds[2], max_out=1 << 16, seed=7, pairs=pairs)
+        order = torch.argsort(st, descending=True)[:top]
+        tops = [describe(int(i[k]), int(j[k]), int(e[k]), float(st[k])) for k in order.tolist()]
+        out[name] = {"mean": res["mean"], "ci": [res["ci_lo"], res["ci_hi"]], "stddev": res["stddev"],
+                     "n_valid": res["n_valid"], "sum": res["sum"], "thresholds": rows, "top": tops}
+    return {"workload": workload, **out}
+
+
+def cpu_baseline(sg, seconds_per_sample: float = 4.0) -> dict:
+    """The oracle on this host's cores: its Hogwild mode on the CPU share of
+    the process, and one pinned thread, each timed on the first terms of a
+    uniform-partner iteration (0) and of a cooling iteration (15) and
+    extrapolated to the 30-iteration layout (15 iterations of each kind)."""
     import oracle as O
     og = O.Graph.from_synth(sg)
-    threads = min(16, len(os.sched_getaffinity(0)))
-    c = O.init_coords(og)
-    n0 = 2_000_000
-    t = time.time()
-    O.layout(og, c, first_iter=0, last_iter=1, threads=threads, term_limit=n0)
-    rate = n0 / max(time.time() - t, 1e-6)
-    n1 = int(min(max(rate * seconds_target, n0), 10 * og.S))
-    c = O.init_coords(og)
-    t = time.time()
-    O.layout(og, c, first_iter=0, last_iter=1, threads=threads, term_limit=n1)
-    dt = time.time() - t
-    return {"value": n1 / dt, "unit": "term updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n1} term updates of iteration 0 of the same graph, oracle Hogwild mode "
-                      f"({threads} threads), {dt:.1f} s"}
+    T = 10 * og.S
+    affinity = sorted(os.sched_getaffinity(0))
+    # the box grants one GPU's process a share of 16 host threads (OMP_NUM_THREADS), whatever nproc shows
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    threads = max(1, min(share, len(affinity)))
+
+    def rate(it, n_threads):
+        c = O.init_coords(og)
+        n0 = 200_000 * n_threads
+        t = time.perf_counter()
+        O.layout(og, c, first_iter=it, last_iter=it + 1, threads=n_threads, term_limit=n0)
+        r0 = n0 / max(time.perf_counter() - t, 1e-6)
+        n1 = int(min(max(r0 * seconds_per_sample, n0), T))
+        c = O.init_coords(og)
+        t = time.perf_counter()
+        O.layout(og, c, first_iter=it, last_iter=it + 1, threads=n_threads, term_limit=n1)
+        dt = time.perf_counter() - t
+        return n1 / dt, n1, dt
+
+    def leg(n_threads):
+        r_u, n_u, t_u = rate(0, n_threads)
+        r_c, n_c, t_c = rate(15, n_threads)
+        layout_s = 15 * T / r_u + 15 * T / r_c  # extrapolated
+        return 30 * T / layout_s, layout_s, (n_u, t_u, r_u), (n_c, t_c, r_c)
+
+    multi = leg(threads)
+    # one thread pinned to one CPU: the worker thread inherits the calling thread's affinity
+    os.sched_setaffinity(0, {affinity[0]})
+    try:
+        single = leg(1)
+    finally:
+        os.sched_setaffinity(0, set(affinity))
+
+    def sample(lg, n):
+        return (f"first {lg[2][0]} terms of iteration 0 ({lg[2][1]:.1f} s) and first {lg[3][0]} terms of iteration 15 "
+                f"({lg[3][1]:.1f} s) of the same graph, {n}; extrapolated to 15 iterations of each kind "
+                f"(30 x {T} terms): {lg[1]:.0f} s per layout")
+
+    return {"value": multi[0], "unit": "term updates/s", "cores": threads, "kind": "oracle",
+            "sample": sample(multi, f"oracle Hogwild mode on {threads} threads (the CPU share of one GPU's process)"),
+            "extrapolated_layout_s": multi[1],
+            "iteration_rates": {"uniform_it0": multi[2][2], "cooling_it15": multi[3][2]},
+            "single_thread": {"value": single[0], "unit": "term updates/s", "cores": 1, "pinned_cpu": affinity[0],
+                              "extrapolated_layout_s": single[1],
+                              "iteration_rates": {"uniform_it0": single[2][2], "cooling_it15": single[3][2]},
+                              "sample": sample(single, "oracle on one thread pinned to one CPU")},
+            "host": _host_record()}
 
 
 FP64_PEAK_TFLOPS = 78.6
@@ -512,13 +649,17 @@ def form_kernels() -> dict:
     x = g.new_coords()
     P.init_coords(g, x)
     n = 10_000_000
-    loss, nv = P.stress_forward(g, x, n, 1, seed=11)
-    ms = ev_time(lambda: P.stress_forward(g, x, n, 1, seed=11), reps=20)
-    row("k_stress_fwd", "mid, 1e7 pairs", "pair", n, ms, 48)
     gr = torch.zeros_like(x)
     one = torch.ones(1, device=x.device)
-    ms = ev_time(lambda: P.stress_backward(g, x, n, 1, one, nv, gr, seed=11), reps=20)
-    row("k_stress_bwd", "mid, 1e7 pairs", "pair", n, ms, 64, note_="48 B read + 2 x 8 B of atomic adds")
+    for sched, fwd, bwd, order in ((1, "k_stress_fwd", "k_stress_bwd", "plain order"),
+                                   (3, "k_loss_win<fwd>", "k_loss_win<bwd>", "window-major order (R22)")):
+        loss, nv = P.stress_forward(g, x, n, 1, seed=11, schedule=sched)
+        ms = ev_time(lambda: P.stress_forward(g, x, n, 1, seed=11, schedule=sched), reps=20)
+        row(fwd, f"mid, 1e7 pairs, {order}", "pair", n, ms, 48,
+            note_="the whole call: coordinate copy, (segment count and scan,) pass, reduction")
+        ms = ev_time(lambda: P.stress_backward(g, x, n, 1, one, nv, gr, seed=11, schedule=sched), reps=20)
+        row(bwd, f"mid, 1e7 pairs, {order}", "pair", n, ms, 64,
+            note_="48 B read + 2 x 8 B of atomic adds; the whole call")
     m_, v_ = torch.zeros_like(x), torch.zeros_like(x)
     ms = ev_time(lambda: P.adam_step(x, gr, m_, v_, 1, lr=1.0), reps=20)
     row("k_adam", "mid coordinates", "float", x.numel(), ms, 28, note_="x, grad, m, v read; x, m, v written")
@@ -548,7 +689,7 @@ def main():
                     help="processing order of the layout loop (the library's automatic choice is windowed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true")
-    ap.add_argument("--form", choices=["batched", "autograd", "metric", "reuse", "kernels"], default=None,
+    ap.add_argument("--form", choices=["batched", "autograd", "metric", "reuse", "kernels", "tail"], default=None,
                     help="measure one of the two forms against the plain loop instead (separate JSON line)")
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--summarize", nargs="+", metavar="PATH",
@@ -578,6 +719,9 @@ def main():
         return
     if a.form == "kernels":
         print(json.dumps({"form": "kernels", **form_kernels()}))
+        return
+    if a.form == "tail":
+        print(json.dumps({"form": "tail", **form_tail(a.workload)}))
         return
 
     import torch

@@ -71,6 +71,7 @@ typedef struct {
   uint64_t device_bytes;  /* device memory held by the handle */
   int32_t device;
   uint32_t max_path_steps;
+  uint32_t renumbered;    /* 1 if the device keeps the nodes in the path-guided order (see pgsgd_graph_create_ex) */
 } pgsgd_graph_info;
 
 /*
@@ -93,13 +94,64 @@ typedef struct {
  *   device        HIP device ordinal
  *   out           receives the handle (NULL on error)
  * The host arrays are copied; the caller may free them once the call returns.
+ * Device memory: 16 B per step (records), 24 B per node (first visit and the
+ * interleaved working copy of the coordinates), the path offsets, the
+ * power-law table (about 258 KB) and reduction scratch (about 49 KB); the
+ * windowed schedule and the window-major sampled path stress add a few words
+ * per window on first use.  If the environment variable
+ * PGSGD_MAX_DEVICE_BYTES holds a positive decimal number, no graph handle may
+ * hold more device memory than that: a creation that would need more fails
+ * with OOM before any device work, as does any later allocation of the handle.
  * Errors: INVALID_ARG (null pointer, node id >= n_nodes, length 0, offsets not
  * monotone, step_pos mismatch, n_paths = 0), RANGE (sizes above the limits,
  * a path longer than 2^62 nt), OOM, DEVICE.  Synchronous.
+ * Equal to pgsgd_graph_create_ex(..., PGSGD_RENUMBER_AUTO, out).
  */
 pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t *node_len, uint32_t n_paths,
                                 const uint64_t *path_offsets, const uint32_t *step_node, const int64_t *step_pos,
                                 int device, pgsgd_graph **out);
+
+/*
+ * pgsgd_graph_create with a choice of the node order kept on the device.  The
+ * windowed schedule gets its locality from nodes that lie close along the
+ * paths having close ids (their coordinates then share cache lines; the
+ * cache-friendly data layout of Section "Cache-friendly Data Layout" makes the
+ * same point).  Graphs sorted along their paths (as pangenome tools emit them)
+ * already have that order; for others the library can renumber the nodes into
+ * the path-guided order of pgsgd_path_order.  Renumbering is invisible to the
+ * caller: coordinates, gradients and node ids at the interface stay in the
+ * caller's order, the sampled terms (steps i, j) and the initial layout are
+ * the same, and a one-wave layout gives the same coordinates bit for bit; the
+ * device holds 4 more bytes per node and the permutes in and out gather and
+ * scatter through it.
+ *   renumber  PGSGD_RENUMBER_AUTO: renumber when more than 20% of the
+ *             consecutive steps of the paths jump more than 32 ids and the
+ *             path-guided order at least halves that fraction;
+ *             PGSGD_RENUMBER_NEVER; PGSGD_RENUMBER_ALWAYS.  Other values:
+ *             INVALID_ARG.
+ */
+enum { PGSGD_RENUMBER_AUTO = 0, PGSGD_RENUMBER_NEVER = 1, PGSGD_RENUMBER_ALWAYS = 2 };
+pgsgd_status pgsgd_graph_create_ex(uint32_t n_nodes, const uint32_t *node_len, uint32_t n_paths,
+                                   const uint64_t *path_offsets, const uint32_t *step_node, const int64_t *step_pos,
+                                   int device, uint32_t renumber, pgsgd_graph **out);
+/* The device node id of every caller node id (host, n_nodes entries; the
+ * identity when the graph is not renumbered).  Errors: INVALID_ARG on NULL. */
+pgsgd_status pgsgd_graph_get_order(const pgsgd_graph *g, uint32_t *perm_out);
+/*
+ * The path-guided node order (host only, no device work), a progressive
+ * linearization along the paths: the first path's nodes in path order; then
+ * each later path, step by step, inserts every node not placed yet right
+ * after the last node of that path already placed (at the front if there is
+ * none), so a node first met on a later path lands next to its neighbours
+ * there; nodes no path visits come last in id order.  perm_out[n] = new id of
+ * node n (host, n_nodes entries).  far_before / far_after (host, may be NULL): the fraction
+ * of consecutive steps of a path whose node ids differ by more than 32, in
+ * the given and in the new order.  Errors: INVALID_ARG (NULL arrays, a node id
+ * >= n_nodes).
+ */
+pgsgd_status pgsgd_path_order(uint32_t n_nodes, const uint32_t *node_len, uint32_t n_paths,
+                              const uint64_t *path_offsets, const uint32_t *step_node, uint32_t *perm_out,
+                              double *far_before, double *far_after);
 /* Frees the handle and its device memory (synchronises the device first).  NULL-safe. */
 void pgsgd_graph_destroy(pgsgd_graph *g);
 /* Fills *out (host).  Errors: INVALID_ARG on NULL. */
@@ -307,6 +359,7 @@ pgsgd_status pgsgd_init_coords(pgsgd_graph *g, uint64_t seed, uint32_t graph_id,
  */
 pgsgd_status pgsgd_layout(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);
 
+
 /*
  * pgsgd_layout with measurement, by HIP events recorded on `stream`:
  *   iter_ms[k]   duration of iteration first_iter + k (all its kernels)
@@ -381,6 +434,26 @@ enum { PGSGD_PAIRS_UNIFORM = 0, PGSGD_PAIRS_POWER_LAW = 1, PGSGD_PAIRS_UNIFORM_W
 pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
                                      uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
                                      pgsgd_stress_result *out, void *stream);
+
+/*
+ * The pairs behind a sampled path stress (Eq. 2 is a mean over millions of
+ * pairs; when a few pairs carry a large share of it, the estimate is heavy
+ * tailed and these are the pairs to look at): runs pgsgd_path_stress_pairs
+ * with the same arguments (same pairs, same *out; out may be NULL) and lists
+ * the valid pairs whose stress exceeds `threshold`:
+ *   i_out, j_out  device uint64[max_out]: the pair's steps
+ *   e_out         device uint8[max_out]: e_i | e_j << 1
+ *   s_out         device double[max_out]: the pair's stress (FP64)
+ *   *n_out        host: how many pairs exceed the threshold (the first
+ *                 max_out found are written, in no particular order)
+ * Synchronises the stream.  Errors: those of pgsgd_path_stress_pairs, plus
+ * INVALID_ARG for NULL outputs with max_out > 0 or a non-finite threshold.
+ */
+pgsgd_status pgsgd_path_stress_outliers(pgsgd_graph *g, const float *coords, uint32_t pairs_per_step, uint64_t seed,
+                                        uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
+                                        double threshold, uint64_t max_out, uint64_t *i_out, uint64_t *j_out,
+                                        uint8_t *e_out, double *s_out, uint64_t *n_out, pgsgd_stress_result *out,
+                                        void *stream);
 
 /*
  * Path stress, Eq. 1 (Section "Path Stress"): over every path and every pair of

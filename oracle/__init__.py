@@ -87,6 +87,7 @@ def _load():
         "or_init_coords": ([P, u64, u32, f32, P], None),
         "or_stress_loss_grad": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
         "or_loss_segment_counts": ([P, u64, u64, u32, u32, P, u64, P], None),
+        "or_sps_outliers": ([P, P, u32, u64, u32, u32, f64, u32, f64, u64, P, P, P, P], u64),
         "or_loss_windowed_pairs": ([P, u64, f64, u32, u64, u32, u32, u64, u64, P, P, P], None),
         "or_stress_loss_grad_windowed": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
     }
@@ -428,3 +429,22 @@ def stress_loss_grad_windowed(g: Graph, coords: np.ndarray, n_pairs: int, seed: 
     _load().or_stress_loss_grad_windowed(g._h, _p(coords), int(n_pairs), float(theta), int(window), int(seed),
                                          int(graph_id), int(step), _p(out), _p(grad))
     return float(out[0]), int(out[1]), grad
+
+
+PAIR_MODES = {"uniform": 0, "power_law": 1, "uniform_windowed": 2}
+
+
+def sps_outliers(g: Graph, coords: np.ndarray, m: int, threshold: float, max_out: int = 1 << 20, seed: int = 7,
+                 graph_id: int = 0, pairs: str = "uniform", theta=0.99, window=1000):
+    """The pairs of Eq. 2 (given order) with stress above threshold, in
+    enumeration order: (count, i, j, e, stress) with the first max_out kept."""
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    i = np.zeros(max_out, dtype=np.uint64)
+    j = np.zeros(max_out, dtype=np.uint64)
+    e = np.zeros(max_out, dtype=np.uint8)
+    s = np.zeros(max_out, dtype=np.float64)
+    n = int(_load().or_sps_outliers(g._h, _p(coords), int(m), int(seed), int(graph_id), PAIR_MODES[pairs],
+                                    float(theta), int(window), float(threshold), int(max_out), _p(i), _p(j), _p(e),
+                                    _p(s)))
+    k = min(n, max_out)
+    return n, i[:k], j[:k], e[:k], s[:k]

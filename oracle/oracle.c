@@ -1408,3 +1408,59 @@ void or_stress_loss_grad_windowed(const or_graph *g, const float *coords, uint64
   loss_segments_free(&ls);
   free((void *)sp.zipf);
 }
+
+/* ---------------------------------------------------------------------------
+ * The pairs of Eq. 2 whose stress exceeds a threshold (for finding the pairs
+ * behind a heavy-tailed estimate): the pairs of the given mode (0 uniform,
+ * 1 power-law partner, 2 uniform in window-major order) in enumeration order;
+ * the first max_out are written (i, j, e = e_i | e_j << 1, stress); returns
+ * how many exceed the threshold.
+ * ------------------------------------------------------------------------- */
+uint64_t or_sps_outliers(const or_graph *g, const float *coords, uint32_t m, uint64_t seed, uint32_t graph_id,
+                         uint32_t mode, double theta, uint32_t W, double threshold, uint64_t max_out,
+                         uint64_t *i_out, uint64_t *j_out, uint8_t *e_out, double *s_out) {
+  uint64_t n_out = 0;
+  sampler sp;
+  sp.zipf = NULL;
+  if (mode == 1) make_sampler(&sp, 1, theta, W, seed, graph_id);
+#define OR_KEEP(I, J, EI, EJ, S)                            \
+  do {                                                      \
+    if ((S) > threshold) {                                  \
+      if (n_out < max_out) {                                \
+        i_out[n_out] = (I); j_out[n_out] = (J);             \
+        e_out[n_out] = (uint8_t)((EI) | ((EJ) << 1));       \
+        s_out[n_out] = (S);                                 \
+      }                                                     \
+      ++n_out;                                              \
+    }                                                       \
+  } while (0)
+  if (mode == 2) {
+    uint64_t n_seg = or_sps_segments(g, NULL, NULL);
+    uint64_t *start = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+    uint32_t *path = (uint32_t *)malloc(sizeof(uint32_t) * (n_seg + 1));
+    uint64_t *cnt = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+    or_sps_segments(g, start, path);
+    or_sps_segment_counts(g, m, seed, graph_id, start, n_seg, cnt);
+    uint64_t u = 0;
+    for (uint64_t s = 0; s < n_seg; ++s)
+      for (uint64_t k = 0; k < cnt[s]; ++k, ++u) {
+        uint64_t i, j; uint32_t ei, ej; int valid;
+        sps_slot(g, seed, graph_id, start[s], start[s + 1] - start[s], path[s], u, &i, &j, &ei, &ej);
+        double st = pair_stress(g, coords, i, j, ei, ej, &valid);
+        if (valid) OR_KEEP(i, j, ei, ej, st);
+      }
+    free(start); free(path); free(cnt);
+  } else {
+    for (uint32_t p = 0; p < g->n_paths; ++p)
+      for (uint64_t q = (uint64_t)m * g->path_off[p]; q < (uint64_t)m * g->path_off[p + 1]; ++q) {
+        uint64_t i, j; uint32_t ei, ej; int valid = 1;
+        if (mode == 1) sps_pair_power_law(g, &sp, p, q, &i, &j, &ei, &ej, &valid);
+        else sps_pair(g, seed, graph_id, p, q, &i, &j, &ei, &ej);
+        double st = valid ? pair_stress(g, coords, i, j, ei, ej, &valid) : 0.0;
+        if (valid) OR_KEEP(i, j, ei, ej, st);
+      }
+  }
+#undef OR_KEEP
+  if (sp.zipf) free((void *)sp.zipf);
+  return n_out;
+}

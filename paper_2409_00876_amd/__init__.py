@@ -22,7 +22,7 @@ import torch
 from ._lib import (GfaView, FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
                    check, lib)
 
-__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_exact", "schedule", "zipf_table",
+__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "path_order", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_outliers", "path_stress_exact", "schedule", "zipf_table",
            "sample_terms", "sample_terms_reuse", "apply_terms", "apply_slots", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
@@ -139,6 +139,20 @@ def _gfa_from_handle(h) -> GfaGraph:
         lib().pgsgd_gfa_free(h)
 
 
+def path_order(node_len, path_off, step_node):
+    """The path-guided node order (host only): (perm, far_before, far_after),
+    perm[n] = new id of node n."""
+    node_len = np.ascontiguousarray(node_len, dtype=np.uint32)
+    path_off = np.ascontiguousarray(path_off, dtype=np.uint64)
+    step_node = np.ascontiguousarray(step_node, dtype=np.uint32)
+    perm = np.empty(len(node_len), dtype=np.uint32)
+    fb, fa = ctypes.c_double(), ctypes.c_double()
+    check(lib().pgsgd_path_order(len(node_len), _np_ptr(node_len), len(path_off) - 1, _np_ptr(path_off),
+                                 _np_ptr(step_node) if step_node.size else None, _np_ptr(perm), ctypes.byref(fb),
+                                 ctypes.byref(fa)))
+    return perm, fb.value, fa.value
+
+
 def read_gfa(path: str) -> GfaGraph:
     """Reads a GFA 1.0/1.1 file (S, P and W lines) into the lean structure."""
     h = ctypes.c_void_p()
@@ -157,15 +171,18 @@ def parse_gfa(text) -> GfaGraph:
 class Graph:
     """A variation graph resident on one GPU (node lengths and path steps)."""
 
-    def __init__(self, node_len, path_off, step_node, step_pos=None, device: int = 0):
+    RENUMBER = {"auto": 0, "never": 1, "always": 2}
+
+    def __init__(self, node_len, path_off, step_node, step_pos=None, device: int = 0, renumber: str = "auto"):
         node_len = np.ascontiguousarray(node_len, dtype=np.uint32)
         path_off = np.ascontiguousarray(path_off, dtype=np.uint64)
         step_node = np.ascontiguousarray(step_node, dtype=np.uint32)
         pos = None if step_pos is None else np.ascontiguousarray(step_pos, dtype=np.int64)
         h = ctypes.c_void_p()
-        check(lib().pgsgd_graph_create(len(node_len), _np_ptr(node_len), len(path_off) - 1, _np_ptr(path_off),
-                                       _np_ptr(step_node) if step_node.size else None,
-                                       _np_ptr(pos) if pos is not None else None, int(device), ctypes.byref(h)))
+        check(lib().pgsgd_graph_create_ex(len(node_len), _np_ptr(node_len), len(path_off) - 1, _np_ptr(path_off),
+                                          _np_ptr(step_node) if step_node.size else None,
+                                          _np_ptr(pos) if pos is not None else None, int(device),
+                                          self.RENUMBER[renumber], ctypes.byref(h)))
         self._h = h
         self.device = int(device)
         info = GraphInfo()
@@ -175,10 +192,17 @@ class Graph:
         self.n_steps = int(info.n_steps)
         self.d_max = int(info.d_max)
         self.device_bytes = int(info.device_bytes)
+        self.renumbered = bool(info.renumbered)
 
     @classmethod
-    def from_synth(cls, sg, device: int = 0):
-        return cls(sg.node_len, sg.path_off, sg.step_node, device=device)
+    def from_synth(cls, sg, device: int = 0, renumber: str = "auto"):
+        return cls(sg.node_len, sg.path_off, sg.step_node, device=device, renumber=renumber)
+
+    def order(self) -> np.ndarray:
+        """Device node id of every caller node id (the identity unless renumbered)."""
+        perm = np.empty(self.n_nodes, dtype=np.uint32)
+        check(lib().pgsgd_graph_get_order(self._h, _np_ptr(perm)))
+        return perm
 
     @classmethod
     def from_gfa(cls, path: str, device: int = 0):
@@ -270,6 +294,32 @@ def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, grap
                                         int(seed), int(graph_id), modes[pairs], float(zipf_theta), int(zipf_window),
                                         ctypes.byref(r), _stream(torch, coords.device)))
     return {f[0]: getattr(r, f[0]) for f in StressResult._fields_}
+
+
+def path_stress_outliers(g: Graph, coords, pairs_per_step: int, threshold: float, max_out: int = 1 << 20,
+                         seed: int = 7, graph_id: int = 0, pairs: str = "uniform", zipf_theta: float = 0.99,
+                         zipf_window: int = 1000):
+    """The pairs of path_stress() whose stress exceeds threshold: (count, i, j,
+    e, stress, result) with i, j, e, stress device tensors of the first
+    min(count, max_out) pairs found (in no particular order)."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    modes = {"uniform": 0, "power_law": 1, "uniform_windowed": 2}
+    dev = coords.device
+    i = torch.empty(max(1, max_out), dtype=torch.int64, device=dev)
+    j = torch.empty_like(i)
+    e = torch.empty(max(1, max_out), dtype=torch.uint8, device=dev)
+    s = torch.empty(max(1, max_out), dtype=torch.float64, device=dev)
+    n = ctypes.c_uint64()
+    r = StressResult()
+    check(lib().pgsgd_path_stress_outliers(g.handle, ctypes.c_void_p(coords.data_ptr()), int(pairs_per_step),
+                                           int(seed), int(graph_id), modes[pairs], float(zipf_theta),
+                                           int(zipf_window), float(threshold), int(max_out),
+                                           ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()),
+                                           ctypes.c_void_p(e.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                           ctypes.byref(n), ctypes.byref(r), _stream(torch, dev)))
+    k = min(int(n.value), max_out)
+    return int(n.value), i[:k], j[:k], e[:k], s[:k], {f[0]: getattr(r, f[0]) for f in StressResult._fields_}
 
 
 def path_stress_exact(g: Graph, coords):

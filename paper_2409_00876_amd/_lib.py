@@ -21,6 +21,7 @@ ERR_UNSUPPORTED = -5
 SCHEDULE_AUTO, SCHEDULE_PLAIN, SCHEDULE_WINDOWED = 0, 1, 3  # 2 is reserved
 PAIRS_UNIFORM, PAIRS_POWER_LAW, PAIRS_UNIFORM_WINDOWED = 0, 1, 2
 FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER = 1, 2
+RENUMBER_AUTO, RENUMBER_NEVER, RENUMBER_ALWAYS = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "RANGE", -3: "OOM", -4: "DEVICE", -5: "UNSUPPORTED"}
 
 
@@ -59,6 +60,7 @@ class GraphInfo(ctypes.Structure):
         ("device_bytes", ctypes.c_uint64),
         ("device", ctypes.c_int32),
         ("max_path_steps", ctypes.c_uint32),
+        ("renumbered", ctypes.c_uint32),
     ]
 
 
@@ -114,6 +116,9 @@ SIGNATURES = {
     "pgsgd_gfa_get_view": ([_P, _P], _i32),
     "pgsgd_gfa_free": ([_P], None),
     "pgsgd_graph_create": ([_u32, _P, _u32, _P, _P, _P, ctypes.c_int, _P], _i32),
+    "pgsgd_graph_create_ex": ([_u32, _P, _u32, _P, _P, _P, ctypes.c_int, _u32, _P], _i32),
+    "pgsgd_graph_get_order": ([_P, _P], _i32),
+    "pgsgd_path_order": ([_u32, _P, _u32, _P, _P, _P, _P, _P], _i32),
     "pgsgd_graph_destroy": ([_P], None),
     "pgsgd_graph_get_info": ([_P, _P], _i32),
     "pgsgd_params_default": ([_P], None),
@@ -124,6 +129,8 @@ SIGNATURES = {
     "pgsgd_layout_timed": ([_P, _P, _P, _P, _P, _P, _P], _i32),
     "pgsgd_path_stress": ([_P, _P, _u32, _u64, _u32, _P, _P], _i32),
     "pgsgd_path_stress_pairs": ([_P, _P, _u32, _u64, _u32, _u32, ctypes.c_double, _u32, _P, _P], _i32),
+    "pgsgd_path_stress_outliers": ([_P, _P, _u32, _u64, _u32, _u32, _f64, _u32, _f64, _u64, _P, _P, _P, _P, _P, _P,
+                                    _P], _i32),
     "pgsgd_path_stress_exact": ([_P, _P, _P, _P, _P], _i32),
     "pgsgd_stress_forward": ([_P, _P, _P, _u64, _u32, _P, _P, _P], _i32),
     "pgsgd_stress_backward": ([_P, _P, _P, _u64, _u32, _P, _P, _P, _P], _i32),

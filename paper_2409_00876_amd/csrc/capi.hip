@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <mutex>
@@ -149,6 +150,8 @@ struct pgsgd_graph {
   uint64_t* d_path_off = nullptr;
   uint64_t* d_first = nullptr;
   float2* d_work = nullptr;     // interleaved working copy of the coordinates
+  uint32_t* d_inv = nullptr;    // renumbered graphs: caller id of every device node id (else NULL)
+  std::vector<uint32_t> h_perm; // renumbered graphs: device node id of every caller id (else empty)
   // power-law table cache
   double zipf_theta = -1.0;
   uint32_t zipf_W = 0;
@@ -166,6 +169,10 @@ struct pgsgd_graph {
   int layout_blocks_per_cu = 0;  // occupancy of k_layout_iter, filled on first use
   // window-major scratch (allocated on first use)
   uint32_t loc_nwin = 0, loc_shift = 0, loc_xstride = 0, loc_streams = 0;
+  // host copy of the window tables (order, run bounds, path of a window) for
+  // h_loc_shift / h_loc_streams, built on first use
+  uint32_t h_loc_shift = 0, h_loc_streams = 0, h_loc_xstride = 0;
+  std::vector<uint32_t> h_lorder, h_lsbeg, h_lwpath;
   uint32_t* d_lcount = nullptr;
   uint64_t* d_loff = nullptr;
   uint64_t* d_lxitem = nullptr;
@@ -195,7 +202,7 @@ struct pgsgd_graph {
   ~pgsgd_graph() {
     DeviceGuard g(device);
     (void)hipDeviceSynchronize();
-    for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
+    for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_inv, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
                     (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
                     (void*)d_lsbeg, (void*)d_lwpath, (void*)d_sseg_start, (void*)d_sseg_path, (void*)d_swseg,
                     (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue,
@@ -209,9 +216,27 @@ struct pgsgd_graph {
 
 namespace {
 
+// PGSGD_MAX_DEVICE_BYTES (decimal bytes; unset, 0 or not a number: no cap)
+// bounds the device memory each graph handle may hold, so an out-of-memory
+// path can be forced without exhausting the device.
+uint64_t device_byte_cap() {
+  const char* v = std::getenv("PGSGD_MAX_DEVICE_BYTES");
+  if (!v || !*v) return 0;
+  char* end = nullptr;
+  const unsigned long long x = std::strtoull(v, &end, 10);
+  return (end && *end == '\0') ? (uint64_t)x : 0;
+}
+
 template <typename T>
 pgsgd_status dev_alloc(pgsgd_graph* g, T** p, size_t count) {
   size_t bytes = sizeof(T) * (count ? count : 1);
+  const uint64_t cap = device_byte_cap();
+  if (cap && g->device_bytes + bytes > cap) {
+    *p = nullptr;
+    return fail(PGSGD_ERR_OOM, "allocating %zu bytes would take the graph to %llu bytes, above "
+                "PGSGD_MAX_DEVICE_BYTES = %llu", bytes, (unsigned long long)(g->device_bytes + bytes),
+                (unsigned long long)cap);
+  }
   hipError_t e = hipMalloc((void**)p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -241,21 +266,14 @@ void free_set(pgsgd_graph* g, std::initializer_list<void**> set) {
     }
 }
 
-// Ensures the graph holds the power-law table for (theta, W) on the device.
+// Ensures the graph holds the power-law table for (theta, W) on the device
+// (its buffers are allocated with the graph, sized for the largest window).
 pgsgd_status ensure_zipf(pgsgd_graph* g, double theta, uint32_t W, hipStream_t s) {
   if (g->d_zipf && g->zipf_theta == theta && g->zipf_W == W) return PGSGD_OK;
   std::vector<uint32_t> C;
   std::vector<uint16_t> guide;
   build_zipf(theta, W, C, guide);
   HIP_TRY(hipStreamSynchronize(s));  // earlier work on this stream may still read the old table
-  if (!g->d_zipf) {  // sized for the largest window (65535)
-    pgsgd_status st = dev_alloc(g, &g->d_zipf, 65536);
-    if (st) return st;
-  }
-  if (!g->d_guide) {
-    pgsgd_status st = dev_alloc(g, &g->d_guide, kGuideSize + 1);
-    if (st) return st;
-  }
   HIP_TRY(hipMemcpy(g->d_zipf, C.data(), sizeof(uint32_t) * C.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(g->d_guide, guide.data(), sizeof(uint16_t) * guide.size(), hipMemcpyHostToDevice));
   g->zipf_theta = theta;
@@ -322,6 +340,7 @@ StressLaunch make_stress_launch(const pgsgd_graph* g, const float* coords, uint3
   P.rec = g->d_rec;
   P.coords = coords;
   P.path_off = g->d_path_off;
+  P.inv = g->d_inv;
   P.zipf = g->d_zipf;
   P.guide = g->d_guide;
   P.n_nodes = g->n_nodes;
@@ -343,6 +362,61 @@ pgsgd_status layout_blocks_per_cu(pgsgd_graph* g, size_t lds, int* out) {
   }
   *out = g->layout_blocks_per_cu;
   return PGSGD_OK;
+}
+
+// Path-guided node order (the locality the windowed schedule relies on): a
+// progressive linearization along the paths.  The first path's nodes come in
+// path order; every later path inserts each node not placed yet right after
+// the last node of that path that is already placed (at the front when there
+// is none), so a node first met on another path sits next to its neighbours
+// there; nodes that no path visits go last in id order.  perm[n] = new id of n.
+void path_guided_order(uint32_t n_nodes, const uint32_t* /*node_len*/, uint32_t n_paths, const uint64_t* path_off,
+                       const uint32_t* step_node, std::vector<uint32_t>& perm) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  std::vector<uint32_t> next(n_nodes, kNone);  // linked order of the placed nodes
+  std::vector<uint8_t> placed(n_nodes, 0);
+  uint32_t head = kNone;
+  for (uint32_t p = 0; p < n_paths; ++p) {
+    uint32_t anchor = kNone;
+    for (uint64_t s = path_off[p]; s < path_off[p + 1]; ++s) {
+      const uint32_t n = step_node[s] & kNodeMask;
+      if (!placed[n]) {
+        placed[n] = 1;
+        if (anchor == kNone) {
+          next[n] = head;
+          head = n;
+        } else {
+          next[n] = next[anchor];
+          next[anchor] = n;
+        }
+      }
+      anchor = n;
+    }
+  }
+  perm.assign(n_nodes, 0);
+  uint32_t k = 0;
+  for (uint32_t n = head; n != kNone; n = next[n]) perm[n] = k++;
+  for (uint32_t n = 0; n < n_nodes; ++n)
+    if (!placed[n]) perm[n] = k++;
+}
+
+// Fraction of consecutive steps of a path whose node ids (after perm, if
+// given) differ by more than kRenumberGap: steps whose coordinates cannot
+// share cache lines.
+constexpr uint32_t kRenumberGap = 32;
+constexpr double kRenumberMinFar = 0.2;  // AUTO renumbers only above this fraction ...
+constexpr double kRenumberGain = 0.5;    // ... and when the path-guided order at least halves it
+double far_step_fraction(uint32_t n_paths, const uint64_t* path_off, const uint32_t* step_node,
+                         const uint32_t* perm) {
+  uint64_t pairs = 0, far = 0;
+  for (uint32_t p = 0; p < n_paths; ++p)
+    for (uint64_t s = path_off[p] + 1; s < path_off[p + 1]; ++s) {
+      uint32_t u = step_node[s - 1] & kNodeMask, v = step_node[s] & kNodeMask;
+      if (perm) u = perm[u], v = perm[v];
+      ++pairs;
+      far += (u > v ? u - v : v - u) > kRenumberGap;
+    }
+  return pairs ? (double)far / (double)pairs : 0.0;
 }
 
 }  // namespace
@@ -395,8 +469,16 @@ pgsgd_status pgsgd_zipf_table(double theta, uint32_t W, uint32_t* C_out) {
 pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t* node_len, uint32_t n_paths,
                                 const uint64_t* path_off, const uint32_t* step_node, const int64_t* step_pos,
                                 int device, pgsgd_graph** out) {
+  return pgsgd_graph_create_ex(n_nodes, node_len, n_paths, path_off, step_node, step_pos, device,
+                               PGSGD_RENUMBER_AUTO, out);
+}
+
+pgsgd_status pgsgd_graph_create_ex(uint32_t n_nodes, const uint32_t* node_len, uint32_t n_paths,
+                                   const uint64_t* path_off, const uint32_t* step_node, const int64_t* step_pos,
+                                   int device, uint32_t renumber, pgsgd_graph** out) {
   if (!out) return fail(PGSGD_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  if (renumber > PGSGD_RENUMBER_ALWAYS) return fail(PGSGD_ERR_INVALID_ARG, "unknown renumber mode %u", renumber);
   if (!node_len && n_nodes > 0) return fail(PGSGD_ERR_INVALID_ARG, "node_len is NULL");
   if (!path_off) return fail(PGSGD_ERR_INVALID_ARG, "path_offsets is NULL");
   if (n_paths == 0) return fail(PGSGD_ERR_INVALID_ARG, "n_paths must be >= 1");
@@ -433,6 +515,26 @@ pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t* node_len, uint
     }
     d_max = std::max(d_max, acc);
   }
+  // node order on the device: the caller's, or the path-guided order when the
+  // caller's ids are scattered along the paths
+  std::vector<uint32_t> perm;
+  if (renumber == PGSGD_RENUMBER_ALWAYS ||
+      (renumber == PGSGD_RENUMBER_AUTO &&
+       far_step_fraction(n_paths, path_off, step_node, nullptr) > kRenumberMinFar)) {
+    path_guided_order(n_nodes, node_len, n_paths, path_off, step_node, perm);
+    if (renumber == PGSGD_RENUMBER_AUTO &&
+        !(far_step_fraction(n_paths, path_off, step_node, perm.data()) <
+          kRenumberGain * far_step_fraction(n_paths, path_off, step_node, nullptr)))
+      perm.clear();
+  }
+  // the buffers allocated below, checked against PGSGD_MAX_DEVICE_BYTES before any device work
+  const uint64_t need = 16ull * std::max<uint64_t>(S, 1) + 8ull * (n_paths + 1) + 8ull * std::max(n_nodes, 1u) +
+                        16ull * std::max(n_nodes, 1u) + 24ull * kStressBlocks + 4 * 8 + 4 * 8 + 8 + 4ull * 65536 +
+                        2ull * (kGuideSize + 1) + (perm.empty() ? 0 : 4ull * n_nodes);
+  const uint64_t cap = device_byte_cap();
+  if (cap && need > cap)
+    return fail(PGSGD_ERR_OOM, "the graph needs %llu bytes of device memory, above PGSGD_MAX_DEVICE_BYTES = %llu",
+                (unsigned long long)need, (unsigned long long)cap);
   int n_dev = 0;
   hipError_t e = hipGetDeviceCount(&n_dev);
   if (e != hipSuccess || n_dev == 0) {
@@ -474,6 +576,9 @@ pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t* node_len, uint
   if ((st = dev_alloc(g, &g->d_out_f, 4))) return bail(st);
   if ((st = dev_alloc(g, &g->d_out_n, 4))) return bail(st);
   if ((st = dev_alloc(g, &g->d_mean, 1))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_zipf, 65536))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_guide, kGuideSize + 1))) return bail(st);
+  if (!perm.empty() && (st = dev_alloc(g, &g->d_inv, n_nodes))) return bail(st);
   auto dev_err = [&](hipError_t err, const char* what) {
     (void)hipGetLastError();
     fail(err == hipErrorOutOfMemory ? PGSGD_ERR_OOM : PGSGD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(err));
@@ -482,6 +587,13 @@ pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t* node_len, uint
   };
   if ((e = hipMemcpy(g->d_path_off, path_off, sizeof(uint64_t) * (n_paths + 1), hipMemcpyHostToDevice)))
     return dev_err(e, "path offsets upload");
+  if (!perm.empty()) {
+    std::vector<uint32_t> inv(n_nodes);
+    for (uint32_t n = 0; n < n_nodes; ++n) inv[perm[n]] = n;
+    if ((e = hipMemcpy(g->d_inv, inv.data(), sizeof(uint32_t) * n_nodes, hipMemcpyHostToDevice)))
+      return dev_err(e, "node order upload");
+    g->h_perm.swap(perm);
+  }
 
   // Pack and upload the step records through two pinned staging buffers.
   if (S > 0) {
@@ -517,7 +629,7 @@ pgsgd_status pgsgd_graph_create(uint32_t n_nodes, const uint32_t* node_len, uint
           const uint32_t v = step_node[s];
           const uint32_t len = node_len[v & kNodeMask];
           out_rec[k].pos = acc;
-          out_rec[k].node_rev = v;
+          out_rec[k].node_rev = g->h_perm.empty() ? v : (g->h_perm[v & kNodeMask] | (v & kRevBit));
           out_rec[k].len = len;
           acc += len;
         }
@@ -556,6 +668,30 @@ pgsgd_status pgsgd_graph_get_info(const pgsgd_graph* g, pgsgd_graph_info* out) {
   out->device_bytes = g->device_bytes;
   out->device = g->device;
   out->max_path_steps = g->max_path_steps;
+  out->renumbered = g->h_perm.empty() ? 0u : 1u;
+  return ok();
+}
+
+pgsgd_status pgsgd_graph_get_order(const pgsgd_graph* g, uint32_t* perm_out) {
+  if (!g || !perm_out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  for (uint32_t n = 0; n < g->n_nodes; ++n) perm_out[n] = g->h_perm.empty() ? n : g->h_perm[n];
+  return ok();
+}
+
+pgsgd_status pgsgd_path_order(uint32_t n_nodes, const uint32_t* node_len, uint32_t n_paths,
+                              const uint64_t* path_off, const uint32_t* step_node, uint32_t* perm_out,
+                              double* far_before, double* far_after) {
+  if (!perm_out || (!node_len && n_nodes) || !path_off || (!step_node && path_off[n_paths]))
+    return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  for (uint64_t s = 0; s < path_off[n_paths]; ++s)
+    if ((step_node[s] & kNodeMask) >= n_nodes)
+      return fail(PGSGD_ERR_INVALID_ARG, "step %llu refers to node %u >= n_nodes %u", (unsigned long long)s,
+                  step_node[s] & kNodeMask, n_nodes);
+  std::vector<uint32_t> perm;
+  path_guided_order(n_nodes, node_len, n_paths, path_off, step_node, perm);
+  std::copy(perm.begin(), perm.end(), perm_out);
+  if (far_before) *far_before = far_step_fraction(n_paths, path_off, step_node, nullptr);
+  if (far_after) *far_after = far_step_fraction(n_paths, path_off, step_node, perm.data());
   return ok();
 }
 
@@ -566,7 +702,7 @@ pgsgd_status pgsgd_init_coords(pgsgd_graph* g, uint64_t seed, uint32_t graph_id,
   if (graph_id >= (1u << 24)) return fail(PGSGD_ERR_INVALID_ARG, "graph_id must be < 2^24");
   if (g->n_nodes == 0) return ok();
   DeviceGuard guard(g->device);
-  HIP_TRY(launch_init_coords(g->d_rec, g->d_first, g->n_nodes, (uint32_t)seed, (uint32_t)(seed >> 32),
+  HIP_TRY(launch_init_coords(g->d_rec, g->d_first, g->n_nodes, g->d_inv, (uint32_t)seed, (uint32_t)(seed >> 32),
                              (kStreamInit << 24) | graph_id, jitter, coords, (hipStream_t)stream));
   return ok();
 }
@@ -628,14 +764,53 @@ uint32_t resolve_schedule(const pgsgd_params* p) {
   return p->schedule != PGSGD_SCHEDULE_AUTO ? p->schedule : (uint32_t)PGSGD_SCHEDULE_WINDOWED;
 }
 
-// Window-major scratch: windows of 2^window_shift(S) steps, grouped into
-// kXcds * streams runs by the piece of their path they lie in.
-pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
+// Host tables of the window-major schedule for `streams` runs per XCD:
+// windows of 2^window_shift(S) steps, grouped into kXcds * streams runs by
+// the piece of their path they lie in (built once, kept on the graph).
+pgsgd_status local_host_tables(pgsgd_graph* g, uint32_t streams) {
   const uint32_t shift = window_shift(g->S);
   const uint32_t nwin = (uint32_t)((g->S + (1ull << shift) - 1) >> shift);
   if ((size_t)nwin * 4 > g->lds_limit)
     return fail(PGSGD_ERR_UNSUPPORTED, "the window histogram (%u windows) exceeds the %zu-byte LDS of a block", nwin,
                 g->lds_limit);
+  if (!g->h_lorder.empty() && g->h_loc_shift == shift && g->h_loc_streams == streams) return PGSGD_OK;
+  const uint32_t runs = kXcds * streams;
+  // run of a window: the piece of its path it starts in (each path cut into
+  // `runs` equal pieces); windows keep their id order inside a run
+  std::vector<uint32_t> order(nwin), sbeg(runs + 1, 0), run_of(nwin), wpath(nwin);
+  uint32_t p = 0;
+  for (uint32_t w = 0; w < nwin; ++w) {
+    const uint64_t st0 = (uint64_t)w << shift;
+    while (p + 1 < g->n_paths && g->h_path_off[p + 1] <= st0) ++p;
+    const uint64_t b = g->h_path_off[p], len = g->h_path_off[p + 1] - b;
+    const uint64_t st1 = std::min<uint64_t>(g->S, st0 + (1ull << shift));  // window [st0, st1)
+    wpath[w] = st1 <= g->h_path_off[p + 1] ? p : (p | 0x80000000u);
+    const uint64_t r = len ? ((st0 - b) * runs) / len : 0;
+    run_of[w] = (uint32_t)std::min<uint64_t>(r, runs - 1);
+    ++sbeg[run_of[w] + 1];
+  }
+  for (uint32_t r = 0; r < runs; ++r) sbeg[r + 1] += sbeg[r];
+  std::vector<uint32_t> cur(sbeg.begin(), sbeg.end() - 1);
+  for (uint32_t w = 0; w < nwin; ++w) order[cur[run_of[w]]++] = w;
+  // a row of xitem holds the prefix over the windows of one run and its total
+  uint32_t longest = 0;
+  for (uint32_t r = 0; r < runs; ++r) longest = std::max(longest, sbeg[r + 1] - sbeg[r]);
+  g->h_lorder.swap(order);
+  g->h_lsbeg.swap(sbeg);
+  g->h_lwpath.swap(wpath);
+  g->h_loc_xstride = longest + 1;
+  g->h_loc_shift = shift;
+  g->h_loc_streams = streams;
+  return PGSGD_OK;
+}
+
+// Window-major scratch of the graph: the host tables on the device plus two
+// count/offset sets (allocated on first use).
+pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
+  pgsgd_status st0 = local_host_tables(g, streams);
+  if (st0) return st0;
+  const uint32_t shift = g->h_loc_shift;
+  const uint32_t nwin = (uint32_t)g->h_lwpath.size();
   if (g->d_lcount && g->loc_nwin == nwin && g->loc_shift == shift && g->loc_streams == streams) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
   const auto set = {(void**)&g->d_lcount, (void**)&g->d_loff, (void**)&g->d_lxitem, (void**)&g->d_lqueue,
@@ -645,30 +820,8 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
   g->loc_nwin = nwin;
   g->loc_shift = shift;
   g->loc_streams = streams;
+  g->loc_xstride = g->h_loc_xstride;
   const uint32_t runs = kXcds * streams;
-  // run of a window: the piece of its path it starts in (each path cut into
-  // `runs` equal pieces); windows keep their id order inside a run
-  std::vector<uint32_t> order(nwin), sbeg(runs + 1, 0), run_of(nwin), wpath(nwin);
-  {
-    uint32_t p = 0;
-    for (uint32_t w = 0; w < nwin; ++w) {
-      const uint64_t st0 = (uint64_t)w << shift;
-      while (p + 1 < g->n_paths && g->h_path_off[p + 1] <= st0) ++p;
-      const uint64_t b = g->h_path_off[p], len = g->h_path_off[p + 1] - b;
-      const uint64_t st1 = std::min<uint64_t>(g->S, st0 + (1ull << shift));  // window [st0, st1)
-      wpath[w] = st1 <= g->h_path_off[p + 1] ? p : (p | 0x80000000u);
-      const uint64_t r = len ? ((st0 - b) * runs) / len : 0;
-      run_of[w] = (uint32_t)std::min<uint64_t>(r, runs - 1);
-      ++sbeg[run_of[w] + 1];
-    }
-    for (uint32_t r = 0; r < runs; ++r) sbeg[r + 1] += sbeg[r];
-    std::vector<uint32_t> cur(sbeg.begin(), sbeg.end() - 1);
-    for (uint32_t w = 0; w < nwin; ++w) order[cur[run_of[w]]++] = w;
-  }
-  // a row of xitem holds the prefix over the windows of one run and its total
-  uint32_t longest = 0;
-  for (uint32_t r = 0; r < runs; ++r) longest = std::max(longest, sbeg[r + 1] - sbeg[r]);
-  g->loc_xstride = longest + 1;
   const pgsgd_status st = [&]() -> pgsgd_status {
     pgsgd_status e;
     if ((e = dev_alloc(g, &g->d_lcount, nwin))) return e;
@@ -682,9 +835,9 @@ pgsgd_status ensure_local(pgsgd_graph* g, uint32_t streams, hipStream_t s) {
     if ((e = dev_alloc(g, &g->d_loff2, nwin + 1))) return e;
     if ((e = dev_alloc(g, &g->d_lxitem2, (size_t)runs * g->loc_xstride))) return e;
     if ((e = dev_alloc(g, &g->d_lqueue2, (size_t)runs * 16))) return e;
-    HIP_TRY(hipMemcpy(g->d_lorder, order.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->d_lsbeg, sbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->d_lwpath, wpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_lorder, g->h_lorder.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_lsbeg, g->h_lsbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_lwpath, g->h_lwpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice));
     HIP_TRY(launch_fill_u32(g->d_lcount, nwin, 0u, s));  // the histograms must start at zero
     HIP_TRY(launch_fill_u32(g->d_lcount2, nwin, 0u, s));
     return PGSGD_OK;
@@ -921,7 +1074,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
       for (auto e : v) (void)hipEventDestroy(e);
     }
   } events_free{ev};
-  if (!tracing) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  if (!tracing) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
   // Windowed layouts of several iterations of at least kOverlapMinTerms
   // terms count iteration it + 1 on the graph's counting stream while
   // iteration it is laid out, alternating between two count/offset sets: a
@@ -984,7 +1137,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     if (subset) break;
   }
   if (iter_ms) HIP_TRY(hipEventRecord(ev.back(), s));
-  if (!tracing) HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
+  if (!tracing) HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, g->d_inv, s));
   if (iter_ms) {
     HIP_TRY(hipEventSynchronize(ev.back()));
     for (uint32_t k = 0; k < n_run; ++k) {
@@ -1133,9 +1286,9 @@ pgsgd_status pgsgd_apply_terms(pgsgd_graph* g, float eta, const uint64_t* i, con
   if (count >= (1ull << 40)) return fail(PGSGD_ERR_RANGE, "count too large");
   DeviceGuard guard(g->device);
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
   HIP_TRY(launch_apply_terms(g->d_rec, g->d_work, eta, i, j, flags, count, s));
-  HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, s));
+  HIP_TRY(launch_from_work(g->d_work, coords, g->n_nodes, g->d_inv, s));
   return ok();
 }
 
@@ -1160,10 +1313,102 @@ pgsgd_status pgsgd_apply_slots(pgsgd_graph* g, const pgsgd_params* p, uint32_t i
   return layout_impl(g, &q, coords, nullptr, nullptr, nullptr, stream, h);
 }
 
+namespace {
+
+// Launch arguments of the window-major passes over the graph's segments
+// (ensure_sps_windowed done): slots drawn from Philox stream slot_stream;
+// loss_pairs > 0 counts the loss's plain pairs instead of Eq. 2's.
+SpsWinLaunch sps_win_launch(const pgsgd_graph* g, const StressLaunch& P, uint32_t slot_stream, uint32_t graph_id,
+                            uint64_t loss_pairs) {
+  SpsWinLaunch W{};
+  W.P = P;
+  W.slot_c3 = (slot_stream << 24) | (graph_id & 0xFFFFFFu);
+  W.win_shift = g->sps_shift;
+  W.n_seg = g->sps_nseg;
+  W.xstride = g->sps_xstride;
+  W.count_blocks = (uint32_t)g->n_cu * 2;
+  W.seg_start = g->d_sseg_start;
+  W.seg_path = g->d_sseg_path;
+  W.wseg = g->d_swseg;
+  W.count = g->d_scount;
+  W.seg_off = g->d_soff;
+  W.sbeg = g->d_ssbeg;
+  W.xitem = g->d_sxitem;
+  W.queue = g->d_squeue;
+  W.loss_pairs = loss_pairs;
+  return W;
+}
+
+// Segments and their counts for the loss's window-major pairs (reading R22) of
+// one optimiser step: validates what the window-major loss needs.
+pgsgd_status loss_win_prepare(pgsgd_graph* g, const pgsgd_params* p, const StressLaunch& P, uint64_t n_pairs,
+                              hipStream_t s, SpsWinLaunch* W) {
+  pgsgd_status st = ensure_sps_windowed(g, s);
+  if (st) return st;
+  if ((size_t)g->path_slots * 8 + (size_t)g->sps_nseg * 4 > g->lds_limit)
+    return fail(PGSGD_ERR_UNSUPPORTED, "the segment histogram (%u segments) exceeds the %zu-byte LDS of a block",
+                g->sps_nseg, g->lds_limit);
+  if (n_pairs >= (1ull << 32))
+    return fail(PGSGD_ERR_UNSUPPORTED, "n_pairs %llu too large for 32-bit segment counts (the PLAIN order has no "
+                "such limit)", (unsigned long long)n_pairs);
+  *W = sps_win_launch(g, P, kStreamLossSlot, p->graph_id, n_pairs);
+  HIP_TRY(launch_sps_win_count_scan(*W, s));
+  return PGSGD_OK;
+}
+
+}  // namespace
+
+namespace {
+
+struct OutlierSink {
+  double threshold = 0.0;
+  uint64_t max_out = 0;
+  uint64_t *i = nullptr, *j = nullptr;
+  uint8_t* e = nullptr;
+  double* s = nullptr;
+  uint64_t* n_host = nullptr;
+};
+
+pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
+                              uint32_t pair_mode, double zipf_theta, uint32_t zipf_window, pgsgd_stress_result* out,
+                              void* stream, const OutlierSink* sink);
+
+}  // namespace
+
 pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed,
                                      uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
                                      pgsgd_stress_result* out, void* stream) {
+  return path_stress_impl(g, coords, m, seed, graph_id, pair_mode, zipf_theta, zipf_window, out, stream, nullptr);
+}
+
+pgsgd_status pgsgd_path_stress_outliers(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed,
+                                        uint32_t graph_id, uint32_t pair_mode, double zipf_theta,
+                                        uint32_t zipf_window, double threshold, uint64_t max_out, uint64_t* i_out,
+                                        uint64_t* j_out, uint8_t* e_out, double* s_out, uint64_t* n_out,
+                                        pgsgd_stress_result* out, void* stream) {
+  if (!n_out || (max_out && (!i_out || !j_out || !e_out || !s_out)))
+    return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (!std::isfinite(threshold)) return fail(PGSGD_ERR_INVALID_ARG, "threshold must be finite");
+  OutlierSink sink;
+  sink.threshold = threshold;
+  sink.max_out = max_out;
+  sink.i = i_out;
+  sink.j = j_out;
+  sink.e = e_out;
+  sink.s = s_out;
+  sink.n_host = n_out;
+  pgsgd_stress_result tmp;
+  return path_stress_impl(g, coords, m, seed, graph_id, pair_mode, zipf_theta, zipf_window, out ? out : &tmp, stream,
+                          &sink);
+}
+
+namespace {
+
+pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
+                              uint32_t pair_mode, double zipf_theta, uint32_t zipf_window, pgsgd_stress_result* out,
+                              void* stream, const OutlierSink* sink) {
   if (!g || !coords || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (sink) *sink->n_host = 0;
   if (pair_mode > PGSGD_PAIRS_UNIFORM_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown pair mode %u", pair_mode);
   if (pair_mode == PGSGD_PAIRS_POWER_LAW) {
     if (zipf_window < 1 || zipf_window > 65535)
@@ -1191,6 +1436,16 @@ pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32
   P.count = g->S;
   P.W = zipf_window;
   P.work = g->d_work;
+  if (sink) {
+    P.out_count = g->d_out_n + 3;  // d_out_n[3]: the outlier counter
+    P.out_max = sink->max_out;
+    P.out_threshold = sink->threshold;
+    P.out_i = sink->i;
+    P.out_j = sink->j;
+    P.out_e = sink->e;
+    P.out_s = sink->s;
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(P.out_count), 2, 0u, s));
+  }
   if (mode == PGSGD_PAIRS_UNIFORM_WINDOWED) {
     pgsgd_status st = ensure_sps_windowed(g, s);
     if (st) return st;
@@ -1199,29 +1454,15 @@ pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32
                   g->sps_nseg, g->lds_limit);
     if (((uint64_t)m << (g->sps_shift + 1)) >= (1ull << 32))
       return fail(PGSGD_ERR_UNSUPPORTED, "pairs_per_step %u too large for 32-bit segment counts", m);
-    SpsWinLaunch W{};
-    W.P = P;
-    W.slot_c3 = (kStreamSpsSlot << 24) | (graph_id & 0xFFFFFFu);
-    W.win_shift = g->sps_shift;
-    W.n_seg = g->sps_nseg;
-    W.xstride = g->sps_xstride;
-    W.count_blocks = (uint32_t)g->n_cu * 2;
-    W.seg_start = g->d_sseg_start;
-    W.seg_path = g->d_sseg_path;
-    W.wseg = g->d_swseg;
-    W.count = g->d_scount;
-    W.seg_off = g->d_soff;
-    W.sbeg = g->d_ssbeg;
-    W.xitem = g->d_sxitem;
-    W.queue = g->d_squeue;
-    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+    const SpsWinLaunch W = sps_win_launch(g, P, kStreamSpsSlot, graph_id, 0);
+    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
     HIP_TRY(launch_sps_win_count_scan(W, s));
     HIP_TRY(launch_sps_win_pass(W, 1, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, s));
     HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
                                 g->d_mean, nullptr, nullptr, s));
     HIP_TRY(launch_sps_win_pass(W, 2, g->d_mean, g->d_part_f, nullptr, nullptr, kStressBlocks, s));
   } else {
-    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
     HIP_TRY(launch_sps_pass(P, 1, mode, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
     HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
                                 g->d_mean, nullptr, nullptr, s));
@@ -1243,8 +1484,13 @@ pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32
   const double half = n[0] ? 1.96 * out->stddev / std::sqrt((double)n[0]) : 0.0;
   out->ci_lo = out->mean - half;
   out->ci_hi = out->mean + half;
+  if (sink) {
+    HIP_TRY(hipMemcpy(sink->n_host, P.out_count, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  }
   return ok();
 }
+
+}  // namespace
 
 pgsgd_status pgsgd_path_stress(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
                                pgsgd_stress_result* out, void* stream) {
@@ -1262,7 +1508,7 @@ pgsgd_status pgsgd_path_stress_exact(pgsgd_graph* g, const float* coords, double
   hipStream_t s = (hipStream_t)stream;
   StressLaunch P = make_stress_launch(g, coords, kStreamSps, 0, 0);
   P.work = g->d_work;
-  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
   HIP_TRY(launch_path_stress_exact(P, g->d_part_f, g->d_part_n, s));
   HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, kStressBlocks, g->d_out_f, g->d_out_n, nullptr,
                               nullptr, nullptr, s));
@@ -1292,8 +1538,14 @@ pgsgd_status pgsgd_stress_forward(pgsgd_graph* g, const pgsgd_params* p, const f
   P.word2 = step;
   P.count = g->S ? n_pairs : 0;
   P.work = g->d_work;
-  if (P.count) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
-  HIP_TRY(launch_stress_fwd(P, g->d_part_f, g->d_part_n, s));
+  if (P.count) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
+  if (P.count && resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
+    SpsWinLaunch W;
+    if ((st = loss_win_prepare(g, p, P, n_pairs, s, &W))) return st;
+    HIP_TRY(launch_loss_win_fwd(W, g->d_part_f, g->d_part_n, kStressBlocks, s));
+  } else {
+    HIP_TRY(launch_stress_fwd(P, g->d_part_f, g->d_part_n, s));
+  }
   HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, kStressBlocks, nullptr, nullptr, nullptr, loss_dev,
                               n_valid_dev, s));
   return ok();
@@ -1318,8 +1570,14 @@ pgsgd_status pgsgd_stress_backward(pgsgd_graph* g, const pgsgd_params* p, const 
   P.word2 = step;
   P.count = n_pairs;
   P.work = g->d_work;
-  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, s));
-  HIP_TRY(launch_stress_bwd(P, grad_out_dev, n_valid_dev, grad_coords, s));
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
+  if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
+    SpsWinLaunch W;
+    if ((st = loss_win_prepare(g, p, P, n_pairs, s, &W))) return st;
+    HIP_TRY(launch_loss_win_bwd(W, grad_out_dev, n_valid_dev, grad_coords, kStressBlocks, s));
+  } else {
+    HIP_TRY(launch_stress_bwd(P, grad_out_dev, n_valid_dev, grad_coords, s));
+  }
   return ok();
 }
 
@@ -1501,7 +1759,7 @@ pgsgd_status batch_build_windowed(pgsgd_graph* const* graphs, uint32_t n, const 
       e = hipStreamWaitEvent(bs[j], fork, 0);
       for (uint32_t k : b->branch_graphs[j]) {
         pgsgd_graph* g = graphs[k];
-        if (!e) e = launch_to_work(coords[k], g->d_work, g->n_nodes, bs[j]);
+        if (!e) e = launch_to_work(coords[k], g->d_work, g->n_nodes, g->d_inv, bs[j]);
         for (uint32_t it = p->first_iter; it < last && !e; ++it) {
           LocalLaunch W = b->wl[k];
           W.L.iter = it;
@@ -1509,7 +1767,7 @@ pgsgd_status batch_build_windowed(pgsgd_graph* const* graphs, uint32_t n, const 
           W.L.eta = b->weta[k][it];
           e = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
         }
-        if (!e) e = launch_from_work(g->d_work, coords[k], g->n_nodes, bs[j]);
+        if (!e) e = launch_from_work(g->d_work, coords[k], g->n_nodes, g->d_inv, bs[j]);
       }
       if (!e) e = hipEventRecord(join[j], bs[j]);
       if (!e) e = hipStreamWaitEvent(cs, join[j], 0);
@@ -1683,7 +1941,7 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
     const uint32_t last = p->last_iter == 0 ? p->n_iters : p->last_iter;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     for (uint32_t k = 0; k < n && e == hipSuccess; ++k)
-      e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, cs);
+      e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, graphs[k]->d_inv, cs);
     for (uint32_t it = p->first_iter; it < last && e == hipSuccess; ++it) {
       BatchLaunch Li = L;
       Li.iter = it;
@@ -1691,7 +1949,7 @@ pgsgd_status batch_build(pgsgd_graph* const* graphs, uint32_t n, const pgsgd_par
       e = launch_layout_batch(Li, b->blocks, t.block_threads, cs);
     }
     for (uint32_t k = 0; k < n && e == hipSuccess; ++k)
-      e = launch_from_work(graphs[k]->d_work, coords[k], graphs[k]->n_nodes, cs);
+      e = launch_from_work(graphs[k]->d_work, coords[k], graphs[k]->n_nodes, graphs[k]->d_inv, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -1815,7 +2073,7 @@ pgsgd_status autotune_windowed(pgsgd_graph* const* graphs, uint32_t n, const pgs
     if (!e) e = hipEventCreateWithFlags(&join[j], hipEventDisableTiming);
   }
   // the caller's coordinates are loaded into the working copies and never written back
-  for (uint32_t k = 0; k < n && !e; ++k) e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, s);
+  for (uint32_t k = 0; k < n && !e; ++k) e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, graphs[k]->d_inv, s);
   auto run = [&](uint32_t nb, float* ms) -> hipError_t {
     const auto br = assign_branches(graphs, n, nb);
     hipError_t r = hipEventRecord(e0, s);
@@ -1915,7 +2173,7 @@ pgsgd_status pgsgd_autotune_batched(pgsgd_graph* const* graphs, uint32_t n, cons
         float ms = 0.0f;
         bool good = true;
         for (uint32_t k = 0; k < n && good; ++k)
-          good = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, s) == hipSuccess;
+          good = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, graphs[k]->d_inv, s) == hipSuccess;
         if (good) good = launch_layout_batch(L, b->blocks, th, s) == hipSuccess;  // warm-up
         if (good) good = hipEventRecord(e0, s) == hipSuccess;
         for (int r = 0; r < 2 && good; ++r) good = launch_layout_batch(L, b->blocks, th, s) == hipSuccess;

@@ -62,6 +62,35 @@ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) { return __u
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Exclusive prefix of v over the block (blockDim.x = 1024: 16 waves): wave
+// scans with shuffles, then one wave scans the 16 wave totals.  *total gets
+// the block sum.  Every thread calls it.
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* lds16, uint64_t* total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) lds16[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    uint64_t t = lane < 16 ? lds16[lane] : 0;
+#pragma unroll
+    for (uint32_t d = 1; d < 16; d <<= 1) {
+      const uint64_t y = __shfl_up(t, d, 64);
+      if (lane >= d) t += y;
+    }
+    if (lane < 16) lds16[lane] = t;  // inclusive prefix of the wave totals
+  }
+  __syncthreads();
+  const uint64_t before = wave ? lds16[wave - 1] : 0;
+  *total = lds16[15];
+  __syncthreads();  // lds16 may be reused by the caller
+  return before + x - v;
+}
+
 // Largest p in [0, n_paths) with off[p] <= i (off is non-decreasing and
 // off[n_paths] = S > i).  Fixed trip count: log2 of the power of two >= n_paths.
 __device__ __forceinline__ uint32_t find_path(const uint64_t* __restrict__ off, uint32_t top_bit, uint64_t i) {

@@ -52,9 +52,11 @@ hipError_t launch_layout_iter(const LayoutLaunch& P, uint32_t blocks, uint32_t t
 hipError_t launch_layout_reuse(const LayoutLaunch& P, uint32_t blocks, uint32_t threads, hipStream_t s);
 hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const uint64_t* i, const uint64_t* j,
                               const uint8_t* f, uint64_t count, hipStream_t s);
-// boundary layout [2][n][2] <-> interleaved working copy [n][2](x, y)
-hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s);
-hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s);
+// boundary layout [2][n][2] (caller's node ids) <-> interleaved working copy
+// [n][2](x, y) (device node ids); inv[m] = caller id of device node m, or
+// NULL when the two orders are the same
+hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, const uint32_t* inv, hipStream_t s);
+hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, const uint32_t* inv, hipStream_t s);
 const void* layout_iter_kernel();
 // Error reporting shared by the host files (capi.hip): set_error stores the
 // calling thread's pgsgd_last_error() message and returns `code`;

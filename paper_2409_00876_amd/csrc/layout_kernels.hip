@@ -177,20 +177,25 @@ __global__ __launch_bounds__(256) void k_apply_terms(const StepRec* __restrict__
 }
 
 // Boundary layout [2][n][2] (X plane, Y plane) <-> working copy W[2n+e] = (x, y).
+// Working copy <-> boundary layout.  Thread k handles endpoint k = 2m + e of
+// device node m; with a renumbered graph its caller id is inv[m].
 __global__ __launch_bounds__(256) void k_to_work(const float* __restrict__ coords, float2* __restrict__ work,
-                                                 uint64_t n2) {
+                                                 uint64_t n2, const uint32_t* __restrict__ inv) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n2; k += stride)
-    work[k] = make_float2(coords[k], coords[n2 + k]);
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n2; k += stride) {
+    const uint64_t c = inv ? 2ull * inv[k >> 1] + (k & 1) : k;
+    work[k] = make_float2(coords[c], coords[n2 + c]);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_from_work(const float2* __restrict__ work, float* __restrict__ coords,
-                                                   uint64_t n2) {
+                                                   uint64_t n2, const uint32_t* __restrict__ inv) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n2; k += stride) {
     const float2 v = work[k];
-    coords[k] = v.x;
-    coords[n2 + k] = v.y;
+    const uint64_t c = inv ? 2ull * inv[k >> 1] + (k & 1) : k;
+    coords[c] = v.x;
+    coords[n2 + c] = v.y;
   }
 }
 
@@ -222,13 +227,16 @@ hipError_t launch_apply_terms(const StepRec* rec, float2* work, float eta, const
   return hipGetLastError();
 }
 
-hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_work, dim3(elementwise_grid(2 * n_nodes)), dim3(256), 0, s, coords, work, 2 * n_nodes);
+hipError_t launch_to_work(const float* coords, float2* work, uint64_t n_nodes, const uint32_t* inv, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_work, dim3(elementwise_grid(2 * n_nodes)), dim3(256), 0, s, coords, work, 2 * n_nodes,
+                     inv);
   return hipGetLastError();
 }
 
-hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, hipStream_t s) {
-  hipLaunchKernelGGL(k_from_work, dim3(elementwise_grid(2 * n_nodes)), dim3(256), 0, s, work, coords, 2 * n_nodes);
+hipError_t launch_from_work(const float2* work, float* coords, uint64_t n_nodes, const uint32_t* inv,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_from_work, dim3(elementwise_grid(2 * n_nodes)), dim3(256), 0, s, work, coords, 2 * n_nodes,
+                     inv);
   return hipGetLastError();
 }
 

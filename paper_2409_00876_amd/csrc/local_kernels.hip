@@ -60,44 +60,42 @@ __global__ __launch_bounds__(1024) void k_local_count(LocalLaunch P) {
     if (hist[k]) atomicAdd(&P.wcount[k], hist[k]);
 }
 
-// One block.  woff = exclusive prefix of wcount; per run the prefix of
-// ceil(n_w / 64) over its windows; then wcount = 0.
+// One block of 1024 threads.  woff = exclusive prefix of wcount (window-id
+// order); per run the prefix of ceil(n_w / 64) over its windows (run order);
+// then wcount = 0.  Each thread owns a contiguous chunk of windows; every
+// stage is a chunk pass plus a block scan, so no thread walks a long chain of
+// dependent loads.
 __global__ __launch_bounds__(1024) void k_local_scan(LocalLaunch P) {
-  __shared__ uint64_t part[1024];
+  __shared__ uint64_t lds16[16];
   const uint32_t n = P.n_win;
   const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
   const uint32_t k0 = min(n, threadIdx.x * per);
   const uint32_t k1 = min(n, k0 + per);
   uint64_t s = 0;
   for (uint32_t k = k0; k < k1; ++k) s += P.wcount[k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t acc = 0;
-    for (uint32_t k = 0; k < blockDim.x; ++k) {
-      const uint64_t v = part[k];
-      part[k] = acc;
-      acc += v;
-    }
-    P.woff[n] = acc;
-  }
-  __syncthreads();
-  uint64_t acc = part[threadIdx.x];
+  uint64_t total;
+  uint64_t acc = block_exclusive_scan(s, lds16, &total);
   for (uint32_t k = k0; k < k1; ++k) {
     P.woff[k] = acc;
     acc += P.wcount[k];
   }
-  __syncthreads();
-  if (threadIdx.x < kXcds * P.streams) {
-    const uint32_t run = threadIdx.x;
-    uint64_t* xi = P.xitem + (size_t)run * P.xstride;
+  if (threadIdx.x == 0) P.woff[n] = total;
+  // per run: the threads split the run's windows (in run order) into chunks
+  const uint32_t runs = kXcds * P.streams;
+  for (uint32_t run = 0; run < runs; ++run) {
+    const uint32_t b = P.sbeg[run], e = P.sbeg[run + 1], nq = e - b;
+    const uint32_t rper = (nq + blockDim.x - 1) / blockDim.x;
+    const uint32_t q0 = min(nq, threadIdx.x * rper), q1 = min(nq, q0 + rper);
     uint64_t items = 0;
-    const uint32_t b = P.sbeg[run], e = P.sbeg[run + 1];
-    for (uint32_t q = b; q < e; ++q) {
-      xi[q - b] = items;
-      items += (P.wcount[P.worder[q]] + 63) >> 6;
+    for (uint32_t q = q0; q < q1; ++q) items += (P.wcount[P.worder[b + q]] + 63) >> 6;
+    uint64_t run_total;
+    uint64_t pre = block_exclusive_scan(items, lds16, &run_total);
+    uint64_t* xi = P.xitem + (size_t)run * P.xstride;
+    for (uint32_t q = q0; q < q1; ++q) {
+      xi[q] = pre;
+      pre += (P.wcount[P.worder[b + q]] + 63) >> 6;
     }
-    xi[e - b] = items;
+    if (threadIdx.x == 0) xi[nq] = run_total;
   }
   __syncthreads();
   for (uint32_t k = k0; k < k1; ++k) P.wcount[k] = 0;
@@ -304,7 +302,10 @@ __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
   const uint32_t lane = threadIdx.x & 63u;
   for (uint32_t x = blockIdx.x % nx; x < kXcds; x += nx)
   for (uint32_t h = 0; h < P.streams; ++h) {
-    const uint32_t run = x * P.streams + (v + h) % P.streams;
+    // wave-uniform run: its metadata then comes through the scalar cache, and
+    // no vector-memory wait (which would also wait for the wave's in-flight
+    // far loads) is spent on it
+    const uint32_t run = uniform_u32(x * P.streams + (v + h) % P.streams);
     const uint32_t wb = uniform_u32(uload(P.sbeg + run));
     const uint32_t nq = uniform_u32(uload(P.sbeg + run + 1)) - wb;
     const uint64_t* __restrict__ xi = P.xitem + (size_t)run * P.xstride;

@@ -10,11 +10,13 @@
 namespace pgsgd {
 
 constexpr uint32_t kStreamSpsSlot = 6;  // Philox stream of the window-major sampled path stress slots
+constexpr uint32_t kStreamLossSlot = 7; // Philox stream of the window-major loss slots
 
 struct StressLaunch {
   const StepRec* rec;
   const float* coords;
   const float2* work;      // interleaved copy of coords (sampled path stress only)
+  const uint32_t* inv;     // renumbered graph: caller id of every device node id (else NULL)
   const uint64_t* path_off;
   const uint32_t* zipf;
   const uint16_t* guide;
@@ -29,6 +31,16 @@ struct StressLaunch {
   uint32_t word2;          // counter word 2
   uint32_t c3;
   uint32_t k0, k1;
+  // pass 1 of the sampled path stress, when out_count is set: pairs with stress
+  // above out_threshold are appended (i, j, e_i | e_j << 1, stress; the first
+  // out_max kept) and counted in *out_count
+  uint64_t* out_count;
+  uint64_t out_max;
+  double out_threshold;
+  uint64_t* out_i;
+  uint64_t* out_j;
+  uint8_t* out_e;
+  double* out_s;
 };
 
 // SPS: pass 1 writes per-block (sum, n_valid, n_skipped); pass 2 per-block sum
@@ -61,17 +73,25 @@ struct SpsWinLaunch {
   const uint32_t* sbeg;       // [kXcds + 1] first segment of every run
   uint64_t* xitem;            // [kXcds][xstride] prefix of 64-slot items over the segments of each run
   uint64_t* queue;            // [2][kXcds][16] item counters of the two passes (zeroed by the scan)
+  uint64_t loss_pairs;        // the loss's window-major pairs (reading R22): the number of plain pairs; 0 = SPS
 };
 hipError_t launch_sps_win_count_scan(const SpsWinLaunch& W, hipStream_t s);
 // grid: blocks a multiple of kXcds
 hipError_t launch_sps_win_pass(const SpsWinLaunch& W, int pass, const double* mean_dev, double* part_f,
                                uint64_t* part_n, uint64_t* part_skip, uint32_t blocks, hipStream_t s);
+// The loss (reading R22) over the segments' slots counted with loss_pairs:
+// forward per-block sums (grid: blocks a multiple of kXcds), and the adjoint
+// added into the planar gradient.
+hipError_t launch_loss_win_fwd(const SpsWinLaunch& W, double* part_f, uint64_t* part_n, uint32_t blocks,
+                               hipStream_t s);
+hipError_t launch_loss_win_bwd(const SpsWinLaunch& W, const float* grad_out, const uint64_t* n_valid, float* grad,
+                               uint32_t blocks, hipStream_t s);
 hipError_t launch_path_stress_exact(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,
                              hipStream_t s);
-hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, uint32_t k0,
-                              uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s);
+hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, const uint32_t* inv,
+                              uint32_t k0, uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s);
 hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, uint64_t* first_step,
                               hipStream_t s);
 hipError_t launch_adam(float* x, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,

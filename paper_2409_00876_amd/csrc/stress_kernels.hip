@@ -75,6 +75,19 @@ __device__ __forceinline__ double stress_work(const float2* __restrict__ W, uint
   return stress_xy(va.x, va.y, vb.x, vb.y, d);
 }
 
+// Pass 1 with outlier collection: a pair whose stress exceeds the threshold is
+// appended (slot from one atomic; the first out_max are kept).
+__device__ __forceinline__ void keep_outlier(const StressLaunch& P, uint64_t i, uint64_t j, uint32_t e, double st) {
+  if (!P.out_count || !(st > P.out_threshold)) return;
+  const unsigned long long k = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), 1ull);
+  if (k < P.out_max) {
+    P.out_i[k] = i;
+    P.out_j[k] = j;
+    P.out_e[k] = (uint8_t)e;
+    P.out_s[k] = st;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sampled path stress: thread-strided over steps s; step s owns pairs
 // q = m*s .. m*s+m-1, which all belong to the path of s.
@@ -133,6 +146,7 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, int mode,
       if (pass == 1) {
         acc += st;
         ++nv;
+        keep_outlier(P, i, j, r.r3 & 3u, st);
       } else {
 #pragma clang fp contract(off)
         acc += (st - mean) * (st - mean);
@@ -183,6 +197,8 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 
 // The segment histogram: step s owns the plain pairs q = m*s .. m*s+m-1 (all
 // of the path of s); each draws its i as k_sps does and counts its segment.
+// With loss_pairs set, the loss's plain pairs q < loss_pairs are counted
+// instead.
 __global__ __launch_bounds__(1024) void k_sps_win_count(SpsWinLaunch W) {
   extern __shared__ __align__(16) char lds[];
   const StressLaunch& P = W.P;
@@ -192,7 +208,21 @@ __global__ __launch_bounds__(1024) void k_sps_win_count(SpsWinLaunch W) {
   for (uint32_t k = threadIdx.x; k < W.n_seg; k += blockDim.x) hist[k] = 0;
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < P.S; s += stride) {
+  // the loss's pairs (reading R22): pair q < loss_pairs draws i uniformly over all steps
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < W.loss_pairs; q += stride) {
+    const Rand4 r = philox10((uint32_t)q, (uint32_t)(q >> 32), P.word2, P.c3, P.k0, P.k1);
+    const uint64_t i = mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), P.S);
+    const uint32_t w = (uint32_t)(i >> W.win_shift);
+    uint32_t lo = W.wseg[w], hi = W.wseg[w + 1];
+    while (hi - lo > 1) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (W.seg_start[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    atomicAdd(&hist[lo], 1u);
+  }
+  const uint64_t sps_steps = W.loss_pairs ? 0 : P.S;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < sps_steps; s += stride) {
     const uint32_t p = find_path(off, P.path_top, s);
     const uint64_t start = off[p], len = off[p + 1] - start;
     for (uint32_t k = 0; k < P.m; ++k) {
@@ -214,44 +244,39 @@ __global__ __launch_bounds__(1024) void k_sps_win_count(SpsWinLaunch W) {
     if (hist[k]) atomicAdd(&W.count[k], hist[k]);
 }
 
-// One block: seg_off = exclusive prefix of the counts, the per-run item
-// prefixes and zeroed item counters, then the histogram back to zero.
+// One block of 1024 threads: seg_off = exclusive prefix of the counts, the
+// per-run item prefixes and zeroed item counters, then the histogram back to
+// zero.  Each thread owns a contiguous chunk; every stage is a chunk pass and
+// a block scan.
 __global__ __launch_bounds__(1024) void k_sps_win_scan(SpsWinLaunch W) {
-  __shared__ uint64_t part[1024];
+  __shared__ uint64_t lds16[16];
   const uint32_t n = W.n_seg;
   const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
   const uint32_t k0 = min(n, threadIdx.x * per);
   const uint32_t k1 = min(n, k0 + per);
   uint64_t s = 0;
   for (uint32_t k = k0; k < k1; ++k) s += W.count[k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t acc = 0;
-    for (uint32_t k = 0; k < blockDim.x; ++k) {
-      const uint64_t v = part[k];
-      part[k] = acc;
-      acc += v;
-    }
-    W.seg_off[n] = acc;
-  }
-  __syncthreads();
-  uint64_t acc = part[threadIdx.x];
+  uint64_t total;
+  uint64_t acc = block_exclusive_scan(s, lds16, &total);
   for (uint32_t k = k0; k < k1; ++k) {
     W.seg_off[k] = acc;
     acc += W.count[k];
   }
-  __syncthreads();
-  if (threadIdx.x < kXcds) {
-    const uint32_t run = threadIdx.x;
-    uint64_t* xi = W.xitem + (size_t)run * W.xstride;
+  if (threadIdx.x == 0) W.seg_off[n] = total;
+  for (uint32_t run = 0; run < kXcds; ++run) {  // run x: segments [sbeg[x], sbeg[x + 1])
+    const uint32_t b = W.sbeg[run], e = W.sbeg[run + 1], nq = e - b;
+    const uint32_t rper = (nq + blockDim.x - 1) / blockDim.x;
+    const uint32_t q0 = min(nq, threadIdx.x * rper), q1 = min(nq, q0 + rper);
     uint64_t items = 0;
-    const uint32_t b = W.sbeg[run], e = W.sbeg[run + 1];
-    for (uint32_t g = b; g < e; ++g) {
-      xi[g - b] = items;
-      items += (W.count[g] + 63) >> 6;
+    for (uint32_t q = q0; q < q1; ++q) items += (W.count[b + q] + 63) >> 6;
+    uint64_t run_total;
+    uint64_t pre = block_exclusive_scan(items, lds16, &run_total);
+    uint64_t* xi = W.xitem + (size_t)run * W.xstride;
+    for (uint32_t q = q0; q < q1; ++q) {
+      xi[q] = pre;
+      pre += (W.count[b + q] + 63) >> 6;
     }
-    xi[e - b] = items;
+    if (threadIdx.x == 0) xi[nq] = run_total;
   }
   if (threadIdx.x < 2 * kXcds) W.queue[(size_t)threadIdx.x * 16] = 0;
   __syncthreads();
@@ -309,6 +334,7 @@ __global__ __launch_bounds__(256) void k_sps_win(SpsWinLaunch W, int pass, const
         if (pass == 1) {
           acc += st;
           ++nv;
+          keep_outlier(P, i, j, r.r3 & 3u, st);
         } else {
 #pragma clang fp contract(off)
           acc += (st - mean) * (st - mean);
@@ -489,10 +515,109 @@ __global__ __launch_bounds__(256) void k_stress_bwd(StressLaunch P, const float*
     const float gx = (float)(c * dx), gy = (float)(c * dy);
     float* __restrict__ GX = grad;
     float* __restrict__ GY = grad + 2ull * P.n_nodes;
+    if (P.inv) {  // the gradient is in the caller's node order
+      a = 2ull * P.inv[a >> 1] + (a & 1);
+      b = 2ull * P.inv[b >> 1] + (b & 1);
+    }
     unsafeAtomicAdd(&GX[a], gx);
     unsafeAtomicAdd(&GY[a], gy);
     unsafeAtomicAdd(&GX[b], -gx);
     unsafeAtomicAdd(&GY[b], -gy);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The loss over its window-major pairs (reading R22): the waves of XCD x take
+// the items (64 slots of one segment) of run x from the counter of row
+// `kGrad` of the queue; slot u draws Philox stream 7 (W.slot_c3) at counter u
+// with word 2 = the optimiser step: i uniform in the segment, j its power-law
+// partner, endpoint coins.  A segment's steps, their partners (at most W steps
+// away) and the coordinates and gradient entries of the nodes they visit stay
+// in the XCD's L2 while the XCD works on it.  Forward: per-block sums of the
+// stress and the valid-pair count; adjoint: as k_stress_bwd.
+// ---------------------------------------------------------------------------
+template <bool kGrad>
+__global__ __launch_bounds__(256) void k_loss_win(SpsWinLaunch W, const float* __restrict__ grad_out,
+                                                  const uint64_t* __restrict__ n_valid, float* __restrict__ grad,
+                                                  double* __restrict__ part_f, uint64_t* __restrict__ part_n) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  const StressLaunch& P = W.P;
+  uint32_t* zipf = reinterpret_cast<uint32_t*>(lds);
+  uint16_t* guide = reinterpret_cast<uint16_t*>(lds + (size_t)(P.W + 1) * 4);
+  for (uint32_t k = threadIdx.x; k <= P.W; k += blockDim.x) zipf[k] = P.zipf[k];
+  for (uint32_t k = threadIdx.x; k <= kGuideSize; k += blockDim.x) guide[k] = P.guide[k];
+  __syncthreads();
+  double scale = 0.0;
+  if (kGrad) {
+    const uint64_t n = n_valid[0];
+    if (n == 0) return;
+    scale = (double)grad_out[0] * 2.0 / (double)n;
+  }
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t x = blockIdx.x % kXcds;
+  const uint32_t gb = uload(W.sbeg + x);
+  const uint32_t nq = uload(W.sbeg + x + 1) - gb;
+  const uint64_t* __restrict__ xi = W.xitem + (size_t)x * W.xstride;
+  const uint64_t n_items = uniform_u64(uload(xi + nq));
+  unsigned long long* ctr = reinterpret_cast<unsigned long long*>(W.queue + ((size_t)(kGrad ? 1 : 0) * kXcds + x) * 16);
+  float* __restrict__ GX = grad;
+  float* __restrict__ GY = grad + 2ull * P.n_nodes;
+  double acc = 0.0;
+  uint64_t nv = 0;
+  uint32_t q = 0;
+  for (uint64_t m = 0, m_end = 0;; ++m) {
+    if (m >= m_end) {
+      uint64_t base = 0;
+      if (lane == 0) base = atomicAdd(ctr, (unsigned long long)kSpsGrab);
+      m = uniform_u64(base);
+      if (m >= n_items) break;
+      m_end = min(m + kSpsGrab, n_items);
+    }
+    while (q + 1 < nq && uniform_u64(uload(xi + q + 1)) <= m) q = uniform_u32(q + 1);
+    const uint32_t g = gb + q;
+    const uint64_t u0 = uniform_u64(uload(W.seg_off + g)) + (m - uniform_u64(uload(xi + q))) * 64;
+    const uint64_t u_end = uniform_u64(uload(W.seg_off + g + 1));
+    const uint64_t sst = uniform_u64(uload(W.seg_start + g));
+    const uint64_t slen = uniform_u64(uload(W.seg_start + g + 1)) - sst;
+    const uint32_t p = uniform_u32(uload(W.seg_path + g));
+    const uint64_t pst = uniform_u64(uload(P.path_off + p));
+    const uint64_t plen = uniform_u64(uload(P.path_off + p + 1)) - pst;
+    const uint64_t u = u0 + lane;
+    if (u >= u_end) continue;
+    const Rand4 r = philox10((uint32_t)u, (uint32_t)(u >> 32), P.word2, W.slot_c3, P.k0, P.k1);
+    const uint64_t i = sst + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), slen);
+    uint64_t j, a, b;
+    double d;
+    if (!partner_power_law(i, pst, plen, r.r2, r.r3, zipf, guide, P.W, j)) continue;
+    if (!pair_terms(P.rec, i, j, r.r3 & 1u, (r.r3 >> 1) & 1u, a, b, d) || a == b) continue;
+    if (!kGrad) {
+      acc += stress_work(P.work, a, b, d);
+      ++nv;
+    } else {
+      double dx, dy;
+      const double mag = delta_work(P.work, a, b, dx, dy);
+      if (mag == 0.0) continue;
+      const double c = scale * (mag - d) / (d * d) / mag;
+      const float gx = (float)(c * dx), gy = (float)(c * dy);
+      if (P.inv) {  // the gradient is in the caller's node order
+        a = 2ull * P.inv[a >> 1] + (a & 1);
+        b = 2ull * P.inv[b >> 1] + (b & 1);
+      }
+      unsafeAtomicAdd(&GX[a], gx);
+      unsafeAtomicAdd(&GY[a], gy);
+      unsafeAtomicAdd(&GX[b], -gx);
+      unsafeAtomicAdd(&GY[b], -gy);
+    }
+  }
+  if (!kGrad) {
+    acc = block_sum(acc, red_f);
+    nv = block_sum(nv, red_n);
+    if (threadIdx.x == 0) {
+      part_f[blockIdx.x] = acc;
+      part_n[blockIdx.x] = nv;
+    }
   }
 }
 
@@ -518,24 +643,27 @@ __global__ __launch_bounds__(256) void k_first_visit(const StepRec* __restrict__
   }
 }
 
+// Thread k handles endpoint k = 2m + e of device node m (caller id inv[m] on a
+// renumbered graph); the jitter draw is keyed by the caller's endpoint index.
 __global__ __launch_bounds__(256) void k_init_coords(const StepRec* __restrict__ rec,
                                                      const uint64_t* __restrict__ first, uint64_t n_nodes,
-                                                     uint32_t k0, uint32_t k1, uint32_t c3, float jitter,
-                                                     float* __restrict__ coords) {
+                                                     const uint32_t* __restrict__ inv, uint32_t k0, uint32_t k1,
+                                                     uint32_t c3, float jitter, float* __restrict__ coords) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   float* __restrict__ X = coords;
   float* __restrict__ Y = coords + 2 * n_nodes;
   for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 2 * n_nodes; k += stride) {
     const uint64_t s = first[k >> 1];
+    const uint64_t c = inv ? 2ull * inv[k >> 1] + (k & 1) : k;
     float x = 0.0f;
     if (s != ~0ull) {
       const StepRec r = load_rec(rec, s);
       x = (float)(r.pos + (int64_t)r.len * (int64_t)(k & 1));
     }
-    X[k] = x;
-    const Rand4 rn = philox10((uint32_t)k, (uint32_t)(k >> 32), 0u, c3, k0, k1);
+    X[c] = x;
+    const Rand4 rn = philox10((uint32_t)c, (uint32_t)(c >> 32), 0u, c3, k0, k1);
     const float u = (float)(rn.r0 >> 8) * (1.0f / 16777216.0f);
-    Y[k] = jitter * (u - 0.5f);
+    Y[c] = jitter * (u - 0.5f);
   }
 }
 
@@ -619,6 +747,22 @@ hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const
   return hipGetLastError();
 }
 
+hipError_t launch_loss_win_fwd(const SpsWinLaunch& W, double* part_f, uint64_t* part_n, uint32_t blocks,
+                               hipStream_t s) {
+  const size_t lds = (size_t)(W.P.W + 1) * 4 + (size_t)(kGuideSize + 1) * 2;
+  hipLaunchKernelGGL(k_loss_win<false>, dim3(blocks), dim3(kStressThreads), lds, s, W, nullptr, nullptr, nullptr,
+                     part_f, part_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_win_bwd(const SpsWinLaunch& W, const float* grad_out, const uint64_t* n_valid, float* grad,
+                               uint32_t blocks, hipStream_t s) {
+  const size_t lds = (size_t)(W.P.W + 1) * 4 + (size_t)(kGuideSize + 1) * 2;
+  hipLaunchKernelGGL(k_loss_win<true>, dim3(blocks), dim3(kStressThreads), lds, s, W, grad_out, n_valid, grad,
+                     nullptr, nullptr);
+  return hipGetLastError();
+}
+
 hipError_t launch_first_visit(const StepRec* rec, uint64_t S, uint64_t n_nodes, uint64_t* first_step,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n_nodes, 4096)), dim3(256), 0, s, first_step, n_nodes, ~0ull);
@@ -633,10 +777,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, uint32_t k0,
-                              uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s) {
+hipError_t launch_init_coords(const StepRec* rec, const uint64_t* first_step, uint64_t n_nodes, const uint32_t* inv,
+                              uint32_t k0, uint32_t k1, uint32_t c3, float jitter, float* coords, hipStream_t s) {
   hipLaunchKernelGGL(k_init_coords, dim3(grid_for(2 * n_nodes, 8192)), dim3(256), 0, s, rec, first_step, n_nodes,
-                     k0, k1, c3, jitter, coords);
+                     inv, k0, k1, c3, jitter, coords);
   return hipGetLastError();
 }
 

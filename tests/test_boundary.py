@@ -42,7 +42,9 @@ def test_binding_constants_match_the_header():
                "PGSGD_SCHEDULE_WINDOWED": _lib.SCHEDULE_WINDOWED,
                "PGSGD_PAIRS_UNIFORM": _lib.PAIRS_UNIFORM, "PGSGD_PAIRS_POWER_LAW": _lib.PAIRS_POWER_LAW,
                "PGSGD_PAIRS_UNIFORM_WINDOWED": _lib.PAIRS_UNIFORM_WINDOWED,
-               "PGSGD_FLAG_COUNT_AHEAD": _lib.FLAG_COUNT_AHEAD, "PGSGD_FLAG_COUNT_IN_ORDER": _lib.FLAG_COUNT_IN_ORDER}
+               "PGSGD_FLAG_COUNT_AHEAD": _lib.FLAG_COUNT_AHEAD, "PGSGD_FLAG_COUNT_IN_ORDER": _lib.FLAG_COUNT_IN_ORDER,
+               "PGSGD_RENUMBER_AUTO": _lib.RENUMBER_AUTO, "PGSGD_RENUMBER_NEVER": _lib.RENUMBER_NEVER,
+               "PGSGD_RENUMBER_ALWAYS": _lib.RENUMBER_ALWAYS}
     for name, val in declared.items():
         assert name in binding, f"{name} declared in pgsgd.h but missing from the binding"
         assert binding[name] == val, f"{name}: header {val}, binding {binding[name]}"
@@ -131,3 +133,53 @@ def test_python_binding_rejects_cpu_tensors():
     import torch
     with pytest.raises((ValueError, TypeError)):
         P._check_tensor(torch.zeros(4), torch.float32, 4, "coords")
+
+
+def test_device_byte_cap_forces_oom_before_device_work(monkeypatch, tiny_synth):
+    """PGSGD_MAX_DEVICE_BYTES below what a graph needs: OOM, reported before
+    any device work (so it shows without a GPU); a cap above it (or no cap)
+    gets past the check."""
+    sg = tiny_synth
+    monkeypatch.setenv("PGSGD_MAX_DEVICE_BYTES", "100000")  # the records alone need 16 B x 14,416 steps
+    st, h = _create(sg.n_nodes, sg.node_len, sg.path_off, sg.step_node)
+    assert st == _lib.ERR_OOM and not h.value
+    msg = P.lib().pgsgd_last_error().decode()
+    assert "PGSGD_MAX_DEVICE_BYTES = 100000" in msg and "needs" in msg
+    for cap in ("1000000000", "0", "garbage"):
+        monkeypatch.setenv("PGSGD_MAX_DEVICE_BYTES", cap)
+        st, h = _create(sg.n_nodes, sg.node_len, sg.path_off, sg.step_node)
+        assert st in (_lib.OK, _lib.ERR_DEVICE)
+        if st == _lib.OK:
+            P.lib().pgsgd_graph_destroy(h)
+
+
+def test_path_order_by_hand():
+    """Progressive linearization: path 0 gives 0 1 2; path 1 (0, 3, 2) inserts
+    node 3 right after 0; node 4 (on no path) goes last."""
+    perm, fb, fa = P.path_order([1, 1, 1, 1, 1], [0, 3, 6], [0, 1, 2, 0, 3 | 0x80000000, 2])
+    assert perm.tolist() == [0, 2, 3, 1, 4]
+    # consecutive steps 0-1, 1-2, 0-3, 3-2: no jump is above 32 ids in either order
+    assert fb == 0.0 and fa == 0.0
+
+
+def test_path_order_restores_locality_of_scrambled_ids(tiny_synth):
+    sg = tiny_synth
+    rng = np.random.default_rng(3)
+    q = rng.permutation(sg.n_nodes).astype(np.uint32)   # caller id of every original node
+    node_len = np.empty_like(sg.node_len)
+    node_len[q] = sg.node_len
+    steps = q[sg.step_node & 0x7FFFFFFF] | (sg.step_node & 0x80000000)
+    perm, fb, fa = P.path_order(node_len, sg.path_off, steps)
+    assert sorted(perm.tolist()) == list(range(sg.n_nodes))       # a permutation
+    assert fb > 0.9 and fa < 0.01
+    # the order depends on the graph only, not on the caller's ids
+    perm0, _, _ = P.path_order(sg.node_len, sg.path_off, sg.step_node)
+    assert np.array_equal(perm[q], perm0)
+
+
+def test_graph_create_ex_rejects_unknown_renumber_mode():
+    st = P.lib().pgsgd_graph_create_ex(3, np.array([1, 1, 1], np.uint32).ctypes.data, 1,
+                                       np.array([0, 3], np.uint64).ctypes.data,
+                                       np.array([0, 1, 2], np.uint32).ctypes.data, None, 0, 3,
+                                       ctypes.byref(ctypes.c_void_p()))
+    assert st == _lib.ERR_INVALID_ARG and "renumber" in P.lib().pgsgd_last_error().decode()

@@ -451,6 +451,30 @@ def test_graph_without_steps(P):
     assert torch.equal(c, before)
 
 
+def test_device_byte_cap_on_lazy_scratch(P, tiny_synth, monkeypatch):
+    """PGSGD_MAX_DEVICE_BYTES just above a graph's creation footprint: the
+    windowed layout's first-use tables no longer fit (OOM, coordinates
+    untouched), the plain layout still runs."""
+    import torch
+    g0 = P.Graph.from_synth(tiny_synth)
+    need = g0.device_bytes
+    g0.close()
+    monkeypatch.setenv("PGSGD_MAX_DEVICE_BYTES", str(need + 64))
+    g = P.Graph.from_synth(tiny_synth)
+    assert g.device_bytes == need
+    c = g.new_coords()
+    P.init_coords(g, c)
+    before = c.clone()
+    with pytest.raises(P.PgsgdError) as e:
+        P.layout(g, c, schedule=3)
+    assert e.value.status == -3 and "PGSGD_MAX_DEVICE_BYTES" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.equal(c, before)
+    P.layout(g, c, schedule=1, max_inflight_waves=1)
+    torch.cuda.synchronize()
+    assert not torch.equal(c, before)
+
+
 def test_sps_mode_and_size_errors(P, tiny):
     import torch
     from paper_2409_00876_amd import _lib
@@ -583,7 +607,7 @@ def _mid_goldens():
     return out
 
 
-@pytest.mark.parametrize("schedule", [1, 2, 3])
+@pytest.mark.parametrize("schedule", [1, 3])
 def test_full_layout_sps_parity_mid(P, mid, schedule):
     import torch
     goldens = _mid_goldens()
@@ -618,17 +642,22 @@ def small_diff(P):
     return sg, og, g, c
 
 
-def test_loss_and_gradient_match_oracle(P, small_diff):
+# the loss's pair order: plain enumeration (schedule 1) and window-major (reading R22, schedule 3, the default)
+LOSS_ORDERS = [(1, O.stress_loss_grad), (3, O.stress_loss_grad_windowed)]
+
+
+@pytest.mark.parametrize("schedule,ref", LOSS_ORDERS)
+def test_loss_and_gradient_match_oracle(P, small_diff, schedule, ref):
     import torch
     sg, og, g, c0 = small_diff
     n_pairs, step = 200_000, 3
     c = torch.from_numpy(c0).cuda()
-    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11)
-    L_ref, n_ref, grad_ref = O.stress_loss_grad(og, c0, n_pairs, seed=11, step=step)
+    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11, schedule=schedule)
+    L_ref, n_ref, grad_ref = ref(og, c0, n_pairs, seed=11, step=step)
     assert int(nv.item()) == n_ref
     assert abs(float(loss.item()) - L_ref) <= 1e-5 * abs(L_ref)
     grad = torch.zeros_like(c)
-    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11)
+    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11, schedule=schedule)
     gg = grad.cpu().numpy().astype(np.float64)
     gmax = np.abs(grad_ref).max()
     sel = np.abs(grad_ref) > 1e-6 * gmax
@@ -638,14 +667,15 @@ def test_loss_and_gradient_match_oracle(P, small_diff):
     assert np.all(err[~sel] <= 1e-6 * gmax)
 
 
-def test_gradient_matches_fp64_finite_differences(P, small_diff):
+@pytest.mark.parametrize("schedule,ref", LOSS_ORDERS)
+def test_gradient_matches_fp64_finite_differences(P, small_diff, schedule, ref):
     import torch
     sg, og, g, c0 = small_diff
     n_pairs, step = 50_000, 1
     c = torch.from_numpy(c0).cuda()
-    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11)
+    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11, schedule=schedule)
     grad = torch.zeros_like(c)
-    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11)
+    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11, schedule=schedule)
     gg = grad.cpu().numpy().astype(np.float64)
     gmax = np.abs(gg).max()
     rng = np.random.default_rng(3)
@@ -655,10 +685,32 @@ def test_gradient_matches_fp64_finite_differences(P, small_diff):
         cp, cm = c0.copy(), c0.copy()
         cp[k] += h
         cm[k] -= h
-        Lp = O.stress_loss_grad(og, cp, n_pairs, seed=11, step=step, want_grad=False)[0]
-        Lm = O.stress_loss_grad(og, cm, n_pairs, seed=11, step=step, want_grad=False)[0]
+        Lp = ref(og, cp, n_pairs, seed=11, step=step, want_grad=False)[0]
+        Lm = ref(og, cm, n_pairs, seed=11, step=step, want_grad=False)[0]
         fd = (Lp - Lm) / (float(cp[k]) - float(cm[k]))
         assert abs(fd - gg[k]) <= 1e-3 * abs(fd) + 1e-6 * gmax, (k, fd, gg[k])
+
+
+def test_windowed_loss_on_the_mid_graph_matches_oracle(P, mid):
+    """The window-major loss (reading R22) at the differentiable workload's
+    size: 1e7 pairs on the mid graph, loss and valid-pair count against the
+    oracle, the gradient against the oracle's on a sample of entries."""
+    import torch
+    sg, og, g = mid
+    c0 = O.init_coords(og)
+    c = torch.from_numpy(c0).cuda()
+    n_pairs, step = 10_000_000, 7
+    loss, nv = P.stress_forward(g, c, n_pairs, step, seed=11)
+    L_ref, n_ref, grad_ref = O.stress_loss_grad_windowed(og, c0, n_pairs, seed=11, step=step)
+    assert int(nv.item()) == n_ref
+    assert abs(float(loss.item()) - L_ref) <= 1e-5 * abs(L_ref)
+    grad = torch.zeros_like(c)
+    P.stress_backward(g, c, n_pairs, step, torch.ones(1, device="cuda"), nv, grad, seed=11)
+    gg = grad.cpu().numpy().astype(np.float64)
+    gmax = np.abs(grad_ref).max()
+    sel = np.abs(grad_ref) > 1e-4 * gmax
+    err = np.abs(gg - grad_ref)
+    assert np.all(err[sel] <= 1e-4 * np.abs(grad_ref[sel]) + 1e-6 * gmax)
 
 
 def test_autograd_function_and_adam_reduce_loss(P, small_diff):
@@ -803,3 +855,113 @@ def test_batch_handle_runs_and_autotune_keeps_coords(P, small_batch):
     torch.cuda.synchronize()
     assert any(not torch.equal(a, c) for a, c in zip(before, cs))
     b.close()
+
+
+def _scrambled(sg, seed):
+    """The same graph with node ids permuted at random (caller id of original node k: q[k])."""
+    rng = np.random.default_rng(seed)
+    q = rng.permutation(sg.n_nodes).astype(np.uint32)
+    node_len = np.empty_like(sg.node_len)
+    node_len[q] = sg.node_len
+    steps = q[sg.step_node & 0x7FFFFFFF] | (sg.step_node & 0x80000000)
+    return synth.SynthGraph(node_len, sg.path_off, steps, dict(sg.stats), sg.name + "-scrambled"), q
+
+
+def test_renumbered_graph_is_invisible_to_the_caller(P, tiny_synth):
+    """The path-guided device order against the caller's own: the same initial
+    layout, sampled terms, one-wave layouts (both schedules) bit for bit, the
+    same sampled path stress, loss and (to float32 atomics' rounding) gradient,
+    all in the caller's node order."""
+    import torch
+    sg, _ = _scrambled(tiny_synth, 5)
+    a = P.Graph.from_synth(sg, renumber="never")
+    b = P.Graph.from_synth(sg, renumber="always")
+    assert not a.renumbered and b.renumbered
+    perm = b.order()
+    assert sorted(perm.tolist()) == list(range(sg.n_nodes)) and not np.array_equal(perm, np.arange(sg.n_nodes))
+    ca, cb = a.new_coords(), b.new_coords()
+    P.init_coords(a, ca)
+    P.init_coords(b, cb)
+    assert torch.equal(ca, cb)
+    for it in (0, 20):
+        for x, y in zip(P.sample_terms(a, it, 0, 4096), P.sample_terms(b, it, 0, 4096)):
+            assert torch.equal(x, y)
+    c0 = ca.clone()
+    for sched in (3, 1):
+        ca.copy_(c0)
+        cb.copy_(c0)
+        P.layout(a, ca, schedule=sched, max_inflight_waves=1)
+        P.layout(b, cb, schedule=sched, max_inflight_waves=1)
+        torch.cuda.synchronize()
+        assert torch.equal(ca, cb), f"schedule {sched}: coordinates differ"
+    for pairs in ("uniform", "uniform_windowed", "power_law"):
+        ra, rb = P.path_stress(a, ca, 10, 7, pairs=pairs), P.path_stress(b, cb, 10, 7, pairs=pairs)
+        assert ra["n_valid"] == rb["n_valid"] and ra["sum"] == rb["sum"], pairs
+    assert P.path_stress_exact(a, ca) == P.path_stress_exact(b, cb)
+    la, na = P.stress_forward(a, c0, 100_000, 3)
+    lb, nb = P.stress_forward(b, c0, 100_000, 3)
+    assert float(la) == float(lb) and int(na) == int(nb)
+    one = torch.ones(1, device="cuda")
+    ga, gb = torch.zeros_like(c0), torch.zeros_like(c0)
+    P.stress_backward(a, c0, 100_000, 3, one, na, ga)
+    P.stress_backward(b, c0, 100_000, 3, one, nb, gb)
+    torch.cuda.synchronize()
+    assert torch.allclose(ga, gb, rtol=1e-5, atol=1e-6 * float(ga.abs().max()))
+
+
+def test_scrambled_ids_lay_out_at_the_ordered_rate(P):
+    """A mid-size graph with random node ids: the automatic choice renumbers
+    it, and its layout runs at >= 90% of the locality-ordered graph's rate with
+    the same sampled path stress (5%); without renumbering it is slower."""
+    import time
+    import torch
+    base = synth.generate(400_000, 0.2, 32, 2)
+    sg, q = _scrambled(base, 9)
+    res = {}
+    for name, s_, mode in (("ordered", base, "auto"), ("scrambled", sg, "auto"), ("scrambled-never", sg, "never")):
+        g = P.Graph.from_synth(s_, renumber=mode)
+        if name == "scrambled":
+            assert g.renumbered
+        if name == "ordered":
+            assert not g.renumbered
+        c = g.new_coords()
+        P.init_coords(g, c)
+        P.layout(g, c, seed=3)  # warm-up
+        best = 1e9
+        for rep in range(3):
+            P.init_coords(g, c)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.layout(g, c)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        res[name] = (best, P.path_stress(g, c, 10, 7)["mean"])
+        print(f"[renumber] {name}: {best:.4f} s, SPS {res[name][1]:.5g}", flush=True)
+        g.close()
+    assert res["ordered"][0] / res["scrambled"][0] >= 0.9
+    assert abs(res["scrambled"][1] / res["ordered"][1] - 1) < 0.05
+
+
+@pytest.mark.parametrize("pairs", ["uniform", "power_law", "uniform_windowed"])
+def test_sps_outliers_equal_oracle(P, tiny, pairs):
+    """The pairs above a stress threshold (the top 1% of Eq. 2's pairs on a
+    partly converged tiny layout): the same set of pairs as the oracle's, with
+    the same stress, and the same estimate."""
+    import torch
+    sg, og, g = tiny
+    c0 = O.init_coords(og)
+    O.layout(og, c0, first_iter=0, last_iter=8)
+    n_all, i, j, e, st = O.sps_outliers(og, c0, 10, -1.0, max_out=10 * og.S + 1, seed=7, pairs=pairs)
+    thr = float(np.quantile(st, 0.99))
+    n_ref, i_ref, j_ref, e_ref, s_ref = O.sps_outliers(og, c0, 10, thr, seed=7, pairs=pairs)
+    c = torch.from_numpy(c0).cuda()
+    n, gi, gj, ge, gs, res = P.path_stress_outliers(g, c, 10, thr, max_out=4096, seed=7, pairs=pairs)
+    assert n == n_ref and res["n_valid"] == n_all
+    got = sorted(zip(gi.cpu().numpy().tolist(), gj.cpu().numpy().tolist(), ge.cpu().numpy().tolist(),
+                     gs.cpu().numpy().tolist()))
+    ref = sorted(zip(i_ref.tolist(), j_ref.tolist(), e_ref.tolist(), s_ref.tolist()))
+    assert [x[:3] for x in got] == [x[:3] for x in ref]
+    assert all(abs(a[3] - b[3]) <= 1e-12 * abs(b[3]) for a, b in zip(got, ref))
+    # max_out below the count: the count stays exact, max_out pairs are written
+    n2, gi2, *_ = P.path_stress_outliers(g, c, 10, thr, max_out=7, seed=7, pairs=pairs)
+    assert n2 == n_ref and gi2.numel() == 7

@@ -1005,3 +1005,22 @@ def test_threaded_sps_on_a_graph_with_empty_paths():
         b = O.sampled_path_stress(g, c, m=7, seed=1, pairs=pairs, threads=4)
         assert (a["n_valid"], a["n_skipped"]) == (b["n_valid"], b["n_skipped"])
         assert b["sum"] == pytest.approx(a["sum"], rel=1e-12)
+
+
+@pytest.mark.parametrize("pairs", ["uniform", "power_law", "uniform_windowed"])
+def test_sps_outliers_list_the_pairs_of_eq2(tiny_oracle, pairs):
+    # with a threshold below every stress the listing is every valid pair of Eq. 2: its count and its sum are
+    # the estimator's; a threshold keeps exactly the pairs above it
+    g = tiny_oracle
+    c = O.init_coords(g)
+    O.layout(g, c, first_iter=0, last_iter=8)
+    s = O.sampled_path_stress(g, c, m=5, seed=7, pairs=pairs)
+    n, i, j, e, st = O.sps_outliers(g, c, 5, -1.0, max_out=5 * g.S + 1, seed=7, pairs=pairs)
+    assert n == s["n_valid"] == len(st)
+    assert abs(float(np.sum(st)) - s["sum"]) <= 1e-9 * abs(s["sum"])
+    thr = float(np.quantile(st, 0.99))
+    n2, i2, j2, e2, st2 = O.sps_outliers(g, c, 5, thr, seed=7, pairs=pairs)
+    keep = st > thr
+    assert n2 == int(keep.sum()) and np.array_equal(st2, st[keep]) and np.array_equal(i2, i[keep])
+    n3, *_ = O.sps_outliers(g, c, 5, thr, max_out=3, seed=7, pairs=pairs)
+    assert n3 == n2
