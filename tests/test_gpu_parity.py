@@ -454,7 +454,8 @@ def test_graph_without_steps(P):
 def test_device_byte_cap_on_lazy_scratch(P, tiny_synth, monkeypatch):
     """PGSGD_MAX_DEVICE_BYTES just above a graph's creation footprint: the
     windowed layout's first-use tables no longer fit (OOM, coordinates
-    untouched), the plain layout still runs."""
+    untouched), the plain layout and the allocation-free entry point still
+    run."""
     import torch
     g0 = P.Graph.from_synth(tiny_synth)
     need = g0.device_bytes
@@ -471,6 +472,7 @@ def test_device_byte_cap_on_lazy_scratch(P, tiny_synth, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(c, before)
     P.layout(g, c, schedule=1, max_inflight_waves=1)
+    P.layout_noalloc(g, before, max_inflight_waves=1)
     torch.cuda.synchronize()
     assert not torch.equal(c, before)
 
@@ -894,13 +896,14 @@ def test_renumbered_graph_is_invisible_to_the_caller(P, tiny_synth):
         P.layout(b, cb, schedule=sched, max_inflight_waves=1)
         torch.cuda.synchronize()
         assert torch.equal(ca, cb), f"schedule {sched}: coordinates differ"
+    # the same pairs; the window-major orders take work from counters, so their sums agree to rounding
     for pairs in ("uniform", "uniform_windowed", "power_law"):
         ra, rb = P.path_stress(a, ca, 10, 7, pairs=pairs), P.path_stress(b, cb, 10, 7, pairs=pairs)
-        assert ra["n_valid"] == rb["n_valid"] and ra["sum"] == rb["sum"], pairs
+        assert ra["n_valid"] == rb["n_valid"] and abs(ra["sum"] - rb["sum"]) <= 1e-12 * abs(ra["sum"]), pairs
     assert P.path_stress_exact(a, ca) == P.path_stress_exact(b, cb)
     la, na = P.stress_forward(a, c0, 100_000, 3)
     lb, nb = P.stress_forward(b, c0, 100_000, 3)
-    assert float(la) == float(lb) and int(na) == int(nb)
+    assert abs(float(la) - float(lb)) <= 1e-6 * abs(float(la)) and int(na) == int(nb)
     one = torch.ones(1, device="cuda")
     ga, gb = torch.zeros_like(c0), torch.zeros_like(c0)
     P.stress_backward(a, c0, 100_000, 3, one, na, ga)
@@ -965,3 +968,33 @@ def test_sps_outliers_equal_oracle(P, tiny, pairs):
     # max_out below the count: the count stays exact, max_out pairs are written
     n2, gi2, *_ = P.path_stress_outliers(g, c, 10, thr, max_out=7, seed=7, pairs=pairs)
     assert n2 == n_ref and gi2.numel() == 7
+
+
+def test_windowed_batch_keeps_its_power_law_table(P, small_batch):
+    """A batch captured with W = 1000 keeps its own power-law table: calls on
+    its graphs with another window and exponent (which rewrite each graph's own
+    table) in between do not change what the batch samples, so its one-wave
+    layouts still equal the single-graph layouts with W = 1000."""
+    import torch
+    sgs, ogs, gs = small_batch
+    init = [O.init_coords(og) for og in ogs]
+    cb = [torch.from_numpy(c).cuda() for c in init]
+    b = P.Batch(gs, cb, tune={"block_threads": 256, "groups_per_item": 1, "blocks_per_cu": 1, "branches": 1},
+                graph_id=3)
+    for g, c in zip(gs, cb):
+        P.stress_forward(g, c, 10_000, 1, zipf_window=100, zipf_theta=0.5)
+    b.run()
+    torch.cuda.synchronize()
+    b.close()
+    for k, g in enumerate(gs):
+        c = torch.from_numpy(init[k]).cuda()
+        P.layout(g, c, graph_id=3 + k)
+        assert torch.equal(c, cb[k]), f"graph {k} differs from its single layout"
+
+
+def test_batch_rejects_the_data_reuse_variant(P, small_batch):
+    sgs, ogs, gs = small_batch
+    cs = [g.new_coords() for g in gs]
+    for kw in ({"reuse_factor": 2}, {"step_reduction": 2}):
+        with pytest.raises(P.PgsgdError):
+            P.Batch(gs, cs, **kw)
