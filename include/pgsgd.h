@@ -359,6 +359,26 @@ pgsgd_status pgsgd_init_coords(pgsgd_graph *g, uint64_t seed, uint32_t graph_id,
  */
 pgsgd_status pgsgd_layout(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);
 
+/*
+ * pgsgd_layout for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same layout, the same kernels and the same sampled terms, but the
+ * window tables of the WINDOWED schedule live in a device array of the
+ * library (4 MiB per device, held until the process ends; enough for the
+ * 32,768 windows the schedule allows) instead of buffers the graph allocates
+ * on first use, and every iteration counts its windows in order on `stream`.
+ * The call makes no hipMalloc/hipFree: the graph's working copy and power-law
+ * table are allocated by pgsgd_graph_create.  The PLAIN schedule needs no
+ * scratch and runs as in pgsgd_layout.
+ * All calls on one device share that device's array, and it keeps the last
+ * call's contents (the call itself clears what must start at zero): calls
+ * that overlap on one device, on any streams or graphs, race and give wrong
+ * layouts; order them on one stream.
+ * Errors: those of pgsgd_layout, plus INVALID_ARG for PGSGD_FLAG_COUNT_AHEAD
+ * (counting ahead needs a second table set), RANGE if a graph's window tables
+ * would exceed the array, UNSUPPORTED for a device ordinal >= 64.
+ */
+pgsgd_status pgsgd_layout_noalloc(pgsgd_graph *g, const pgsgd_params *p, float *coords, void *stream);
 
 /*
  * pgsgd_layout with measurement, by HIP events recorded on `stream`:

@@ -22,7 +22,7 @@ import torch
 from ._lib import (GfaView, FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
                    check, lib)
 
-__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "path_order", "LayoutParams", "layout", "layout_timed", "init_coords", "path_stress", "path_stress_outliers", "path_stress_exact", "schedule", "zipf_table",
+__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "path_order", "LayoutParams", "layout", "layout_noalloc", "layout_timed", "init_coords", "path_stress", "path_stress_outliers", "path_stress_exact", "schedule", "zipf_table",
            "sample_terms", "sample_terms_reuse", "apply_terms", "apply_slots", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
@@ -258,6 +258,18 @@ def layout(g: Graph, coords, params: LayoutParams | None = None, **kw):
     p = _params(params, kw)
     check(lib().pgsgd_layout(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()),
                              _stream(torch, coords.device)))
+    return coords
+
+
+def layout_noalloc(g: Graph, coords, params: LayoutParams | None = None, **kw):
+    """layout() without device allocation: the windowed schedule's tables live
+    in the library's per-device scratch array (calls on one device must not
+    overlap); async on the current stream."""
+    import torch
+    _check_tensor(coords, torch.float32, 4 * g.n_nodes, "coords")
+    p = _params(params, kw)
+    check(lib().pgsgd_layout_noalloc(g.handle, ctypes.byref(p), ctypes.c_void_p(coords.data_ptr()),
+                                     _stream(torch, coords.device)))
     return coords
 
 

@@ -126,6 +126,7 @@ SIGNATURES = {
     "pgsgd_zipf_table": ([_f64, _u32, _P], _i32),
     "pgsgd_init_coords": ([_P, _u64, _u32, _f32, _P, _P], _i32),
     "pgsgd_layout": ([_P, _P, _P, _P], _i32),
+    "pgsgd_layout_noalloc": ([_P, _P, _P, _P], _i32),
     "pgsgd_layout_timed": ([_P, _P, _P, _P, _P, _P, _P], _i32),
     "pgsgd_path_stress": ([_P, _P, _u32, _u64, _u32, _P, _P], _i32),
     "pgsgd_path_stress_pairs": ([_P, _P, _u32, _u64, _u32, _u32, ctypes.c_double, _u32, _P, _P], _i32),

@@ -974,6 +974,67 @@ pgsgd_status local_plan(pgsgd_graph* g, const pgsgd_params* p, size_t lds, const
   return PGSGD_OK;
 }
 
+// Byte offsets of the window tables inside one contiguous scratch region
+// (every table 256-byte aligned).
+struct ScratchCarve {
+  size_t wcount, woff, xitem, queue, worder, sbeg, wpath, total;
+};
+
+ScratchCarve carve_scratch(uint32_t nwin, uint32_t runs, uint32_t xstride) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  ScratchCarve c{};
+  size_t o = 0;
+  c.wcount = o, o = up(o + 4ull * nwin);
+  c.woff = o, o = up(o + 8ull * (nwin + 1));
+  c.xitem = o, o = up(o + 8ull * runs * xstride);
+  c.queue = o, o = up(o + 8ull * runs * 16);
+  c.worder = o, o = up(o + 4ull * nwin);
+  c.sbeg = o, o = up(o + 4ull * (runs + 1));
+  c.wpath = o, o = up(o + 4ull * nwin);
+  c.total = o;
+  return c;
+}
+
+// As local_plan, with the window tables in the caller-provided device region
+// `scratch` of `scratch_bytes` (nothing allocated): the host tables are copied
+// in and the histogram cleared on stream s, in stream order before the
+// iterations that read them.
+pgsgd_status local_plan_scratch(pgsgd_graph* g, const pgsgd_params* p, size_t lds, const LayoutLaunch& L,
+                                hipStream_t s, void* scratch, size_t scratch_bytes, LocalLaunch* W,
+                                uint32_t* blocks, uint32_t* threads) {
+  pgsgd_status st;
+  if ((st = local_host_tables(g, kLocalStreams))) return st;
+  if ((st = local_grid(g, p, lds, blocks, threads))) return st;
+  const uint32_t nwin = (uint32_t)g->h_lwpath.size();
+  const uint32_t runs = kXcds * kLocalStreams;
+  const ScratchCarve c = carve_scratch(nwin, runs, g->h_loc_xstride);
+  if (c.total > scratch_bytes)
+    return fail(PGSGD_ERR_RANGE, "the window tables of this graph need %zu bytes of scratch, above the %zu available",
+                c.total, scratch_bytes);
+  char* base = static_cast<char*>(scratch);
+  *W = LocalLaunch{};
+  W->L = L;
+  W->n_win = nwin;
+  W->win_shift = g->h_loc_shift;
+  W->count_blocks = (uint32_t)g->n_cu * 2;
+  W->xstride = g->h_loc_xstride;
+  W->wcount = reinterpret_cast<uint32_t*>(base + c.wcount);
+  W->woff = reinterpret_cast<uint64_t*>(base + c.woff);
+  W->xitem = reinterpret_cast<uint64_t*>(base + c.xitem);
+  W->queue = reinterpret_cast<uint64_t*>(base + c.queue);
+  W->worder = reinterpret_cast<const uint32_t*>(base + c.worder);
+  W->sbeg = reinterpret_cast<const uint32_t*>(base + c.sbeg);
+  W->wpath = reinterpret_cast<const uint32_t*>(base + c.wpath);
+  W->streams = kLocalStreams;
+  W->grab = kLocalGrab;
+  // the host tables live as long as the graph, so the copies may stay in flight
+  HIP_TRY(hipMemcpyAsync(base + c.worder, g->h_lorder.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + c.sbeg, g->h_lsbeg.data(), sizeof(uint32_t) * (runs + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + c.wpath, g->h_lwpath.data(), sizeof(uint32_t) * nwin, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_fill_u32(W->wcount, nwin, 0u, s));  // the histogram must start at zero
+  return PGSGD_OK;
+}
+
 // The layout part of a windowed iteration whose counts and offsets are in W:
 // run counters cleared, layout kernel.  With e_mid set, an event is recorded
 // right before the layout kernel.
@@ -1010,7 +1071,8 @@ struct LayoutHook {
 };
 
 pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms, float* main_ms,
-                         uint32_t* main_launches, void* stream, const LayoutHook& hook = LayoutHook()) {
+                         uint32_t* main_launches, void* stream, const LayoutHook& hook = LayoutHook(),
+                         void* scratch = nullptr, size_t scratch_bytes = 0) {
   const bool tracing = hook.trace_f != nullptr;
   const bool subset = tracing || hook.apply_mask != nullptr;
   if (!g || (!coords && !tracing)) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
@@ -1042,7 +1104,9 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   if (tracing && !windowed) return fail(PGSGD_ERR_INVALID_ARG, "recording through the layout loop needs WINDOWED");
   uint32_t blocks = 0, threads = 256;
   LocalLaunch W{};
-  if (windowed) {
+  if (windowed && scratch) {
+    if ((st = local_plan_scratch(g, p, lds, L, s, scratch, scratch_bytes, &W, &blocks, &threads))) return st;
+  } else if (windowed) {
     if ((st = local_plan(g, p, lds, L, s, &W, &blocks, &threads))) return st;
   } else {
     if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
@@ -1084,7 +1148,7 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   // order there.
   const bool ahead = (p->flags & PGSGD_FLAG_COUNT_AHEAD) ||
                      (!(p->flags & PGSGD_FLAG_COUNT_IN_ORDER) && W.L.n_terms >= kOverlapMinTerms);
-  const bool overlap = windowed && !subset && n_run > 1 && ahead;
+  const bool overlap = windowed && !subset && !scratch && n_run > 1 && ahead;
   LocalLaunch Wset[2] = {W, W};
   hipStream_t s2 = nullptr;
   bool set_used[2] = {false, false};
@@ -1148,6 +1212,44 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     }
   }
   return ok();
+}
+
+// Scratch of pgsgd_layout_noalloc: the window tables of one windowed layout
+// at a time per device (at most 4 MiB, enough for the 32,768 windows the
+// schedule allows: about 2.7 MiB).  Host code must not use the array's name
+// as a device address; noalloc_scratch gives each device's copy.
+constexpr size_t kNoAllocScratchBytes = 4u << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current.
+pgsgd_status noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(PGSGD_ERR_UNSUPPORTED, "device %d: the allocation-free entry point supports devices 0..%d", device,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[device]) {
+    DeviceGuard guard(device);
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(PGSGD_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                  hipGetErrorString(e));
+    }
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return PGSGD_OK;
 }
 
 // The data-reuse kernel in recording mode over the terms of [t_begin, t_begin
@@ -1215,6 +1317,18 @@ pgsgd_status pgsgd_sample_terms_reuse(pgsgd_graph* g, const pgsgd_params* p, uin
 
 pgsgd_status pgsgd_layout(pgsgd_graph* g, const pgsgd_params* p, float* coords, void* stream) {
   return layout_impl(g, p, coords, nullptr, nullptr, nullptr, stream);
+}
+
+pgsgd_status pgsgd_layout_noalloc(pgsgd_graph* g, const pgsgd_params* p, float* coords, void* stream) {
+  if (!g || !p) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (p->flags & PGSGD_FLAG_COUNT_AHEAD)
+    return fail(PGSGD_ERR_INVALID_ARG,
+                "pgsgd_layout_noalloc counts every iteration in order: PGSGD_FLAG_COUNT_AHEAD needs buffers it does "
+                "not allocate");
+  void* base = nullptr;
+  pgsgd_status st = noalloc_scratch(g->device, &base);
+  if (st) return st;
+  return layout_impl(g, p, coords, nullptr, nullptr, nullptr, stream, LayoutHook(), base, kNoAllocScratchBytes);
 }
 
 pgsgd_status pgsgd_layout_timed(pgsgd_graph* g, const pgsgd_params* p, float* coords, float* iter_ms,
