@@ -232,14 +232,14 @@ typedef struct {
   uint16_t step_reduction;    /* data reuse: sampled terms per iteration divided by this (SRF), 0 or 1 = off */
 } pgsgd_params;
 
-/* pgsgd_params.flags.  A WINDOWED layout over several iterations may count
+/* pgsgd_params.flags.  A WINDOWED layout over several iterations can count
  * iteration t + 1 (its window histogram and offsets, in a second set of
- * buffers) on a stream of the graph's own while iteration t is laid out;
- * by default it does so when an iteration has at least 2^31 terms.  The
- * sampled terms and, with one wave, the coordinates are the same either way.
- * PGSGD_FLAG_COUNT_AHEAD forces the overlap, PGSGD_FLAG_COUNT_IN_ORDER keeps
- * every pass on the caller's stream; setting both is INVALID_ARG.  Batched
- * layouts keep the passes in order. */
+ * buffers) on a stream of the graph's own while iteration t is laid out:
+ * PGSGD_FLAG_COUNT_AHEAD asks for that overlap; by default (and with
+ * PGSGD_FLAG_COUNT_IN_ORDER) every pass stays on the caller's stream, in
+ * order.  The sampled terms and, with one wave, the coordinates are the same
+ * either way.  Setting both flags is INVALID_ARG.  Batched layouts keep the
+ * passes in order. */
 enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
 
 /* Data-reuse variant (Section "A Case Study: Explore the Performance-Quality

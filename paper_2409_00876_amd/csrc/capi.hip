@@ -858,10 +858,6 @@ pgsgd_status ensure_count_stream(pgsgd_graph* g) {
   return PGSGD_OK;
 }
 
-// Iterations with at least this many terms count the next iteration on a
-// second stream (layout_impl).
-constexpr uint64_t kOverlapMinTerms = 1ull << 31;
-
 // Segments of the window-major sampled path stress: the windows of the
 // windowed schedule cut at path boundaries, in step order; run x (XCD x)
 // holds the segments starting in the x-th eighth of the steps.
@@ -1139,15 +1135,14 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
     }
   } events_free{ev};
   if (!tracing) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
-  // Windowed layouts of several iterations of at least kOverlapMinTerms
-  // terms count iteration it + 1 on the graph's counting stream while
-  // iteration it is laid out, alternating between two count/offset sets: a
-  // set is rewritten only after the layout that read it (two iterations
-  // earlier) has finished.  On smaller graphs the counting blocks slow the
-  // short layout launches down more than they save, so the passes stay in
-  // order there.
-  const bool ahead = (p->flags & PGSGD_FLAG_COUNT_AHEAD) ||
-                     (!(p->flags & PGSGD_FLAG_COUNT_IN_ORDER) && W.L.n_terms >= kOverlapMinTerms);
+  // With PGSGD_FLAG_COUNT_AHEAD a windowed layout of several iterations
+  // counts iteration it + 1 on the graph's counting stream while iteration it
+  // is laid out, alternating between two count/offset sets: a set is
+  // rewritten only after the layout that read it (two iterations earlier) has
+  // finished.  By default the passes stay in order: measured on MI355X the
+  // overlap saved nothing on the chromosome graph and made a mid-size graph's
+  // layout 74% slower.
+  const bool ahead = (p->flags & PGSGD_FLAG_COUNT_AHEAD) != 0;
   const bool overlap = windowed && !subset && !scratch && n_run > 1 && ahead;
   LocalLaunch Wset[2] = {W, W};
   hipStream_t s2 = nullptr;

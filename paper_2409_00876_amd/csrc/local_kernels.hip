@@ -302,10 +302,7 @@ __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
   const uint32_t lane = threadIdx.x & 63u;
   for (uint32_t x = blockIdx.x % nx; x < kXcds; x += nx)
   for (uint32_t h = 0; h < P.streams; ++h) {
-    // wave-uniform run: its metadata then comes through the scalar cache, and
-    // no vector-memory wait (which would also wait for the wave's in-flight
-    // far loads) is spent on it
-    const uint32_t run = uniform_u32(x * P.streams + (v + h) % P.streams);
+    const uint32_t run = x * P.streams + (v + h) % P.streams;
     const uint32_t wb = uniform_u32(uload(P.sbeg + run));
     const uint32_t nq = uniform_u32(uload(P.sbeg + run + 1)) - wb;
     const uint64_t* __restrict__ xi = P.xitem + (size_t)run * P.xstride;
