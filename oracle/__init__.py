@@ -88,6 +88,7 @@ def _load():
         "or_stress_loss_grad": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
         "or_loss_segment_counts": ([P, u64, u64, u32, u32, P, u64, P], None),
         "or_sps_outliers": ([P, P, u32, u64, u32, u32, f64, u32, f64, u64, P, P, P, P], u64),
+        "or_sps_compare": ([P, P, P, u32, u64, u32, u32, f64, u32, P, P], None),
         "or_loss_windowed_pairs": ([P, u64, f64, u32, u64, u32, u32, u64, u64, P, P, P], None),
         "or_stress_loss_grad_windowed": ([P, P, u64, f64, u32, u64, u32, u32, P, P], None),
     }
@@ -448,3 +449,17 @@ def sps_outliers(g: Graph, coords: np.ndarray, m: int, threshold: float, max_out
                                     _p(s)))
     k = min(n, max_out)
     return n, i[:k], j[:k], e[:k], s[:k]
+
+
+def sps_compare(g: Graph, coords_a: np.ndarray, coords_b: np.ndarray, m: int = 10, seed: int = 7, graph_id: int = 0,
+                pairs: str = "uniform", theta=0.99, window=1000) -> dict:
+    """Two layouts on the same pairs of Eq. 2: means, the ratio of the sums
+    with its delta-method CI95, and the spreads (see oracle.c)."""
+    a = np.ascontiguousarray(coords_a, dtype=np.float32)
+    b = np.ascontiguousarray(coords_b, dtype=np.float32)
+    out = np.zeros(10, dtype=np.float64)
+    cnt = np.zeros(2, dtype=np.uint64)
+    _load().or_sps_compare(g._h, _p(a), _p(b), int(m), int(seed), int(graph_id), PAIR_MODES[pairs], float(theta),
+                           int(window), _p(out), _p(cnt))
+    keys = ("mean_a", "mean_b", "ratio", "ratio_ci_lo", "ratio_ci_hi", "sd_a", "sd_b", "sd_diff", "sum_a", "sum_b")
+    return {**dict(zip(keys, out.tolist())), "n_valid": int(cnt[0]), "n_skipped": int(cnt[1])}

@@ -1464,3 +1464,80 @@ uint64_t or_sps_outliers(const or_graph *g, const float *coords, uint32_t m, uin
   if (sp.zipf) free((void *)sp.zipf);
   return n_out;
 }
+
+/* ---------------------------------------------------------------------------
+ * Two layouts compared on the same pairs of Eq. 2 (a paired estimate): for
+ * every valid pair the stress s_a in layout a and s_b in layout b.  Pass 1
+ * gives the means; pass 2 the spreads and sum (s_a - R s_b)^2 with R =
+ * sum s_a / sum s_b.  The ratio's 95% interval is the delta-method one,
+ * R +- 1.96 sqrt(sum (s_a - R s_b)^2 / (n - 1)) / (sqrt(n) mean_b).
+ * out: mean_a, mean_b, R, R_lo, R_hi, sd_a, sd_b, sd of s_a - R s_b, sum_a,
+ * sum_b; counts: n_valid, n_skipped.  Modes as or_sps_outliers.
+ * ------------------------------------------------------------------------- */
+void or_sps_compare(const or_graph *g, const float *coords_a, const float *coords_b, uint32_t m, uint64_t seed,
+                    uint32_t graph_id, uint32_t mode, double theta, uint32_t W, double *out, uint64_t *counts) {
+  sampler sp;
+  sp.zipf = NULL;
+  if (mode == 1) make_sampler(&sp, 1, theta, W, seed, graph_id);
+  uint64_t n_seg = 0, *start = NULL, *cnt = NULL;
+  uint32_t *path = NULL;
+  if (mode == 2) {
+    n_seg = or_sps_segments(g, NULL, NULL);
+    start = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+    path = (uint32_t *)malloc(sizeof(uint32_t) * (n_seg + 1));
+    cnt = (uint64_t *)malloc(sizeof(uint64_t) * (n_seg + 1));
+    or_sps_segments(g, start, path);
+    or_sps_segment_counts(g, m, seed, graph_id, start, n_seg, cnt);
+  }
+  double sa = 0.0, sb = 0.0, da = 0.0, db = 0.0, dr = 0.0, ma = 0.0, mb = 0.0, R = 0.0;
+  uint64_t n = 0, skipped = 0;
+  for (int pass = 1; pass <= 2; ++pass) {
+    uint64_t u = 0;
+    uint32_t p = 0;
+    uint64_t q = 0, seg = 0, k = 0;
+    for (;;) {  /* the pairs of the mode, in enumeration order */
+      uint64_t i, j; uint32_t ei, ej; int valid = 1;
+      if (mode == 2) {
+        while (seg < n_seg && k >= cnt[seg]) { ++seg; k = 0; }
+        if (seg >= n_seg) break;
+        sps_slot(g, seed, graph_id, start[seg], start[seg + 1] - start[seg], path[seg], u, &i, &j, &ei, &ej);
+        ++u; ++k;
+      } else {
+        while (p < g->n_paths && q >= (uint64_t)m * g->path_off[p + 1]) ++p;
+        if (p >= g->n_paths) break;
+        if (q < (uint64_t)m * g->path_off[p]) q = (uint64_t)m * g->path_off[p];
+        if (mode == 1) sps_pair_power_law(g, &sp, p, q, &i, &j, &ei, &ej, &valid);
+        else sps_pair(g, seed, graph_id, p, q, &i, &j, &ei, &ej);
+        ++q;
+      }
+      int va = valid, vb = valid;
+      double s_a = va ? pair_stress(g, coords_a, i, j, ei, ej, &va) : 0.0;
+      double s_b = vb ? pair_stress(g, coords_b, i, j, ei, ej, &vb) : 0.0;
+      if (!va) {
+        if (pass == 1) ++skipped;
+        continue;
+      }
+      if (pass == 1) {
+        sa += s_a; sb += s_b; ++n;
+      } else {
+        da += (s_a - ma) * (s_a - ma);
+        db += (s_b - mb) * (s_b - mb);
+        dr += (s_a - R * s_b) * (s_a - R * s_b);
+      }
+    }
+    if (pass == 1) {
+      ma = n ? sa / (double)n : 0.0;
+      mb = n ? sb / (double)n : 0.0;
+      R = sb > 0.0 ? sa / sb : 0.0;
+    }
+  }
+  if (start) { free(start); free(path); free(cnt); }
+  if (sp.zipf) free((void *)sp.zipf);
+  double sdr = n > 1 ? sqrt(dr / (double)(n - 1)) : 0.0;
+  double half = (n && mb > 0.0) ? 1.96 * sdr / (sqrt((double)n) * mb) : 0.0;
+  out[0] = ma; out[1] = mb; out[2] = R; out[3] = R - half; out[4] = R + half;
+  out[5] = n > 1 ? sqrt(da / (double)(n - 1)) : 0.0;
+  out[6] = n > 1 ? sqrt(db / (double)(n - 1)) : 0.0;
+  out[7] = sdr; out[8] = sa; out[9] = sb;
+  counts[0] = n; counts[1] = skipped;
+}

@@ -1024,3 +1024,28 @@ def test_sps_outliers_list_the_pairs_of_eq2(tiny_oracle, pairs):
     assert n2 == int(keep.sum()) and np.array_equal(st2, st[keep]) and np.array_equal(i2, i[keep])
     n3, *_ = O.sps_outliers(g, c, 5, thr, max_out=3, seed=7, pairs=pairs)
     assert n3 == n2
+
+
+@pytest.mark.parametrize("pairs", ["uniform", "power_law", "uniform_windowed"])
+def test_sps_compare_pins(tiny_oracle, pairs):
+    # a layout against itself: ratio exactly 1 with a zero-width interval, both means the estimator's
+    g = tiny_oracle
+    c = O.init_coords(g)
+    O.layout(g, c, first_iter=0, last_iter=8)
+    s = O.sampled_path_stress(g, c, m=5, seed=7, pairs=pairs)
+    r = O.sps_compare(g, c, c, m=5, seed=7, pairs=pairs)
+    assert r["n_valid"] == s["n_valid"] and r["n_skipped"] == s["n_skipped"]
+    assert r["mean_a"] == r["mean_b"] and abs(r["mean_a"] - s["mean"]) <= 1e-12 * s["mean"]
+    assert r["ratio"] == 1.0 and r["ratio_ci_lo"] == 1.0 and r["ratio_ci_hi"] == 1.0
+    assert abs(r["sd_a"] - s["stddev"]) <= 1e-9 * s["stddev"]
+
+
+@pytest.mark.parametrize("pairs", ["uniform", "uniform_windowed"])
+def test_sps_compare_on_scaled_lines_is_closed_form(pairs):
+    # per-path lines scaled by lam and by mu: every pair's stress is (lam - 1)^2 and (mu - 1)^2
+    g, c = _disjoint_paths_fixed_point()
+    lam, mu = 2.0, 0.5
+    r = O.sps_compare(g, c * np.float32(lam), c * np.float32(mu), m=7, pairs=pairs)
+    assert abs(r["mean_a"] - (lam - 1) ** 2) < 1e-12 and abs(r["mean_b"] - (mu - 1) ** 2) < 1e-12
+    assert abs(r["ratio"] - (lam - 1) ** 2 / (mu - 1) ** 2) < 1e-12
+    assert r["sd_diff"] < 1e-9 and r["ratio_ci_hi"] - r["ratio_ci_lo"] < 1e-9
