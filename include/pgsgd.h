@@ -476,6 +476,28 @@ pgsgd_status pgsgd_path_stress_outliers(pgsgd_graph *g, const float *coords, uin
                                         void *stream);
 
 /*
+ * Two layouts of one graph on the same pairs of Eq. 2 (a paired estimate):
+ * every valid pair's stress s_a in coords_a and s_b in coords_b, the means,
+ * the ratio R = sum s_a / sum s_b and its 95% interval by the delta method,
+ * R +- 1.96 sd(s_a - R s_b) / (sqrt(n) mean_b).  When a few pairs carry much
+ * of the estimate in both layouts, the paired interval is far narrower than
+ * the two separate ones.  Pairs and modes as pgsgd_path_stress_pairs.  A
+ * second working copy of the coordinates (16 B per node) is allocated on
+ * first use.  Synchronises the stream.  Errors: those of
+ * pgsgd_path_stress_pairs, INVALID_ARG for NULL or misaligned coords_b.
+ */
+typedef struct {
+  double mean_a, mean_b, ratio, ratio_ci_lo, ratio_ci_hi;
+  double sd_a, sd_b, sd_diff;  /* spreads of s_a, s_b and s_a - R s_b */
+  double sum_a, sum_b;
+  uint64_t n_valid, n_skipped;
+} pgsgd_stress_compare_result;
+pgsgd_status pgsgd_path_stress_compare(pgsgd_graph *g, const float *coords_a, const float *coords_b,
+                                       uint32_t pairs_per_step, uint64_t seed, uint32_t graph_id, uint32_t pair_mode,
+                                       double zipf_theta, uint32_t zipf_window, pgsgd_stress_compare_result *out,
+                                       void *stream);
+
+/*
  * Path stress, Eq. 1 (Section "Path Stress"): over every path and every pair of
  * its steps i < j, the stress averaged over the endpoint combinations with
  * d > 0 (a pair with none is left out), then the mean over all such pairs.

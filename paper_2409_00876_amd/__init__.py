@@ -19,10 +19,10 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (GfaView, FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
+from ._lib import (CompareResult, GfaView, FLAG_COUNT_AHEAD, FLAG_COUNT_IN_ORDER, SCHEDULE_AUTO, SCHEDULE_WINDOWED, GraphInfo, Params, PgsgdError, StressResult, Tune,  # noqa: F401
                    check, lib)
 
-__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "path_order", "LayoutParams", "layout", "layout_noalloc", "layout_timed", "init_coords", "path_stress", "path_stress_outliers", "path_stress_exact", "schedule", "zipf_table",
+__all__ = ["Graph", "GfaGraph", "read_gfa", "parse_gfa", "path_order", "LayoutParams", "layout", "layout_noalloc", "layout_timed", "init_coords", "path_stress", "path_stress_compare", "path_stress_outliers", "path_stress_exact", "schedule", "zipf_table",
            "sample_terms", "sample_terms_reuse", "apply_terms", "apply_slots", "stress_forward", "stress_backward", "SampledPathStress", "adam_step",
            "Batch", "layout_batched", "batch_sample_terms", "autotune", "PgsgdError"]
 
@@ -306,6 +306,22 @@ def path_stress(g: Graph, coords, pairs_per_step: int = 100, seed: int = 7, grap
                                         int(seed), int(graph_id), modes[pairs], float(zipf_theta), int(zipf_window),
                                         ctypes.byref(r), _stream(torch, coords.device)))
     return {f[0]: getattr(r, f[0]) for f in StressResult._fields_}
+
+
+def path_stress_compare(g: Graph, coords_a, coords_b, pairs_per_step: int = 10, seed: int = 7, graph_id: int = 0,
+                        pairs: str = "uniform", zipf_theta: float = 0.99, zipf_window: int = 1000) -> dict:
+    """Two layouts on the same pairs of Eq. 2: means, the ratio of the sums
+    with its paired (delta-method) CI95; synchronises the current stream."""
+    import torch
+    _check_tensor(coords_a, torch.float32, 4 * g.n_nodes, "coords_a")
+    _check_tensor(coords_b, torch.float32, 4 * g.n_nodes, "coords_b")
+    modes = {"uniform": 0, "power_law": 1, "uniform_windowed": 2}
+    r = CompareResult()
+    check(lib().pgsgd_path_stress_compare(g.handle, ctypes.c_void_p(coords_a.data_ptr()),
+                                          ctypes.c_void_p(coords_b.data_ptr()), int(pairs_per_step), int(seed),
+                                          int(graph_id), modes[pairs], float(zipf_theta), int(zipf_window),
+                                          ctypes.byref(r), _stream(torch, coords_a.device)))
+    return {f[0]: getattr(r, f[0]) for f in CompareResult._fields_}
 
 
 def path_stress_outliers(g: Graph, coords, pairs_per_step: int, threshold: float, max_out: int = 1 << 20,

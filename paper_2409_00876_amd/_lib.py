@@ -77,6 +77,12 @@ class StressResult(ctypes.Structure):
     ]
 
 
+class CompareResult(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("mean_a", "mean_b", "ratio", "ratio_ci_lo", "ratio_ci_hi", "sd_a",
+                                                "sd_b", "sd_diff", "sum_a", "sum_b")] + \
+               [("n_valid", ctypes.c_uint64), ("n_skipped", ctypes.c_uint64)]
+
+
 class Tune(ctypes.Structure):
     _fields_ = [
         ("block_threads", ctypes.c_uint32),
@@ -132,6 +138,7 @@ SIGNATURES = {
     "pgsgd_path_stress_pairs": ([_P, _P, _u32, _u64, _u32, _u32, ctypes.c_double, _u32, _P, _P], _i32),
     "pgsgd_path_stress_outliers": ([_P, _P, _u32, _u64, _u32, _u32, _f64, _u32, _f64, _u64, _P, _P, _P, _P, _P, _P,
                                     _P], _i32),
+    "pgsgd_path_stress_compare": ([_P, _P, _P, _u32, _u64, _u32, _u32, _f64, _u32, _P, _P], _i32),
     "pgsgd_path_stress_exact": ([_P, _P, _P, _P, _P], _i32),
     "pgsgd_stress_forward": ([_P, _P, _P, _u64, _u32, _P, _P, _P], _i32),
     "pgsgd_stress_backward": ([_P, _P, _P, _u64, _u32, _P, _P, _P, _P], _i32),

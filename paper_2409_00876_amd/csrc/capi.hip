@@ -161,9 +161,10 @@ struct pgsgd_graph {
   double* d_part_f = nullptr;
   uint64_t* d_part_n = nullptr;
   uint64_t* d_part_skip = nullptr;
-  double* d_out_f = nullptr;    // [4]
+  double* d_out_f = nullptr;    // [8]
   uint64_t* d_out_n = nullptr;  // [4]
-  double* d_mean = nullptr;
+  double* d_mean = nullptr;     // [4]
+  float2* d_work2 = nullptr;    // a second layout's working copy (pgsgd_path_stress_compare, on first use)
   size_t device_bytes = 0;
   std::unordered_map<void*, size_t> alloc_bytes;  // size of every lazily allocated buffer
   int layout_blocks_per_cu = 0;  // occupancy of k_layout_iter, filled on first use
@@ -203,7 +204,7 @@ struct pgsgd_graph {
     DeviceGuard g(device);
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_inv, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
-                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
+                    (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_work2, (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
                     (void*)d_lsbeg, (void*)d_lwpath, (void*)d_sseg_start, (void*)d_sseg_path, (void*)d_swseg,
                     (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue,
                     (void*)d_lcount2, (void*)d_loff2, (void*)d_lxitem2, (void*)d_lqueue2})
@@ -529,7 +530,7 @@ pgsgd_status pgsgd_graph_create_ex(uint32_t n_nodes, const uint32_t* node_len, u
   }
   // the buffers allocated below, checked against PGSGD_MAX_DEVICE_BYTES before any device work
   const uint64_t need = 16ull * std::max<uint64_t>(S, 1) + 8ull * (n_paths + 1) + 8ull * std::max(n_nodes, 1u) +
-                        16ull * std::max(n_nodes, 1u) + 24ull * kStressBlocks + 4 * 8 + 4 * 8 + 8 + 4ull * 65536 +
+                        16ull * std::max(n_nodes, 1u) + 40ull * kStressBlocks + 8 * 8 + 4 * 8 + 4 * 8 + 4ull * 65536 +
                         2ull * (kGuideSize + 1) + (perm.empty() ? 0 : 4ull * n_nodes);
   const uint64_t cap = device_byte_cap();
   if (cap && need > cap)
@@ -570,12 +571,12 @@ pgsgd_status pgsgd_graph_create_ex(uint32_t n_nodes, const uint32_t* node_len, u
   if ((st = dev_alloc(g, &g->d_path_off, n_paths + 1))) return bail(st);
   if ((st = dev_alloc(g, &g->d_first, n_nodes))) return bail(st);
   if ((st = dev_alloc(g, &g->d_work, 2ull * n_nodes))) return bail(st);
-  if ((st = dev_alloc(g, &g->d_part_f, kStressBlocks))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_part_f, 3 * kStressBlocks))) return bail(st);
   if ((st = dev_alloc(g, &g->d_part_n, kStressBlocks))) return bail(st);
   if ((st = dev_alloc(g, &g->d_part_skip, kStressBlocks))) return bail(st);
-  if ((st = dev_alloc(g, &g->d_out_f, 4))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_out_f, 8))) return bail(st);
   if ((st = dev_alloc(g, &g->d_out_n, 4))) return bail(st);
-  if ((st = dev_alloc(g, &g->d_mean, 1))) return bail(st);
+  if ((st = dev_alloc(g, &g->d_mean, 4))) return bail(st);
   if ((st = dev_alloc(g, &g->d_zipf, 65536))) return bail(st);
   if ((st = dev_alloc(g, &g->d_guide, kGuideSize + 1))) return bail(st);
   if (!perm.empty() && (st = dev_alloc(g, &g->d_inv, n_nodes))) return bail(st);
@@ -1480,7 +1481,8 @@ struct OutlierSink {
 
 pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
                               uint32_t pair_mode, double zipf_theta, uint32_t zipf_window, pgsgd_stress_result* out,
-                              void* stream, const OutlierSink* sink);
+                              void* stream, const OutlierSink* sink, const float* coords_b = nullptr,
+                              pgsgd_stress_compare_result* cmp = nullptr);
 
 }  // namespace
 
@@ -1488,6 +1490,17 @@ pgsgd_status pgsgd_path_stress_pairs(pgsgd_graph* g, const float* coords, uint32
                                      uint32_t graph_id, uint32_t pair_mode, double zipf_theta, uint32_t zipf_window,
                                      pgsgd_stress_result* out, void* stream) {
   return path_stress_impl(g, coords, m, seed, graph_id, pair_mode, zipf_theta, zipf_window, out, stream, nullptr);
+}
+
+pgsgd_status pgsgd_path_stress_compare(pgsgd_graph* g, const float* coords_a, const float* coords_b, uint32_t m,
+                                       uint64_t seed, uint32_t graph_id, uint32_t pair_mode, double zipf_theta,
+                                       uint32_t zipf_window, pgsgd_stress_compare_result* out, void* stream) {
+  if (!coords_b || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
+  if (g && ((uintptr_t)coords_b & 15u) != 0) return fail(PGSGD_ERR_INVALID_ARG, "coords must be 16-byte aligned");
+  std::memset(out, 0, sizeof(*out));
+  pgsgd_stress_result tmp;
+  return path_stress_impl(g, coords_a, m, seed, graph_id, pair_mode, zipf_theta, zipf_window, &tmp, stream, nullptr,
+                          coords_b, out);
 }
 
 pgsgd_status pgsgd_path_stress_outliers(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed,
@@ -1515,7 +1528,8 @@ namespace {
 
 pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, uint64_t seed, uint32_t graph_id,
                               uint32_t pair_mode, double zipf_theta, uint32_t zipf_window, pgsgd_stress_result* out,
-                              void* stream, const OutlierSink* sink) {
+                              void* stream, const OutlierSink* sink, const float* coords_b,
+                              pgsgd_stress_compare_result* cmp) {
   if (!g || !coords || !out) return fail(PGSGD_ERR_INVALID_ARG, "NULL argument");
   if (sink) *sink->n_host = 0;
   if (pair_mode > PGSGD_PAIRS_UNIFORM_WINDOWED) return fail(PGSGD_ERR_INVALID_ARG, "unknown pair mode %u", pair_mode);
@@ -1555,7 +1569,16 @@ pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, u
     P.out_s = sink->s;
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(P.out_count), 2, 0u, s));
   }
-  if (mode == PGSGD_PAIRS_UNIFORM_WINDOWED) {
+  if (coords_b) {  // the second layout of a paired evaluation
+    if (!g->d_work2) {
+      pgsgd_status st = dev_alloc(g, &g->d_work2, 2ull * g->n_nodes);
+      if (st) return st;
+    }
+    P.work2 = g->d_work2;
+  }
+  SpsWinLaunch W{};
+  const bool windowed = mode == PGSGD_PAIRS_UNIFORM_WINDOWED;
+  if (windowed) {
     pgsgd_status st = ensure_sps_windowed(g, s);
     if (st) return st;
     if ((size_t)g->path_slots * 8 + (size_t)g->sps_nseg * 4 > g->lds_limit)
@@ -1563,23 +1586,43 @@ pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, u
                   g->sps_nseg, g->lds_limit);
     if (((uint64_t)m << (g->sps_shift + 1)) >= (1ull << 32))
       return fail(PGSGD_ERR_UNSUPPORTED, "pairs_per_step %u too large for 32-bit segment counts", m);
-    const SpsWinLaunch W = sps_win_launch(g, P, kStreamSpsSlot, graph_id, 0);
-    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
-    HIP_TRY(launch_sps_win_count_scan(W, s));
-    HIP_TRY(launch_sps_win_pass(W, 1, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, s));
-    HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
-                                g->d_mean, nullptr, nullptr, s));
-    HIP_TRY(launch_sps_win_pass(W, 2, g->d_mean, g->d_part_f, nullptr, nullptr, kStressBlocks, s));
-  } else {
-    HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
-    HIP_TRY(launch_sps_pass(P, 1, mode, nullptr, g->d_part_f, g->d_part_n, g->d_part_skip, s));
-    HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
-                                g->d_mean, nullptr, nullptr, s));
-    HIP_TRY(launch_sps_pass(P, 2, mode, g->d_mean, g->d_part_f, nullptr, nullptr, s));
+    W = sps_win_launch(g, P, kStreamSpsSlot, graph_id, 0);
   }
-  HIP_TRY(launch_reduce_parts(g->d_part_f, nullptr, nullptr, kStressBlocks, g->d_out_f + 1, nullptr, nullptr,
-                              nullptr, nullptr, s));
-  double f[2];
+  auto pass = [&](int k, const double* mean_dev, uint64_t* part_n, uint64_t* part_skip) -> hipError_t {
+    return windowed ? launch_sps_win_pass(W, k, mean_dev, g->d_part_f, part_n, part_skip, kStressBlocks, s)
+                    : launch_sps_pass(P, k, mode, mean_dev, g->d_part_f, part_n, part_skip, s);
+  };
+  auto reduce = [&](uint32_t part, double* out_f) -> hipError_t {  // sum of one of the three partial arrays
+    return launch_reduce_parts(g->d_part_f + (size_t)part * kStressBlocks, nullptr, nullptr, kStressBlocks, out_f,
+                               nullptr, nullptr, nullptr, nullptr, s);
+  };
+  HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
+  if (coords_b) HIP_TRY(launch_to_work(coords_b, g->d_work2, g->n_nodes, g->d_inv, s));
+  if (windowed) HIP_TRY(launch_sps_win_count_scan(W, s));
+  HIP_TRY(pass(1, nullptr, g->d_part_n, g->d_part_skip));
+  HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, g->d_part_skip, kStressBlocks, g->d_out_f, g->d_out_n,
+                              g->d_mean, nullptr, nullptr, s));
+  double sum_b = 0.0;
+  if (coords_b) {  // pass 2 needs both means and the ratio: one round trip
+    HIP_TRY(reduce(1, g->d_out_f + 2));
+    double f0[3];
+    uint64_t n0;
+    HIP_TRY(hipMemcpyAsync(f0, g->d_out_f, sizeof(f0), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&n0, g->d_out_n, sizeof(n0), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    sum_b = f0[2];
+    const double mean3[3] = {n0 ? f0[0] / (double)n0 : 0.0, n0 ? sum_b / (double)n0 : 0.0,
+                             sum_b > 0.0 ? f0[0] / sum_b : 0.0};
+    HIP_TRY(hipMemcpyAsync(g->d_mean, mean3, sizeof(mean3), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // mean3 lives on this stack frame
+  }
+  HIP_TRY(pass(2, g->d_mean, nullptr, nullptr));
+  HIP_TRY(reduce(0, g->d_out_f + 1));
+  if (coords_b) {
+    HIP_TRY(reduce(1, g->d_out_f + 3));
+    HIP_TRY(reduce(2, g->d_out_f + 4));
+  }
+  double f[5];
   uint64_t n[2];
   HIP_TRY(hipMemcpyAsync(f, g->d_out_f, sizeof(f), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(n, g->d_out_n, sizeof(n), hipMemcpyDeviceToHost, s));
@@ -1593,6 +1636,22 @@ pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, u
   const double half = n[0] ? 1.96 * out->stddev / std::sqrt((double)n[0]) : 0.0;
   out->ci_lo = out->mean - half;
   out->ci_hi = out->mean + half;
+  if (cmp) {
+    const uint64_t nv = n[0];
+    cmp->mean_a = out->mean;
+    cmp->mean_b = nv ? sum_b / (double)nv : 0.0;
+    cmp->ratio = sum_b > 0.0 ? f[0] / sum_b : 0.0;
+    cmp->sd_a = out->stddev;
+    cmp->sd_b = nv > 1 ? std::sqrt(f[3] / (double)(nv - 1)) : 0.0;
+    cmp->sd_diff = nv > 1 ? std::sqrt(f[4] / (double)(nv - 1)) : 0.0;
+    const double h = (nv && cmp->mean_b > 0.0) ? 1.96 * cmp->sd_diff / (std::sqrt((double)nv) * cmp->mean_b) : 0.0;
+    cmp->ratio_ci_lo = cmp->ratio - h;
+    cmp->ratio_ci_hi = cmp->ratio + h;
+    cmp->sum_a = f[0];
+    cmp->sum_b = sum_b;
+    cmp->n_valid = nv;
+    cmp->n_skipped = n[1];
+  }
   if (sink) {
     HIP_TRY(hipMemcpy(sink->n_host, P.out_count, sizeof(uint64_t), hipMemcpyDeviceToHost));
   }

@@ -17,6 +17,7 @@ struct StressLaunch {
   const float* coords;
   const float2* work;      // interleaved copy of coords (sampled path stress only)
   const uint32_t* inv;     // renumbered graph: caller id of every device node id (else NULL)
+  const float2* work2;     // a second layout's interleaved copy: the SPS passes evaluate it on the same pairs
   const uint64_t* path_off;
   const uint32_t* zipf;
   const uint16_t* guide;

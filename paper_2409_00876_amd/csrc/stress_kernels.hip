@@ -88,6 +88,44 @@ __device__ __forceinline__ void keep_outlier(const StressLaunch& P, uint64_t i, 
   }
 }
 
+// A second layout (P.work2) on the same pair: pass 1 sums its stress into acc2;
+// pass 2 (mean_dev = mean_a, mean_b, R) sums (s_b - mean_b)^2 into acc2 and
+// (s_a - R s_b)^2 into acc3.
+__device__ __forceinline__ void paired_terms(const StressLaunch& P, int pass, const double* mean_dev, uint64_t a,
+                                             uint64_t b, double d, double st, double& acc2, double& acc3) {
+#pragma clang fp contract(off)
+  const double sb = stress_work(P.work2, a, b, d);
+  if (pass == 1) {
+    acc2 += sb;
+  } else {
+    acc2 += (sb - mean_dev[1]) * (sb - mean_dev[1]);
+    acc3 += (st - mean_dev[2] * sb) * (st - mean_dev[2] * sb);
+  }
+}
+
+// Per-block partial sums: part_f[blockIdx.x] = acc, and for a paired
+// evaluation part_f[gridDim.x + blockIdx.x] = acc2, part_f[2 gridDim.x + blockIdx.x] = acc3.
+__device__ __forceinline__ void write_parts(const StressLaunch& P, double acc, double acc2, double acc3, uint64_t nv,
+                                            uint64_t ns, double* red_f, uint64_t* red_n, double* part_f,
+                                            uint64_t* part_n, uint64_t* part_skip) {
+  acc = block_sum(acc, red_f);
+  if (P.work2) {
+    acc2 = block_sum(acc2, red_f);
+    acc3 = block_sum(acc3, red_f);
+  }
+  nv = block_sum(nv, red_n);
+  ns = block_sum(ns, red_n);
+  if (threadIdx.x == 0) {
+    part_f[blockIdx.x] = acc;
+    if (P.work2) {
+      part_f[gridDim.x + blockIdx.x] = acc2;
+      part_f[2 * gridDim.x + blockIdx.x] = acc3;
+    }
+    if (part_n) part_n[blockIdx.x] = nv;
+    if (part_skip) part_skip[blockIdx.x] = ns;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sampled path stress: thread-strided over steps s; step s owns pairs
 // q = m*s .. m*s+m-1, which all belong to the path of s.
@@ -117,7 +155,7 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, int mode,
   }
   __syncthreads();
   const double mean = pass == 2 ? mean_dev[0] : 0.0;
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0, acc3 = 0.0;
   uint64_t nv = 0, ns = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < P.S; s += stride) {
@@ -151,16 +189,10 @@ __global__ __launch_bounds__(256) void k_sps(StressLaunch P, int pass, int mode,
 #pragma clang fp contract(off)
         acc += (st - mean) * (st - mean);
       }
+      if (P.work2) paired_terms(P, pass, mean_dev, a, b, d, st, acc2, acc3);
     }
   }
-  acc = block_sum(acc, red_f);
-  nv = block_sum(nv, red_n);
-  ns = block_sum(ns, red_n);
-  if (threadIdx.x == 0) {
-    part_f[blockIdx.x] = acc;
-    if (part_n) part_n[blockIdx.x] = nv;
-    if (part_skip) part_skip[blockIdx.x] = ns;
-  }
+  write_parts(P, acc, acc2, acc3, nv, ns, red_f, red_n, part_f, part_n, part_skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +332,7 @@ __global__ __launch_bounds__(256) void k_sps_win(SpsWinLaunch W, int pass, const
   const uint64_t* __restrict__ xi = W.xitem + (size_t)x * W.xstride;
   const uint64_t n_items = uniform_u64(uload(xi + nq));
   unsigned long long* ctr = reinterpret_cast<unsigned long long*>(W.queue + ((size_t)(pass - 1) * kXcds + x) * 16);
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0, acc3 = 0.0;
   uint64_t nv = 0, ns = 0;
   uint32_t q = 0;
   for (uint64_t m = 0, m_end = 0;; ++m) {
@@ -339,17 +371,11 @@ __global__ __launch_bounds__(256) void k_sps_win(SpsWinLaunch W, int pass, const
 #pragma clang fp contract(off)
           acc += (st - mean) * (st - mean);
         }
+        if (P.work2) paired_terms(P, pass, mean_dev, a, b, d, st, acc2, acc3);
       }
     }
   }
-  acc = block_sum(acc, red_f);
-  nv = block_sum(nv, red_n);
-  ns = block_sum(ns, red_n);
-  if (threadIdx.x == 0) {
-    part_f[blockIdx.x] = acc;
-    if (part_n) part_n[blockIdx.x] = nv;
-    if (part_skip) part_skip[blockIdx.x] = ns;
-  }
+  write_parts(P, acc, acc2, acc3, nv, ns, red_f, red_n, part_f, part_n, part_skip);
 }
 
 // ---------------------------------------------------------------------------

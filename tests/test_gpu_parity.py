@@ -998,3 +998,22 @@ def test_batch_rejects_the_data_reuse_variant(P, small_batch):
     for kw in ({"reuse_factor": 2}, {"step_reduction": 2}):
         with pytest.raises(P.PgsgdError):
             P.Batch(gs, cs, **kw)
+
+
+@pytest.mark.parametrize("pairs", ["uniform", "power_law", "uniform_windowed"])
+def test_sps_compare_equals_oracle(P, tiny, pairs):
+    """Two layouts on the same pairs: means, ratio and spreads as the oracle's
+    paired evaluation (sums of FP64 terms in another order: 1e-9)."""
+    import torch
+    sg, og, g = tiny
+    ca = O.init_coords(og)
+    O.layout(og, ca, first_iter=0, last_iter=8)
+    cb = ca.copy()
+    O.layout(og, cb, first_iter=8, last_iter=30)
+    ref = O.sps_compare(og, ca, cb, m=10, seed=7, pairs=pairs)
+    r = P.path_stress_compare(g, torch.from_numpy(ca).cuda(), torch.from_numpy(cb).cuda(), 10, 7, pairs=pairs)
+    assert r["n_valid"] == ref["n_valid"] and r["n_skipped"] == ref["n_skipped"]
+    for k in ("sum_a", "sum_b", "ratio", "ratio_ci_lo", "ratio_ci_hi", "sd_a", "sd_b", "sd_diff"):
+        assert abs(r[k] - ref[k]) <= 1e-9 * abs(ref[k]), k
+    same = P.path_stress_compare(g, torch.from_numpy(ca).cuda(), torch.from_numpy(ca).cuda(), 10, 7, pairs=pairs)
+    assert same["ratio"] == 1.0 and same["sd_diff"] == 0.0
