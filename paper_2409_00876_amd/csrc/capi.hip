@@ -1831,6 +1831,10 @@ std::vector<std::vector<uint32_t>> assign_branches(pgsgd_graph* const* graphs, u
     out[j].push_back(k);
     load[j] += graphs[k]->S;
   }
+  // odd branches run their graphs smallest first, so large graphs (whose
+  // wave caps fill much of the GPU) tend to run beside small ones rather than
+  // beside each other
+  for (uint32_t j = 1; j < nb; j += 2) std::reverse(out[j].begin(), out[j].end());
   return out;
 }
 
@@ -2242,18 +2246,21 @@ pgsgd_status autotune_windowed(pgsgd_graph* const* graphs, uint32_t n, const pgs
   }
   // the caller's coordinates are loaded into the working copies and never written back
   for (uint32_t k = 0; k < n && !e; ++k) e = launch_to_work(coords[k], graphs[k]->d_work, graphs[k]->n_nodes, graphs[k]->d_inv, s);
+  // one iteration with uniform partners and one cooling iteration (their costs differ by almost 2x)
+  const uint32_t probe_iters[2] = {0u, p->n_iters / 2};
   auto run = [&](uint32_t nb, float* ms) -> hipError_t {
     const auto br = assign_branches(graphs, n, nb);
     hipError_t r = hipEventRecord(e0, s);
     for (uint32_t j = 0; j < nb && !r; ++j) {
       r = hipStreamWaitEvent(bs[j], e0, 0);
-      for (uint32_t k : br[j]) {
-        LocalLaunch W = b->wl[k];
-        W.L.iter = 0;
-        W.L.cool_all = 0;
-        W.L.eta = b->weta[k][0];
-        if (!r) r = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
-      }
+      for (uint32_t k : br[j])
+        for (uint32_t it : probe_iters) {
+          LocalLaunch W = b->wl[k];
+          W.L.iter = it;
+          W.L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
+          W.L.eta = b->weta[k][std::min<uint32_t>(it, (uint32_t)b->weta[k].size() - 1)];
+          if (!r) r = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
+        }
       if (!r) r = hipEventRecord(join[j], bs[j]);
       if (!r) r = hipStreamWaitEvent(s, join[j], 0);
     }
