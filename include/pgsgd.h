@@ -569,7 +569,9 @@ typedef struct pgsgd_batch pgsgd_batch;
  *             (max_inflight_waves or automatic); the graphs are spread over
  *             tune->branches concurrent branches of the HIP graph (longest
  *             first, each to the least loaded branch), a branch laying out
- *             its graphs one after another.  Only tune->branches is used.
+ *             its graphs one after another; odd-numbered branches take
+ *             theirs smallest first, so large graphs run beside small ones.
+ *             Only tune->branches is used.
  *   PLAIN     one persistent launch per iteration covers the terms of all
  *             graphs, in the work order of tune->phases (block_threads,
  *             groups_per_item, blocks_per_cu, max_blocks, phases are used;
@@ -589,11 +591,13 @@ void pgsgd_batch_destroy(pgsgd_batch *b);
 pgsgd_status pgsgd_layout_batched(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
                                   float *const *coords, const pgsgd_tune *tune, void *stream);
 /*
- * Times candidate tunings on one iteration of the batch (on scratch copies of
- * the coordinates, which are left unchanged) and writes the fastest to *best:
- * for the windowed form 1, 2, 3, 4, 6 or 8 branches, for the plain form the
- * persistent kernel's shape.  On entry best->max_blocks is a grid cap kept in
- * every plain candidate (0 = none).
+ * Times candidate tunings of the batch (on scratch copies of the coordinates,
+ * which are left unchanged) and writes the fastest to *best: for the windowed
+ * form 1, 2, 3, 4, 6 or 8 branches, each timed on iteration 0 (uniform
+ * partners) plus iteration n_iters / 2 (cooling), whose costs differ by about
+ * 2x; for the plain form the persistent kernel's shape, timed on one
+ * iteration.  On entry best->max_blocks is a grid cap kept in every plain
+ * candidate (0 = none).
  * ms_out (host, may be NULL) receives the best time.  Synchronous.
  */
 pgsgd_status pgsgd_autotune_batched(pgsgd_graph *const *graphs, uint32_t n, const pgsgd_params *p,
