@@ -79,6 +79,8 @@ def _load():
         "or_sampled_path_stress": ([P, P, u32, u64, u32, P, P], None),
         "or_sampled_path_stress_pairs": ([P, P, u32, u64, u32, u32, f64, u32, P, P], None),
         "or_sps_segments": ([P, P, P], u64),
+        "or_loss_shift": ([u64], u32),
+        "or_loss_segments": ([P, P, P], u64),
         "or_sps_segment_counts": ([P, u32, u64, u32, P, u64, P], None),
         "or_sps_windowed_pairs": ([P, u32, u64, u32, u64, u64, P, P, P], None),
         "or_sampled_path_stress_windowed": ([P, P, u32, u64, u32, P, P], None),
@@ -400,9 +402,23 @@ def stress_loss_grad(g: Graph, coords: np.ndarray, n_pairs: int, seed: int = 11,
     return float(out[0]), int(out[1]), grad
 
 
+def loss_shift(S: int) -> int:
+    """Window shift of the loss's segments (reading R22)."""
+    return int(_load().or_loss_shift(int(S)))
+
+
+def loss_segments(g: Graph):
+    """Segments of the window-major loss pairs (reading R22): (start[n + 1], path[n])."""
+    n = int(_load().or_loss_segments(g._h, None, None))
+    start = np.zeros(n + 1, dtype=np.uint64)
+    path = np.zeros(max(1, n), dtype=np.uint32)
+    _load().or_loss_segments(g._h, _p(start), _p(path))
+    return start, path[:n]
+
+
 def loss_segment_counts(g: Graph, n_pairs: int, seed: int = 11, step: int = 0, graph_id: int = 0) -> np.ndarray:
     """Slots per segment of the window-major loss pairs (reading R22)."""
-    start, _ = sps_segments(g)
+    start, _ = loss_segments(g)
     n = len(start) - 1
     out = np.zeros(max(1, n), dtype=np.uint64)
     _load().or_loss_segment_counts(g._h, int(n_pairs), int(seed), int(graph_id), int(step), _p(start), n, _p(out))

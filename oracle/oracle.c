@@ -1276,8 +1276,10 @@ void or_stress_loss_grad(const or_graph *g, const float *coords, uint64_t n_pair
  * The differentiable loss with its pairs in window-major order (reading R22):
  * the law of pairs of or_stress_loss_grad (n_pairs pairs; i uniform over all
  * steps; j the power-law partner of i in its path; independent endpoint
- * coins), listed segment by segment over the segments of R21 (the windows of
- * 2^h steps cut at path boundaries, in step order).  Segment g receives n_g
+ * coins), listed segment by segment over the loss's own segments: the windows
+ * of 2^h steps cut at path boundaries, in step order, with h = or_loss_shift(S)
+ * (the rule of or_window_shift started from 2^10 steps instead of 2^14, so the
+ * segments are shorter than R21's where the graph allows).  Segment g receives n_g
  * slots, the number of the loss's own pairs q < n_pairs whose step i falls in
  * it; slot u (numbered over the segments in order) draws Philox stream 7 at
  * counter u with word 2 = the optimiser step: i = segment start +
@@ -1289,6 +1291,32 @@ void or_stress_loss_grad(const or_graph *g, const float *coords, uint64_t n_pair
  * same law.  Loss and gradient as in or_stress_loss_grad.
  * ------------------------------------------------------------------------- */
 enum { STREAM_LOSS_SLOT = 7 };
+
+/* Window shift of the loss's segments: windows of 2^10 steps, halved while
+ * there are fewer than 16 (down to 2^6), doubled while there are more than
+ * 32768. */
+uint32_t or_loss_shift(uint64_t S) {
+  uint32_t sh = 10;
+  while (sh > 6 && ((S + (1ull << sh) - 1) >> sh) < 16) --sh;
+  while (((S + (1ull << sh) - 1) >> sh) > 32768) ++sh;
+  return sh;
+}
+
+/* The loss's segments: start[0..n] (start[n] = S) and path[0..n-1]; returns n.
+ * With start = NULL only counts them. */
+uint64_t or_loss_segments(const or_graph *g, uint64_t *start, uint32_t *path) {
+  uint32_t sh = or_loss_shift(g->S);
+  uint64_t n = 0;
+  for (uint32_t p = 0; p < g->n_paths; ++p)
+    for (uint64_t a = g->path_off[p], b = g->path_off[p + 1]; a < b; ++n) {
+      uint64_t e = ((a >> sh) + 1) << sh;
+      if (e > b) e = b;
+      if (start) { start[n] = a; path[n] = p; }
+      a = e;
+    }
+  if (start) start[n] = g->S;
+  return n;
+}
 
 /* n_g of every segment for the loss's pairs of optimiser step `step` */
 void or_loss_segment_counts(const or_graph *g, uint64_t n_pairs, uint64_t seed, uint32_t graph_id, uint32_t step,
@@ -1332,11 +1360,11 @@ typedef struct {
 
 static void loss_segments_make(const or_graph *g, uint64_t n_pairs, uint64_t seed, uint32_t graph_id, uint32_t step,
                                loss_segments *ls) {
-  ls->n_seg = or_sps_segments(g, NULL, NULL);
+  ls->n_seg = or_loss_segments(g, NULL, NULL);
   ls->start = (uint64_t *)malloc(sizeof(uint64_t) * (ls->n_seg + 1));
   ls->path = (uint32_t *)malloc(sizeof(uint32_t) * (ls->n_seg + 1));
   ls->cnt = (uint64_t *)malloc(sizeof(uint64_t) * (ls->n_seg + 1));
-  or_sps_segments(g, ls->start, ls->path);
+  or_loss_segments(g, ls->start, ls->path);
   or_loss_segment_counts(g, n_pairs, seed, graph_id, step, ls->start, ls->n_seg, ls->cnt);
 }
 

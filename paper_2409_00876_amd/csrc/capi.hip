@@ -138,6 +138,21 @@ struct DeviceGuard {
 // ---------------------------------------------------------------------------
 // Graph handle
 // ---------------------------------------------------------------------------
+// Window-major segment tables: the windows of 2^shift steps cut at path
+// boundaries, in step order; run x (XCD x) holds the segments starting in the
+// x-th eighth of the steps.
+struct SegTables {
+  uint32_t shift = 0, nseg = 0, xstride = 0;
+  uint64_t* start = nullptr;   // [nseg + 1]
+  uint32_t* path = nullptr;    // [nseg]
+  uint32_t* wseg = nullptr;    // [n_win + 1] first segment of every window
+  uint32_t* count = nullptr;   // [nseg] histogram
+  uint64_t* off = nullptr;     // [nseg + 1] first slot of every segment
+  uint32_t* sbeg = nullptr;    // [kXcds + 1]
+  uint64_t* xitem = nullptr;   // [kXcds][xstride]
+  uint64_t* queue = nullptr;   // [2][kXcds][16]
+};
+
 struct pgsgd_graph {
   int device = 0;
   uint32_t n_nodes = 0, n_paths = 0, path_top = 1, path_slots = 2, max_path_steps = 0;
@@ -181,16 +196,21 @@ struct pgsgd_graph {
   uint32_t* d_lorder = nullptr;
   uint32_t* d_lsbeg = nullptr;
   uint32_t* d_lwpath = nullptr;
-  // window-major sampled path stress tables (allocated on first use)
-  uint32_t sps_shift = 0, sps_nseg = 0, sps_xstride = 0;
-  uint64_t* d_sseg_start = nullptr;
-  uint32_t* d_sseg_path = nullptr;
-  uint32_t* d_swseg = nullptr;
-  uint32_t* d_scount = nullptr;
-  uint64_t* d_soff = nullptr;
-  uint32_t* d_ssbeg = nullptr;
-  uint64_t* d_sxitem = nullptr;
-  uint64_t* d_squeue = nullptr;
+  // window-major segment tables of the sampled path stress (R21) and of the
+  // loss (R22), and the loss adjoint's tiles (allocated on first use)
+  SegTables sps, loss;
+  uint32_t n_tiles = 0, tile_shift = 0;
+  uint32_t* d_tile_seg = nullptr;
+  uint32_t* d_tile_off = nullptr;
+  uint32_t* d_tile_base = nullptr;
+  uint32_t* d_tile_queue = nullptr;
+  // the loss step whose segment offsets the loss tables hold (a backward after
+  // the forward of the same step reuses them)
+  struct {
+    const void* tables = nullptr;
+    uint64_t n_pairs = 0;
+    uint32_t word2 = 0, c3 = 0, k0 = 0, k1 = 0;
+  } loss_key;
   // second count/offset set and the counting stream: the counts of iteration
   // t + 1 are computed on count_stream while iteration t is laid out
   uint32_t* d_lcount2 = nullptr;
@@ -205,10 +225,13 @@ struct pgsgd_graph {
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)d_rec, (void*)d_path_off, (void*)d_first, (void*)d_work, (void*)d_inv, (void*)d_zipf, (void*)d_guide, (void*)d_part_f,
                     (void*)d_part_n, (void*)d_part_skip, (void*)d_out_f, (void*)d_out_n, (void*)d_mean, (void*)d_work2, (void*)d_lcount, (void*)d_loff, (void*)d_lxitem, (void*)d_lqueue, (void*)d_lorder,
-                    (void*)d_lsbeg, (void*)d_lwpath, (void*)d_sseg_start, (void*)d_sseg_path, (void*)d_swseg,
-                    (void*)d_scount, (void*)d_soff, (void*)d_ssbeg, (void*)d_sxitem, (void*)d_squeue,
-                    (void*)d_lcount2, (void*)d_loff2, (void*)d_lxitem2, (void*)d_lqueue2})
+                    (void*)d_lsbeg, (void*)d_lwpath, (void*)d_lcount2, (void*)d_loff2, (void*)d_lxitem2,
+                    (void*)d_lqueue2, (void*)d_tile_seg, (void*)d_tile_off, (void*)d_tile_base, (void*)d_tile_queue})
       if (p) (void)hipFree(p);
+    for (SegTables* t : {&sps, &loss})
+      for (void* p : {(void*)t->start, (void*)t->path, (void*)t->wseg, (void*)t->count, (void*)t->off,
+                      (void*)t->sbeg, (void*)t->xitem, (void*)t->queue})
+        if (p) (void)hipFree(p);
     for (hipEvent_t e : {ev_start, ev_count[0], ev_count[1], ev_layout[0], ev_layout[1]})
       if (e) (void)hipEventDestroy(e);
     if (count_stream) (void)hipStreamDestroy(count_stream);
@@ -859,15 +882,13 @@ pgsgd_status ensure_count_stream(pgsgd_graph* g) {
   return PGSGD_OK;
 }
 
-// Segments of the window-major sampled path stress: the windows of the
-// windowed schedule cut at path boundaries, in step order; run x (XCD x)
-// holds the segments starting in the x-th eighth of the steps.
-pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
-  const uint32_t shift = window_shift(g->S);
-  if (g->d_sseg_start && g->sps_shift == shift) return PGSGD_OK;
+// Segment tables for windows of 2^shift steps (built once per shift, kept on
+// the graph).
+pgsgd_status ensure_seg_tables(pgsgd_graph* g, SegTables& T, uint32_t shift, hipStream_t s) {
+  if (T.start && T.shift == shift) return PGSGD_OK;
   HIP_TRY(hipStreamSynchronize(s));
-  const auto set = {(void**)&g->d_sseg_start, (void**)&g->d_sseg_path, (void**)&g->d_swseg, (void**)&g->d_scount,
-                    (void**)&g->d_soff, (void**)&g->d_ssbeg, (void**)&g->d_sxitem, (void**)&g->d_squeue};
+  const auto set = {(void**)&T.start, (void**)&T.path, (void**)&T.wseg, (void**)&T.count, (void**)&T.off,
+                    (void**)&T.sbeg, (void**)&T.xitem, (void**)&T.queue};
   free_set(g, set);
   const uint64_t nwin = (g->S + (1ull << shift) - 1) >> shift;
   std::vector<uint64_t> start;
@@ -893,28 +914,92 @@ pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
   }
   uint32_t longest = 0;
   for (uint32_t x = 0; x < kXcds; ++x) longest = std::max(longest, sbeg[x + 1] - sbeg[x]);
-  g->sps_shift = shift;
-  g->sps_nseg = (uint32_t)nseg;
-  g->sps_xstride = longest + 1;
+  T.shift = shift;
+  T.nseg = (uint32_t)nseg;
+  T.xstride = longest + 1;
   const pgsgd_status st = [&]() -> pgsgd_status {
     pgsgd_status e;
-    if ((e = dev_alloc(g, &g->d_sseg_start, nseg + 1))) return e;
-    if ((e = dev_alloc(g, &g->d_sseg_path, nseg))) return e;
-    if ((e = dev_alloc(g, &g->d_swseg, nwin + 1))) return e;
-    if ((e = dev_alloc(g, &g->d_scount, nseg))) return e;
-    if ((e = dev_alloc(g, &g->d_soff, nseg + 1))) return e;
-    if ((e = dev_alloc(g, &g->d_ssbeg, kXcds + 1))) return e;
-    if ((e = dev_alloc(g, &g->d_sxitem, (size_t)kXcds * g->sps_xstride))) return e;
-    if ((e = dev_alloc(g, &g->d_squeue, (size_t)2 * kXcds * 16))) return e;
-    HIP_TRY(hipMemcpy(g->d_sseg_start, start.data(), sizeof(uint64_t) * (nseg + 1), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->d_sseg_path, path.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->d_swseg, wseg.data(), sizeof(uint32_t) * (nwin + 1), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->d_ssbeg, sbeg.data(), sizeof(uint32_t) * (kXcds + 1), hipMemcpyHostToDevice));
-    HIP_TRY(launch_fill_u32(g->d_scount, nseg, 0u, s));  // the histogram must start at zero
+    if ((e = dev_alloc(g, &T.start, nseg + 1))) return e;
+    if ((e = dev_alloc(g, &T.path, nseg))) return e;
+    if ((e = dev_alloc(g, &T.wseg, nwin + 1))) return e;
+    if ((e = dev_alloc(g, &T.count, nseg))) return e;
+    if ((e = dev_alloc(g, &T.off, nseg + 1))) return e;
+    if ((e = dev_alloc(g, &T.sbeg, kXcds + 1))) return e;
+    if ((e = dev_alloc(g, &T.xitem, (size_t)kXcds * T.xstride))) return e;
+    if ((e = dev_alloc(g, &T.queue, (size_t)2 * kXcds * 16))) return e;
+    HIP_TRY(hipMemcpy(T.start, start.data(), sizeof(uint64_t) * (nseg + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(T.path, path.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(T.wseg, wseg.data(), sizeof(uint32_t) * (nwin + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(T.sbeg, sbeg.data(), sizeof(uint32_t) * (kXcds + 1), hipMemcpyHostToDevice));
+    HIP_TRY(launch_fill_u32(T.count, nseg, 0u, s));  // the histogram must start at zero
     return PGSGD_OK;
   }();
-  if (st) free_set(g, set);
+  if (st) {
+    free_set(g, set);
+    T.start = nullptr;
+    T.shift = 0;
+  }
   return st;
+}
+
+// Segments of the window-major sampled path stress (R21): the windows of the
+// windowed schedule.
+pgsgd_status ensure_sps_windowed(pgsgd_graph* g, hipStream_t s) {
+  return ensure_seg_tables(g, g->sps, window_shift(g->S), s);
+}
+
+// Tiles of the loss adjoint: the loss's segments grouped by the lowest device
+// node id their steps visit, in units of kTileNodes ids; a tile (at most
+// kTileMaxSeg segments; a fuller group is split) accumulates the gradient of
+// the 2 * kTileNodes ids from its base in LDS.
+pgsgd_status ensure_loss_tiles(pgsgd_graph* g, hipStream_t s) {
+  const SegTables& T = g->loss;
+  if (g->d_tile_seg && g->tile_shift == T.shift) return PGSGD_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  const auto set = {(void**)&g->d_tile_seg, (void**)&g->d_tile_off, (void**)&g->d_tile_base,
+                    (void**)&g->d_tile_queue};
+  free_set(g, set);
+  g->tile_shift = 0;
+  const uint32_t nseg = T.nseg;
+  pgsgd_status st;
+  if ((st = dev_alloc(g, &g->d_tile_seg, std::max<uint32_t>(nseg, 1)))) return st;
+  std::vector<uint32_t> lo(nseg);
+  if (nseg) {
+    HIP_TRY(launch_segment_min_node(g->d_rec, T.start, nseg, g->d_tile_seg, s));
+    HIP_TRY(hipMemcpyAsync(lo.data(), g->d_tile_seg, sizeof(uint32_t) * nseg, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // segments in order of their tile key (counting sort), then cut into tiles
+  const uint32_t n_keys = (uint32_t)(g->n_nodes / kTileNodes + 1);
+  std::vector<uint32_t> kb(n_keys + 1, 0), order(nseg);
+  for (uint32_t k = 0; k < nseg; ++k) ++kb[lo[k] / kTileNodes + 1];
+  for (uint32_t k = 0; k < n_keys; ++k) kb[k + 1] += kb[k];
+  std::vector<uint32_t> cur(kb.begin(), kb.end() - 1);
+  for (uint32_t k = 0; k < nseg; ++k) order[cur[lo[k] / kTileNodes]++] = k;
+  std::vector<uint32_t> toff(1, 0), tbase;
+  for (uint32_t key = 0; key < n_keys; ++key)
+    for (uint32_t a = kb[key]; a < kb[key + 1]; a += kTileMaxSeg) {
+      toff.push_back(std::min(kb[key + 1], a + kTileMaxSeg));
+      tbase.push_back(key * kTileNodes);
+    }
+  const uint32_t nt = (uint32_t)tbase.size();
+  st = [&]() -> pgsgd_status {
+    pgsgd_status e;
+    if ((e = dev_alloc(g, &g->d_tile_off, nt + 1))) return e;
+    if ((e = dev_alloc(g, &g->d_tile_base, std::max<uint32_t>(nt, 1)))) return e;
+    if ((e = dev_alloc(g, &g->d_tile_queue, 64))) return e;
+    if (nseg) HIP_TRY(hipMemcpy(g->d_tile_seg, order.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_tile_off, toff.data(), sizeof(uint32_t) * (nt + 1), hipMemcpyHostToDevice));
+    if (nt) HIP_TRY(hipMemcpy(g->d_tile_base, tbase.data(), sizeof(uint32_t) * nt, hipMemcpyHostToDevice));
+    return PGSGD_OK;
+  }();
+  if (st) {
+    free_set(g, set);
+    return st;
+  }
+  g->n_tiles = nt;
+  g->tile_shift = T.shift;
+  return PGSGD_OK;
 }
 
 // Automatic wave cap of the windowed schedule (see kLocalNodesPerWave).
@@ -1428,23 +1513,23 @@ namespace {
 // Launch arguments of the window-major passes over the graph's segments
 // (ensure_sps_windowed done): slots drawn from Philox stream slot_stream;
 // loss_pairs > 0 counts the loss's plain pairs instead of Eq. 2's.
-SpsWinLaunch sps_win_launch(const pgsgd_graph* g, const StressLaunch& P, uint32_t slot_stream, uint32_t graph_id,
-                            uint64_t loss_pairs) {
+SpsWinLaunch sps_win_launch(const pgsgd_graph* g, const SegTables& T, const StressLaunch& P, uint32_t slot_stream,
+                            uint32_t graph_id, uint64_t loss_pairs) {
   SpsWinLaunch W{};
   W.P = P;
   W.slot_c3 = (slot_stream << 24) | (graph_id & 0xFFFFFFu);
-  W.win_shift = g->sps_shift;
-  W.n_seg = g->sps_nseg;
-  W.xstride = g->sps_xstride;
+  W.win_shift = T.shift;
+  W.n_seg = T.nseg;
+  W.xstride = T.xstride;
   W.count_blocks = (uint32_t)g->n_cu * 2;
-  W.seg_start = g->d_sseg_start;
-  W.seg_path = g->d_sseg_path;
-  W.wseg = g->d_swseg;
-  W.count = g->d_scount;
-  W.seg_off = g->d_soff;
-  W.sbeg = g->d_ssbeg;
-  W.xitem = g->d_sxitem;
-  W.queue = g->d_squeue;
+  W.seg_start = T.start;
+  W.seg_path = T.path;
+  W.wseg = T.wseg;
+  W.count = T.count;
+  W.seg_off = T.off;
+  W.sbeg = T.sbeg;
+  W.xitem = T.xitem;
+  W.queue = T.queue;
   W.loss_pairs = loss_pairs;
   return W;
 }
@@ -1452,17 +1537,30 @@ SpsWinLaunch sps_win_launch(const pgsgd_graph* g, const StressLaunch& P, uint32_
 // Segments and their counts for the loss's window-major pairs (reading R22) of
 // one optimiser step: validates what the window-major loss needs.
 pgsgd_status loss_win_prepare(pgsgd_graph* g, const pgsgd_params* p, const StressLaunch& P, uint64_t n_pairs,
-                              hipStream_t s, SpsWinLaunch* W) {
-  pgsgd_status st = ensure_sps_windowed(g, s);
+                              hipStream_t s, SpsWinLaunch* W, bool offsets_only) {
+  pgsgd_status st = ensure_seg_tables(g, g->loss, loss_shift(g->S), s);
   if (st) return st;
-  if ((size_t)g->path_slots * 8 + (size_t)g->sps_nseg * 4 > g->lds_limit)
+  if ((size_t)g->path_slots * 8 + (size_t)g->loss.nseg * 4 > g->lds_limit)
     return fail(PGSGD_ERR_UNSUPPORTED, "the segment histogram (%u segments) exceeds the %zu-byte LDS of a block",
-                g->sps_nseg, g->lds_limit);
+                g->loss.nseg, g->lds_limit);
   if (n_pairs >= (1ull << 32))
     return fail(PGSGD_ERR_UNSUPPORTED, "n_pairs %llu too large for 32-bit segment counts (the PLAIN order has no "
                 "such limit)", (unsigned long long)n_pairs);
-  *W = sps_win_launch(g, P, kStreamLossSlot, p->graph_id, n_pairs);
+  *W = sps_win_launch(g, g->loss, P, kStreamLossSlot, p->graph_id, n_pairs);
+  // the tile passes read only the segment offsets: those of the same step are
+  // still in the tables when the backward follows its forward
+  auto& key = g->loss_key;
+  if (offsets_only && key.tables == g->loss.start && key.n_pairs == n_pairs && key.word2 == P.word2 &&
+      key.c3 == P.c3 && key.k0 == P.k0 && key.k1 == P.k1)
+    return PGSGD_OK;
+  key.tables = nullptr;
   HIP_TRY(launch_sps_win_count_scan(*W, s));
+  key.tables = g->loss.start;
+  key.n_pairs = n_pairs;
+  key.word2 = P.word2;
+  key.c3 = P.c3;
+  key.k0 = P.k0;
+  key.k1 = P.k1;
   return PGSGD_OK;
 }
 
@@ -1581,12 +1679,12 @@ pgsgd_status path_stress_impl(pgsgd_graph* g, const float* coords, uint32_t m, u
   if (windowed) {
     pgsgd_status st = ensure_sps_windowed(g, s);
     if (st) return st;
-    if ((size_t)g->path_slots * 8 + (size_t)g->sps_nseg * 4 > g->lds_limit)
+    if ((size_t)g->path_slots * 8 + (size_t)g->sps.nseg * 4 > g->lds_limit)
       return fail(PGSGD_ERR_UNSUPPORTED, "the segment histogram (%u segments) exceeds the %zu-byte LDS of a block",
-                  g->sps_nseg, g->lds_limit);
-    if (((uint64_t)m << (g->sps_shift + 1)) >= (1ull << 32))
+                  g->sps.nseg, g->lds_limit);
+    if (((uint64_t)m << (g->sps.shift + 1)) >= (1ull << 32))
       return fail(PGSGD_ERR_UNSUPPORTED, "pairs_per_step %u too large for 32-bit segment counts", m);
-    W = sps_win_launch(g, P, kStreamSpsSlot, graph_id, 0);
+    W = sps_win_launch(g, g->sps, P, kStreamSpsSlot, graph_id, 0);
   }
   auto pass = [&](int k, const double* mean_dev, uint64_t* part_n, uint64_t* part_skip) -> hipError_t {
     return windowed ? launch_sps_win_pass(W, k, mean_dev, g->d_part_f, part_n, part_skip, kStressBlocks, s)
@@ -1707,14 +1805,24 @@ pgsgd_status pgsgd_stress_forward(pgsgd_graph* g, const pgsgd_params* p, const f
   P.count = g->S ? n_pairs : 0;
   P.work = g->d_work;
   if (P.count) HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
+  uint32_t parts = kStressBlocks;
   if (P.count && resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
     SpsWinLaunch W;
-    if ((st = loss_win_prepare(g, p, P, n_pairs, s, &W))) return st;
-    HIP_TRY(launch_loss_win_fwd(W, g->d_part_f, g->d_part_n, kStressBlocks, s));
+    const bool tiles = loss_tile_lds_bytes(p->zipf_window, true) + kTileStaticLds <= g->lds_limit;
+    if ((st = loss_win_prepare(g, p, P, n_pairs, s, &W, tiles))) return st;
+    if (tiles) {
+      if ((st = ensure_loss_tiles(g, s))) return st;
+      parts = std::max<uint32_t>(1, std::min<uint32_t>(g->n_tiles, 2u * (uint32_t)g->n_cu));
+      HIP_TRY(launch_fill_u32(g->d_tile_queue, 1, 0u, s));
+      const TileLaunch T{g->d_tile_seg, g->d_tile_off, g->d_tile_base, g->n_tiles, g->d_tile_queue};
+      HIP_TRY(launch_loss_tile_fwd(W, T, g->d_part_f, g->d_part_n, parts, s));
+    } else {
+      HIP_TRY(launch_loss_win_fwd(W, g->d_part_f, g->d_part_n, kStressBlocks, s));
+    }
   } else {
     HIP_TRY(launch_stress_fwd(P, g->d_part_f, g->d_part_n, s));
   }
-  HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, kStressBlocks, nullptr, nullptr, nullptr, loss_dev,
+  HIP_TRY(launch_reduce_parts(g->d_part_f, g->d_part_n, nullptr, parts, nullptr, nullptr, nullptr, loss_dev,
                               n_valid_dev, s));
   return ok();
 }
@@ -1741,8 +1849,20 @@ pgsgd_status pgsgd_stress_backward(pgsgd_graph* g, const pgsgd_params* p, const 
   HIP_TRY(launch_to_work(coords, g->d_work, g->n_nodes, g->d_inv, s));
   if (resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED) {
     SpsWinLaunch W;
-    if ((st = loss_win_prepare(g, p, P, n_pairs, s, &W))) return st;
-    HIP_TRY(launch_loss_win_bwd(W, grad_out_dev, n_valid_dev, grad_coords, kStressBlocks, s));
+    // by tiles when their LDS image fits a block (it does for every window W up to ~10^4)
+    const bool tiles = loss_tile_lds_bytes(p->zipf_window, true) + kTileStaticLds <= g->lds_limit;
+    if ((st = loss_win_prepare(g, p, P, n_pairs, s, &W, tiles))) return st;
+    if (tiles) {
+      if ((st = ensure_loss_tiles(g, s))) return st;
+      if (g->n_tiles) {
+        HIP_TRY(launch_fill_u32(g->d_tile_queue, 1, 0u, s));
+        const TileLaunch T{g->d_tile_seg, g->d_tile_off, g->d_tile_base, g->n_tiles, g->d_tile_queue};
+        const uint32_t blocks = std::min<uint32_t>(g->n_tiles, 2u * (uint32_t)g->n_cu);
+        HIP_TRY(launch_loss_tile_bwd(W, T, grad_out_dev, n_valid_dev, grad_coords, blocks, s));
+      }
+    } else {
+      HIP_TRY(launch_loss_win_bwd(W, grad_out_dev, n_valid_dev, grad_coords, kStressBlocks, s));
+    }
   } else {
     HIP_TRY(launch_stress_bwd(P, grad_out_dev, n_valid_dev, grad_coords, s));
   }

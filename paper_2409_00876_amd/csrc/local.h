@@ -34,6 +34,18 @@ inline uint32_t window_shift(uint64_t S) {
   return sh;
 }
 
+// log2 of the segment length of the loss's window-major pairs (reading R22):
+// 2^10 steps, halved while there would be fewer than 16 windows (not below
+// 2^6), doubled while there would be more than 32768.  Part of the loss's pair
+// definition.
+inline uint32_t loss_shift(uint64_t S) {
+  auto n = [&](uint32_t sh) { return (S + (1ull << sh) - 1) >> sh; };
+  uint32_t sh = 10;
+  while (sh > 6 && n(sh) < kLocalMinWindows) --sh;
+  while (n(sh) > kLocalMaxWindows) ++sh;
+  return sh;
+}
+
 // Processing order: kXcds * streams runs of windows; run sigma = x * streams +
 // r is stream r of XCD x and holds the windows starting in piece sigma of
 // every path (paths cut into kXcds * streams equal pieces), in id order.

@@ -87,6 +87,32 @@ hipError_t launch_loss_win_fwd(const SpsWinLaunch& W, double* part_f, uint64_t* 
                                hipStream_t s);
 hipError_t launch_loss_win_bwd(const SpsWinLaunch& W, const float* grad_out, const uint64_t* n_valid, float* grad,
                                uint32_t blocks, hipStream_t s);
+// The loss adjoint by tiles: block b takes tiles from *queue (zero at
+// launch); tile t covers the segments seg[off[t] .. off[t + 1]) (at most
+// kTileMaxSeg) and accumulates the gradient of device node ids [base[t],
+// base[t] + 2 * kTileNodes) in LDS, flushed with one atomic add per touched
+// entry; other endpoints are added directly.  The pairs are the window-major
+// loss pairs of W, the same slots as launch_loss_win_bwd.
+constexpr uint32_t kTileNodes = 2048;
+constexpr uint32_t kTileMaxSeg = 256;
+constexpr uint32_t kTileThreads = 512;
+struct TileLaunch {
+  const uint32_t* seg;
+  const uint32_t* off;
+  const uint32_t* base;
+  uint32_t n_tiles;
+  uint32_t* queue;
+};
+hipError_t launch_loss_tile_bwd(const SpsWinLaunch& W, const TileLaunch& T, const float* grad_out,
+                                const uint64_t* n_valid, float* grad, uint32_t blocks, hipStream_t s);
+// The forward pass over the same tiles: per-block sums into part_f / part_n[0 .. blocks).
+hipError_t launch_loss_tile_fwd(const SpsWinLaunch& W, const TileLaunch& T, double* part_f, uint64_t* part_n,
+                                uint32_t blocks, hipStream_t s);
+size_t loss_tile_lds_bytes(uint32_t W, bool grad);  // dynamic LDS of k_loss_tile
+constexpr size_t kTileStaticLds = 9 * 1024;   // static LDS of k_loss_tile (a tile's segment table), rounded up
+// out[g] = the lowest device node id over the steps [start[g], start[g + 1])
+hipError_t launch_segment_min_node(const StepRec* rec, const uint64_t* start, uint32_t nseg, uint32_t* out,
+                                   hipStream_t s);
 hipError_t launch_path_stress_exact(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_fwd(const StressLaunch& P, double* part_f, uint64_t* part_n, hipStream_t s);
 hipError_t launch_stress_bwd(const StressLaunch& P, const float* grad_out, const uint64_t* n_valid, float* grad,

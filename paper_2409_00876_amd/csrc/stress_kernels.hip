@@ -280,19 +280,28 @@ __global__ __launch_bounds__(1024) void k_sps_win_count(SpsWinLaunch W) {
 // per-run item prefixes and zeroed item counters, then the histogram back to
 // zero.  Each thread owns a contiguous chunk; every stage is a chunk pass and
 // a block scan.
+// One block.  The histogram is read into LDS with coalesced loads (and
+// cleared for the next use), so the chunk passes below read LDS, not memory.
 __global__ __launch_bounds__(1024) void k_sps_win_scan(SpsWinLaunch W) {
+  extern __shared__ __align__(16) char lds[];
   __shared__ uint64_t lds16[16];
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(lds);
   const uint32_t n = W.n_seg;
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+    cnt[k] = W.count[k];
+    W.count[k] = 0;
+  }
+  __syncthreads();
   const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
   const uint32_t k0 = min(n, threadIdx.x * per);
   const uint32_t k1 = min(n, k0 + per);
   uint64_t s = 0;
-  for (uint32_t k = k0; k < k1; ++k) s += W.count[k];
+  for (uint32_t k = k0; k < k1; ++k) s += cnt[k];
   uint64_t total;
   uint64_t acc = block_exclusive_scan(s, lds16, &total);
   for (uint32_t k = k0; k < k1; ++k) {
     W.seg_off[k] = acc;
-    acc += W.count[k];
+    acc += cnt[k];
   }
   if (threadIdx.x == 0) W.seg_off[n] = total;
   for (uint32_t run = 0; run < kXcds; ++run) {  // run x: segments [sbeg[x], sbeg[x + 1])
@@ -300,19 +309,17 @@ __global__ __launch_bounds__(1024) void k_sps_win_scan(SpsWinLaunch W) {
     const uint32_t rper = (nq + blockDim.x - 1) / blockDim.x;
     const uint32_t q0 = min(nq, threadIdx.x * rper), q1 = min(nq, q0 + rper);
     uint64_t items = 0;
-    for (uint32_t q = q0; q < q1; ++q) items += (W.count[b + q] + 63) >> 6;
+    for (uint32_t q = q0; q < q1; ++q) items += (cnt[b + q] + 63) >> 6;
     uint64_t run_total;
     uint64_t pre = block_exclusive_scan(items, lds16, &run_total);
     uint64_t* xi = W.xitem + (size_t)run * W.xstride;
     for (uint32_t q = q0; q < q1; ++q) {
       xi[q] = pre;
-      pre += (W.count[b + q] + 63) >> 6;
+      pre += (cnt[b + q] + 63) >> 6;
     }
     if (threadIdx.x == 0) xi[nq] = run_total;
   }
   if (threadIdx.x < 2 * kXcds) W.queue[(size_t)threadIdx.x * 16] = 0;
-  __syncthreads();
-  for (uint32_t k = k0; k < k1; ++k) W.count[k] = 0;
 }
 
 // One pass: the waves of XCD x take the items of run x from its counter,
@@ -648,6 +655,157 @@ __global__ __launch_bounds__(256) void k_loss_win(SpsWinLaunch W, const float* _
 }
 
 // ---------------------------------------------------------------------------
+// The loss adjoint by tiles.  The ~30 paths through a node each add to its
+// gradient, from their own segments; a tile gathers the segments of all paths
+// whose steps start in one range of device node ids (the ids follow the
+// paths), so most of a tile's adjoint lands in an LDS image of that range and
+// reaches memory once per touched entry instead of once per pair.
+// ---------------------------------------------------------------------------
+size_t loss_tile_lds_bytes(uint32_t W, bool grad) {
+  const size_t head = ((size_t)(W + 1) * 4 + (size_t)(kGuideSize + 1) * 2 + 15) & ~(size_t)15;
+  return head + (grad ? (size_t)4 * kTileNodes * sizeof(float2) : 0);
+}
+
+// kGrad = false: the forward pass over the same tiles (per-block sums of the
+// stress and the valid-pair count; the tile order keeps a block's coordinate
+// reads within one range of node ids).
+template <bool kGrad>
+__global__ __launch_bounds__(kTileThreads) void k_loss_tile(SpsWinLaunch W, TileLaunch T,
+                                                           const float* __restrict__ grad_out,
+                                                           const uint64_t* __restrict__ n_valid,
+                                                           float* __restrict__ grad, double* __restrict__ part_f,
+                                                           uint64_t* __restrict__ part_n) {
+  __shared__ double red_f[16];
+  __shared__ uint64_t red_n[16];
+  extern __shared__ __align__(16) char lds[];
+  __shared__ uint64_t s_flat[kTileMaxSeg + 1];  // slot prefix over the tile's segments
+  __shared__ uint64_t s_slot[kTileMaxSeg];      // first slot of each segment
+  __shared__ uint64_t s_start[kTileMaxSeg];     // first step of each segment
+  __shared__ uint32_t s_len[kTileMaxSeg];       // steps of each segment
+  __shared__ uint32_t s_path[kTileMaxSeg];
+  __shared__ uint32_t s_tile;
+  const StressLaunch& P = W.P;
+  uint32_t* zipf = reinterpret_cast<uint32_t*>(lds);
+  uint16_t* guide = reinterpret_cast<uint16_t*>(lds + (size_t)(P.W + 1) * 4);
+  float2* acc = reinterpret_cast<float2*>(
+      lds + (((size_t)(P.W + 1) * 4 + (size_t)(kGuideSize + 1) * 2 + 15) & ~(size_t)15));
+  constexpr uint32_t kAcc = 4 * kTileNodes;  // entries: 2 * kTileNodes nodes x 2 endpoints
+  for (uint32_t k = threadIdx.x; k <= P.W; k += blockDim.x) zipf[k] = P.zipf[k];
+  for (uint32_t k = threadIdx.x; k <= kGuideSize; k += blockDim.x) guide[k] = P.guide[k];
+  double scale = 0.0;
+  if (kGrad) {
+    const uint64_t n = n_valid[0];
+    if (n == 0) return;  // uniform over the grid: no block waits at a barrier below
+    scale = (double)grad_out[0] * 2.0 / (double)n;
+  }
+  double sum = 0.0;
+  uint64_t nv = 0;
+  float* __restrict__ GX = grad;
+  float* __restrict__ GY = grad + 2ull * P.n_nodes;
+  auto global_add = [&](uint64_t a, float gx, float gy) {
+    if (P.inv) a = 2ull * P.inv[a >> 1] + (a & 1);  // the gradient is in the caller's node order
+    unsafeAtomicAdd(&GX[a], gx);
+    unsafeAtomicAdd(&GY[a], gy);
+  };
+  for (;;) {
+    __syncthreads();  // the previous tile's flush (and the tables above) are done
+    if (threadIdx.x == 0) s_tile = atomicAdd(T.queue, 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= T.n_tiles) break;
+    const uint64_t base = T.base[t];
+    const uint32_t k0 = T.off[t];
+    const uint32_t nk = T.off[t + 1] - k0;
+    if (kGrad)
+      for (uint32_t e = threadIdx.x; e < kAcc; e += blockDim.x) acc[e] = make_float2(0.0f, 0.0f);
+    for (uint32_t k = threadIdx.x; k < nk; k += blockDim.x) {
+      const uint32_t g = T.seg[k0 + k];
+      s_slot[k] = W.seg_off[g];
+      s_flat[k + 1] = W.seg_off[g + 1] - W.seg_off[g];
+      s_start[k] = W.seg_start[g];
+      s_len[k] = (uint32_t)(W.seg_start[g + 1] - W.seg_start[g]);
+      s_path[k] = W.seg_path[g];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_flat[0] = 0;
+      for (uint32_t k = 0; k < nk; ++k) s_flat[k + 1] += s_flat[k];
+    }
+    __syncthreads();
+    const uint64_t total = s_flat[nk];
+    for (uint64_t f = threadIdx.x; f < total; f += blockDim.x) {
+      uint32_t lo = 0, hi = nk;  // the segment k with s_flat[k] <= f < s_flat[k + 1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_flat[mid] <= f) lo = mid;
+        else hi = mid;
+      }
+      const uint64_t u = s_slot[lo] + (f - s_flat[lo]);
+      const uint32_t p = s_path[lo];
+      const uint64_t pst = P.path_off[p];
+      const uint64_t plen = P.path_off[p + 1] - pst;
+      const Rand4 r = philox10((uint32_t)u, (uint32_t)(u >> 32), P.word2, W.slot_c3, P.k0, P.k1);
+      const uint64_t i = s_start[lo] + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), s_len[lo]);
+      uint64_t j, a, b;
+      double d;
+      if (!partner_power_law(i, pst, plen, r.r2, r.r3, zipf, guide, P.W, j)) continue;
+      if (!pair_terms(P.rec, i, j, r.r3 & 1u, (r.r3 >> 1) & 1u, a, b, d) || a == b) continue;
+      if (!kGrad) {
+        sum += stress_work(P.work, a, b, d);
+        ++nv;
+        continue;
+      }
+      double dx, dy;
+      const double mag = delta_work(P.work, a, b, dx, dy);
+      if (mag == 0.0) continue;
+      const double c = scale * (mag - d) / (d * d) / mag;
+      const float gx = (float)(c * dx), gy = (float)(c * dy);
+      const uint64_t oa = (a >> 1) - base, ob = (b >> 1) - base;  // wraps to huge below the base
+      if (oa < 2ull * kTileNodes) {
+        atomicAdd(&acc[(oa << 1) | (a & 1)].x, gx);
+        atomicAdd(&acc[(oa << 1) | (a & 1)].y, gy);
+      } else {
+        global_add(a, gx, gy);
+      }
+      if (ob < 2ull * kTileNodes) {
+        atomicAdd(&acc[(ob << 1) | (b & 1)].x, -gx);
+        atomicAdd(&acc[(ob << 1) | (b & 1)].y, -gy);
+      } else {
+        global_add(b, -gx, -gy);
+      }
+    }
+    if (kGrad) {
+      __syncthreads();
+      for (uint32_t e = threadIdx.x; e < kAcc; e += blockDim.x) {
+        const float2 v = acc[e];
+        const uint64_t node = base + (e >> 1);
+        if ((v.x != 0.0f || v.y != 0.0f) && node < P.n_nodes) global_add(2ull * node + (e & 1), v.x, v.y);
+      }
+    }
+  }
+  if (!kGrad) {
+    sum = block_sum(sum, red_f);
+    nv = block_sum(nv, red_n);
+    if (threadIdx.x == 0) {
+      part_f[blockIdx.x] = sum;
+      part_n[blockIdx.x] = nv;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_segment_min_node(const StepRec* __restrict__ rec,
+                                                          const uint64_t* __restrict__ start, uint32_t nseg,
+                                                          uint32_t* __restrict__ out) {
+  const uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // one wave per segment
+  if (g >= nseg) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t m = 0xFFFFFFFFu;
+  for (uint64_t k = start[g] + lane; k < start[g + 1]; k += 64) m = min(m, rec[k].node_rev & kNodeMask);
+  for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, o, 64));
+  if (lane == 0) out[g] = m;
+}
+
+// ---------------------------------------------------------------------------
 // Initial layout and first visits
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
@@ -735,7 +893,7 @@ hipError_t launch_sps_win_count_scan(const SpsWinLaunch& W, hipStream_t s) {
   hipLaunchKernelGGL(k_sps_win_count, dim3(W.count_blocks), dim3(1024), lds, s, W);
   hipError_t e = hipGetLastError();
   if (e) return e;
-  hipLaunchKernelGGL(k_sps_win_scan, dim3(1), dim3(1024), 0, s, W);
+  hipLaunchKernelGGL(k_sps_win_scan, dim3(1), dim3(1024), (size_t)W.n_seg * 4, s, W);
   return hipGetLastError();
 }
 
@@ -786,6 +944,26 @@ hipError_t launch_loss_win_bwd(const SpsWinLaunch& W, const float* grad_out, con
   const size_t lds = (size_t)(W.P.W + 1) * 4 + (size_t)(kGuideSize + 1) * 2;
   hipLaunchKernelGGL(k_loss_win<true>, dim3(blocks), dim3(kStressThreads), lds, s, W, grad_out, n_valid, grad,
                      nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_tile_bwd(const SpsWinLaunch& W, const TileLaunch& T, const float* grad_out,
+                                const uint64_t* n_valid, float* grad, uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_tile<true>, dim3(blocks), dim3(kTileThreads), loss_tile_lds_bytes(W.P.W, true), s, W,
+                     T, grad_out, n_valid, grad, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_tile_fwd(const SpsWinLaunch& W, const TileLaunch& T, double* part_f, uint64_t* part_n,
+                                uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_tile<false>, dim3(blocks), dim3(kTileThreads), loss_tile_lds_bytes(W.P.W, false), s,
+                     W, T, nullptr, nullptr, nullptr, part_f, part_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_min_node(const StepRec* rec, const uint64_t* start, uint32_t nseg, uint32_t* out,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_segment_min_node, dim3((nseg + 3) / 4), dim3(256), 0, s, rec, start, nseg, out);
   return hipGetLastError();
 }
 

@@ -800,11 +800,38 @@ def test_gradient_matches_finite_differences():
 # The loss pairs in window-major order (reading R22): the law of the plain
 # loss pairs listed segment by segment
 # ---------------------------------------------------------------------------
+def test_loss_shift_rule():
+    # 2^10-step windows, halved (down to 2^6) while fewer than 16, doubled while more than 32768
+    cases = {0: 6, 1: 6, 1000: 6, 16 * 64: 6, 16 * 64 + 1: 6, 16 * 128: 7, 14416: 9, 16 * 1024: 10, 10**6: 10,
+             32768 * 1024: 10, 32768 * 1024 + 1: 11, 29_016_220: 10, 408_037_251: 14}
+    for S, sh in cases.items():
+        assert O.loss_shift(S) == sh, (S, O.loss_shift(S), sh)
+        n = -(-S // (1 << sh))
+        assert n <= 32768
+        assert sh == 6 or n >= 16 or sh > 10
+
+
+def test_loss_segments_tile_the_paths_along_their_window_boundaries(tiny_oracle):
+    graphs = [tiny_oracle, _disjoint_paths_fixed_point()[0], _small_graph_with_empty_path(),
+              O.Graph.from_synth(synth.linear_path(3000, seed=4))]
+    for g in graphs:
+        start, path = O.loss_segments(g)
+        sh = O.loss_shift(g.S)
+        off = g.path_off.astype(np.int64)
+        assert start[0] == 0 and int(start[-1]) == g.S and np.all(np.diff(start.astype(np.int64)) > 0)
+        for k in range(len(path)):
+            a, b, p = int(start[k]), int(start[k + 1]), int(path[k])
+            assert off[p] <= a < b <= off[p + 1], "a segment lies inside one path"
+            assert a >> sh == (b - 1) >> sh, "a segment lies inside one window"
+            assert a % (1 << sh) == 0 or a == off[p], "segments are maximal"
+            assert b % (1 << sh) == 0 or b == off[p + 1], "segments are maximal"
+
+
 def test_loss_segment_counts_are_the_histogram_of_the_loss_draws():
     # brute force over the plain loss pairs (Philox stream 2 at counter q, word 2 = step)
     g, _ = _disjoint_paths_fixed_point()
     n_pairs, seed, gid, step = 3000, 11, 3, 5
-    start, path = O.sps_segments(g)
+    start, path = O.loss_segments(g)
     brute = np.zeros(len(path), np.int64)
     for q in range(n_pairs):
         r = O.philox([q & 0xFFFFFFFF, q >> 32, step, (2 << 24) | gid], [seed, 0])
@@ -820,7 +847,7 @@ def test_loss_windowed_pairs_follow_the_power_law(tiny_synth, tiny_oracle):
     n_pairs, W = 400_000, 200  # paths of ~1,800 steps: room for hops up to W both ways in the middle
     i, j, f = O.loss_windowed_pairs(g, n_pairs, 0, n_pairs, seed=11, step=3, window=W)
     i, j = i.astype(np.int64), j.astype(np.int64)
-    start, path = O.sps_segments(g)
+    start, path = O.loss_segments(g)
     counts = O.loss_segment_counts(g, n_pairs, seed=11, step=3).astype(np.int64)
     seg_of_slot = np.repeat(np.arange(len(counts)), counts)
     assert np.all((i >= start[seg_of_slot]) & (i < start[seg_of_slot + 1])), "slot step outside its segment"
