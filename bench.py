@@ -660,7 +660,7 @@ def form_kernels() -> dict:
     gr = torch.zeros_like(x)
     one = torch.ones(1, device=x.device)
     for sched, fwd, bwd, order in ((1, "k_stress_fwd", "k_stress_bwd", "plain order"),
-                                   (3, "k_loss_win<fwd>", "k_loss_tile_bwd", "window-major order (R22)")):
+                                   (3, "k_loss_tile<fwd>", "k_loss_tile<bwd>", "window-major order (R22)")):
         P.stress_forward(g, x, n, 0, seed=11, schedule=sched)  # builds the tables (first call only)
         step = iter(range(1, 1 << 20))  # a new optimiser step per forward call, as in training
         ms = ev_time(lambda: P.stress_forward(g, x, n, next(step), seed=11, schedule=sched), reps=20)

@@ -519,6 +519,15 @@ pgsgd_status pgsgd_path_stress_exact(pgsgd_graph *g, const float *coords, double
  * p->zipf_window.  Skipped pairs (single-step path, same slot, d = 0) do not
  * count.  Writes loss_dev[0] (device float32) and n_valid_dev[0] (device
  * uint64).  Async.
+ * p->schedule PLAIN enumerates pair q < n_pairs directly.  WINDOWED (the AUTO
+ * choice) lists the same law of pairs window-major: the steps are cut into
+ * the loss's segments (windows of 2^h steps cut at path boundaries; h = 10,
+ * halved while there would be fewer than 16 windows, not below 6, doubled
+ * while there would be more than 32768); segment g receives as many slots as
+ * plain pair draws fall in it, and slot u draws Philox stream 7 at counter u
+ * (word 2 = step): its step uniform in the segment, its partner and coins as
+ * above.  The two orders give two samples of the same loss, not the same
+ * value.  WINDOWED needs n_pairs < 2^32 (UNSUPPORTED otherwise).
  */
 pgsgd_status pgsgd_stress_forward(pgsgd_graph *g, const pgsgd_params *p, const float *coords, uint64_t n_pairs,
                                   uint32_t step, float *loss_dev, uint64_t *n_valid_dev, void *stream);
@@ -527,6 +536,11 @@ pgsgd_status pgsgd_stress_forward(pgsgd_graph *g, const pgsgd_params *p, const f
  * grad_out_dev[0] * dL/dcoords into grad_coords (device, [2][n_nodes][2]
  * float32) with float32 atomics; dL/dv_a = (2/n_valid)(mag - d)/d^2 (v_a - v_b)/mag,
  * dL/dv_b = -dL/dv_a, zero when mag = 0.  n_valid_dev is the forward's count.
+ * In the WINDOWED order the segments are grouped into tiles of nearby node
+ * ids and most of the adjoint is summed in LDS first; a backward right after
+ * the forward of the same step, n_pairs, seed and graph_id reuses that
+ * forward's segment offsets.  The order of the float32 additions (not their
+ * terms) varies from run to run.
  * Forward and backward read the graph's interleaved working copy of coords,
  * so calls on one graph must be ordered on one stream.  Async.
  */
