@@ -1002,24 +1002,27 @@ pgsgd_status ensure_loss_tiles(pgsgd_graph* g, hipStream_t s) {
   return PGSGD_OK;
 }
 
-// Automatic wave cap of the windowed schedule (see kLocalNodesPerWave).
-uint64_t auto_local_waves(const pgsgd_graph* g) {
+// Automatic wave cap of the windowed schedule (see kLocalNodesPerWave; the
+// all-cooling iterations use kLocalNodesPerWaveCooling).
+uint64_t auto_local_waves(const pgsgd_graph* g, bool cooling = false) {
   const uint32_t sh = window_shift(g->S);
   const double nodes_w = std::min<double>((double)g->n_nodes,
                                           std::ldexp(1.0, (int)sh) * (double)g->n_nodes * g->n_paths / (double)g->S);
-  const uint64_t w = (uint64_t)(nodes_w / (double)kLocalNodesPerWave);
+  const uint64_t w = (uint64_t)(nodes_w / (double)(cooling ? kLocalNodesPerWaveCooling : kLocalNodesPerWave));
   return std::max<uint64_t>(1, std::min(w, auto_inflight_waves(g)));
 }
 
 // Grid of k_layout_local: the in-flight wave cap (params.max_inflight_waves,
 // automatic: auto_local_waves) and occupancy give the waves; 256-thread
 // blocks in a multiple of 8 (one share per XCD), or 64-thread blocks below 32
-// waves.
-pgsgd_status local_grid(pgsgd_graph* g, const pgsgd_params* p, size_t lds, uint32_t* blocks, uint32_t* threads) {
+// waves.  cooling: the grid of the iterations whose terms all have power-law
+// partners (t >= n_iters / 2).
+pgsgd_status local_grid(pgsgd_graph* g, const pgsgd_params* p, size_t lds, uint32_t* blocks, uint32_t* threads,
+                        bool cooling = false) {
   int nb = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, layout_local_kernel(), 256, lds));
   uint64_t waves = (uint64_t)g->n_cu * (uint64_t)std::max(nb, 1) * 4;
-  const uint64_t cap = p->max_inflight_waves ? p->max_inflight_waves : auto_local_waves(g);
+  const uint64_t cap = p->max_inflight_waves ? p->max_inflight_waves : auto_local_waves(g, cooling);
   waves = std::max<uint64_t>(1, std::min(waves, cap));
   if (waves >= 4ull * kXcds) {
     *threads = 256;
@@ -1184,12 +1187,14 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
   const bool reuse = p->reuse_factor > 1 || p->step_reduction > 1;
   const bool windowed = resolve_schedule(p) == PGSGD_SCHEDULE_WINDOWED;
   if (tracing && !windowed) return fail(PGSGD_ERR_INVALID_ARG, "recording through the layout loop needs WINDOWED");
-  uint32_t blocks = 0, threads = 256;
+  uint32_t blocks = 0, threads = 256, blocks_c = 0, threads_c = 256;
   LocalLaunch W{};
   if (windowed && scratch) {
     if ((st = local_plan_scratch(g, p, lds, L, s, scratch, scratch_bytes, &W, &blocks, &threads))) return st;
+    if ((st = local_grid(g, p, lds, &blocks_c, &threads_c, true))) return st;
   } else if (windowed) {
     if ((st = local_plan(g, p, lds, L, s, &W, &blocks, &threads))) return st;
+    if ((st = local_grid(g, p, lds, &blocks_c, &threads_c, true))) return st;
   } else {
     if ((st = layout_grid(g, p, lds, L.n_groups, &blocks, &threads))) return st;
     L.wave_stride = (uint64_t)blocks * (threads / 64);
@@ -1265,13 +1270,15 @@ pgsgd_status layout_impl(pgsgd_graph* g, const pgsgd_params* p, float* coords, f
       if (it + 1 < last) HIP_TRY(count_into(it + 1, k ^ 1u));
       LocalLaunch Wi = Wset[k];
       Wi.L = L;
-      HIP_TRY(local_layout(Wi, blocks, threads, s, iter_ms ? ev[e0 + 1] : nullptr));
+      HIP_TRY(local_layout(Wi, L.cool_all ? blocks_c : blocks, L.cool_all ? threads_c : threads, s,
+                           iter_ms ? ev[e0 + 1] : nullptr));
       HIP_TRY(hipEventRecord(g->ev_layout[k], s));
       set_used[k] = true;
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
     } else if (windowed) {
       W.L = L;
-      HIP_TRY(local_iteration(W, blocks, threads, s, iter_ms ? ev[e0 + 1] : nullptr));
+      HIP_TRY(local_iteration(W, L.cool_all ? blocks_c : blocks, L.cool_all ? threads_c : threads, s,
+                              iter_ms ? ev[e0 + 1] : nullptr));
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 2], s));
     } else {
       if (iter_ms) HIP_TRY(hipEventRecord(ev[e0 + 1], s));
@@ -1911,7 +1918,7 @@ struct pgsgd_batch {
   bool windowed = false;
   std::vector<pgsgd_graph*> graphs;
   std::vector<LocalLaunch> wl;
-  std::vector<uint32_t> wblocks, wthreads;
+  std::vector<uint32_t> wblocks, wthreads, wblocks_c, wthreads_c;  // grids of mixed and all-cooling iterations
   std::vector<std::vector<float>> weta;
   std::vector<std::vector<uint32_t>> branch_graphs;
 
@@ -1992,14 +1999,17 @@ pgsgd_status batch_build_windowed(pgsgd_graph* const* graphs, uint32_t n, const 
     L.g_begin = 0;
     L.g_end = L.n_groups;
     LocalLaunch W;
-    uint32_t blk = 0, thr = 0;
+    uint32_t blk = 0, thr = 0, blk_c = 0, thr_c = 0;
     if ((st = local_plan(g, &q, lds, L, cs, &W, &blk, &thr))) break;
+    if ((st = local_grid(g, &q, lds, &blk_c, &thr_c, true))) break;
     std::vector<float> eta;
     build_schedule(q.n_iters, eta_max_of(&q, g->d_max), q.eta_min, eta);
     b->graphs.push_back(g);
     b->wl.push_back(W);
     b->wblocks.push_back(blk);
     b->wthreads.push_back(thr);
+    b->wblocks_c.push_back(blk_c);
+    b->wthreads_c.push_back(thr_c);
     b->weta.push_back(eta);
     b->coords.push_back(coords[k]);
     b->total_terms += L.n_terms;
@@ -2057,7 +2067,8 @@ pgsgd_status batch_build_windowed(pgsgd_graph* const* graphs, uint32_t n, const 
           W.L.iter = it;
           W.L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
           W.L.eta = b->weta[k][it];
-          e = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
+          e = local_iteration(W, W.L.cool_all ? b->wblocks_c[k] : b->wblocks[k],
+                              W.L.cool_all ? b->wthreads_c[k] : b->wthreads[k], bs[j]);
         }
         if (!e) e = launch_from_work(g->d_work, coords[k], g->n_nodes, g->d_inv, bs[j]);
       }
@@ -2379,7 +2390,9 @@ pgsgd_status autotune_windowed(pgsgd_graph* const* graphs, uint32_t n, const pgs
           W.L.iter = it;
           W.L.cool_all = it >= p->n_iters / 2 ? 1u : 0u;
           W.L.eta = b->weta[k][std::min<uint32_t>(it, (uint32_t)b->weta[k].size() - 1)];
-          if (!r) r = local_iteration(W, b->wblocks[k], b->wthreads[k], bs[j]);
+          if (!r)
+            r = local_iteration(W, W.L.cool_all ? b->wblocks_c[k] : b->wblocks[k],
+                                W.L.cool_all ? b->wthreads_c[k] : b->wthreads[k], bs[j]);
         }
       if (!r) r = hipEventRecord(join[j], bs[j]);
       if (!r) r = hipStreamWaitEvent(s, join[j], 0);

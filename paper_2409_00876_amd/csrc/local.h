@@ -22,6 +22,13 @@ constexpr uint32_t kLocalGrab = 4;          // items a wave takes from its run's
 // With the far-first update order of uniform-partner terms, layout quality on
 // locality-ordered graphs is flat up to this cap.
 constexpr uint64_t kLocalNodesPerWave = 8;
+// In the iterations whose terms all have power-law partners (t >= n_iters /
+// 2) both endpoints of every in-flight term lie in the XCD's active window, so
+// lost Hogwild updates concentrate there: the automatic cap is nodes_w / 32
+// (measured on a 9.9M-node, 90-path graph against the oracle's layout, on the
+// same pairs of Eq. 2 at m = 3000: nodes_w / 8 left 5.3% more stress, nodes_w /
+// 32 2.6%, for 0.6 s more per layout of 3.5 s).
+constexpr uint64_t kLocalNodesPerWaveCooling = 32;
 
 // log2 of the window length for S steps: 2^14, halved while there would be
 // fewer than 16 windows (not below 2^6), doubled while there would be more
