@@ -174,6 +174,93 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
   else apply_update_far_first(L.work, a, b, d, L.eta);
 }
 
+// The draws of item m of a run in an all-cooling iteration (no loads beyond
+// the run's metadata, read at wave-uniform addresses, and the LDS tables):
+// the lane's term, or flags bit 3 when the lane has no slot or no partner.
+__device__ __forceinline__ Term cooling_draw(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
+                                             const uint64_t* __restrict__ xi, uint64_t m, uint32_t& q) {
+  const LayoutLaunch& L = P.L;
+  const uint32_t lane = threadIdx.x & 63u;
+  while (q + 1 < nq && uniform_u64(uload(xi + q + 1)) <= m) q = uniform_u32(q + 1);
+  const uint32_t w = uniform_u32(uload(P.worder + wb + q));
+  const uint64_t wbeg = uniform_u64(uload(P.woff + w));
+  const uint64_t nw = uniform_u64(uload(P.woff + w + 1)) - wbeg;
+  const uint64_t k = (m - uniform_u64(uload(xi + q))) * 64 + lane;
+  const uint64_t s = wbeg + k;
+  const uint32_t slot_c3 = (kStreamWindow << 24) | (L.c3 & 0xFFFFFFu);
+  const Rand4 r = philox10((uint32_t)s, (uint32_t)(s >> 32), L.iter, slot_c3, L.k0, L.k1);
+  Term T;
+  T.j = 0;
+  if (k >= nw) {
+    T.i = 0;
+    T.flags = 8u;
+    return T;
+  }
+  const uint64_t wstart = (uint64_t)w << P.win_shift;
+  const uint64_t wlen = min((uint64_t)1 << P.win_shift, L.S - wstart);
+  T.i = wstart + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), wlen);
+  const uint32_t wp = uniform_u32(uload(P.wpath + w));
+  const uint32_t p = (wp >> 31) ? find_path(V.off, L.path_top, T.i) : wp;
+  const uint64_t start = V.off[p];
+  const uint64_t len = V.off[p + 1] - start;
+  const bool ok = partner_power_law(T.i, start, len, r.r2, r.r3, V.zipf, V.guide, L.W, T.j);
+  T.flags = (r.r3 & 3u) | 4u | ((ok ? 0u : 1u) << 3);
+  return T;
+}
+
+// A run of an all-cooling iteration, two items deep: the step records of
+// item m are requested, then item m + 1 is drawn (Philox, path, power-law
+// partner: arithmetic and LDS only) while they arrive, then item m is updated.
+// Only the read-only records and draws run ahead; the coordinates of item m
+// are read and written as in local_item, so no more updates are in flight.
+// The slots and their terms are those of local_item.
+__device__ __forceinline__ void local_run_cooling(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
+                                                  const uint64_t* __restrict__ xi_in, uint64_t n_items,
+                                                  unsigned long long* ctr) {
+  const LayoutLaunch& L = P.L;
+  const uint32_t lane = threadIdx.x & 63u;
+  // the run's prefix row at a wave-uniform address: its reads are scalar loads, which the
+  // vector-memory waits for the records below do not include
+  const uint64_t* __restrict__ xi = reinterpret_cast<const uint64_t*>(uniform_u64(reinterpret_cast<uint64_t>(xi_in)));
+  auto grab = [&](uint64_t& m, uint64_t& m_end) -> bool {
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(ctr, (unsigned long long)P.grab);
+    m = ((uint64_t)uniform_u32((uint32_t)(base >> 32)) << 32) | uniform_u32((uint32_t)base);
+    if (m >= n_items) return false;
+    m_end = min(m + P.grab, n_items);
+    return true;
+  };
+  uint32_t q = 0;
+  uint64_t m = 0, m_end = 0;
+  if (!grab(m, m_end)) return;
+  Term cur = cooling_draw(P, V, wb, nq, xi, m, q);
+  for (;;) {
+    // the next item's index first: a grab waits for its atomic before this item's loads are issued
+    uint64_t mn = m + 1, mn_end = m_end;
+    const bool more = mn < m_end || grab(mn, mn_end);
+    const bool live = !(cur.flags & 8u);
+    StepRec si, sj;
+    if (live) {
+      si = load_rec(L.rec, cur.i);
+      sj = load_rec(L.rec, cur.j);
+    }
+    Term nxt;
+    nxt.flags = 8u;
+    if (more) nxt = cooling_draw(P, V, wb, nq, xi, mn, q);
+    if (live) {
+      const uint32_t ei = cur.flags & 1u, ej = (cur.flags >> 1) & 1u;
+      const uint64_t a = 2ull * (si.node_rev & kNodeMask) + ei;
+      const uint64_t b = 2ull * (sj.node_rev & kNodeMask) + ej;
+      const int64_t dd = endpoint_pos(si, ei) - endpoint_pos(sj, ej);
+      if (a != b && dd != 0) apply_update(L.work, a, b, (float)(dd < 0 ? -dd : dd), L.eta);
+    }
+    if (!more) break;
+    cur = nxt;
+    m = mn;
+    m_end = mn_end;
+  }
+}
+
 __device__ __forceinline__ float2 shfl_f2(float2 v, int src) {
   return make_float2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
@@ -308,6 +395,10 @@ __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
     const uint64_t* __restrict__ xi = P.xitem + (size_t)run * P.xstride;
     const uint64_t n_items = uniform_u64(uload(xi + nq));
     unsigned long long* ctr = reinterpret_cast<unsigned long long*>(P.queue + (size_t)run * 16);
+    if (L.cool_all && L.drf <= 1 && !L.trace_f && !L.apply_mask) {
+      local_run_cooling(P, V, wb, nq, xi, n_items, ctr);
+      continue;
+    }
     uint32_t q = 0;
     for (uint64_t m = 0, m_end = 0;; ++m) {
       if (m >= m_end) {
