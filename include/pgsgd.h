@@ -285,8 +285,10 @@ enum { PGSGD_FLAG_COUNT_AHEAD = 1, PGSGD_FLAG_COUNT_IN_ORDER = 2 };
  *            pieces, XCD x takes piece x of every path), a window at a time
  *            per XCD, so its step records and the coordinates of the nodes
  *            it visits stay in the XCD's L2.  max_inflight_waves caps the
- *            waves (automatic: about nodes_w / 8, nodes_w = 2^h * n_nodes *
- *            n_paths / S the nodes a window visits, at most the PLAIN cap).
+ *            waves in every iteration (automatic: about nodes_w / 8, nodes_w =
+ *            2^h * n_nodes * n_paths / S the nodes a window visits, and
+ *            nodes_w / 32 in the iterations t >= n_iters / 2, whose partners
+ *            all lie in the active window; both at most the PLAIN cap).
  *            Uniform-partner updates read the partner first and the window-
  *            local endpoint after it arrived, which keeps the window in which
  *            a concurrent update of a local node can be lost short.  Scratch: a few
