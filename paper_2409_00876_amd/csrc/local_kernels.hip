@@ -176,9 +176,11 @@ __device__ __forceinline__ void local_item(const LocalLaunch& P, const LdsView& 
 
 // The draws of item m of a run in an all-cooling iteration (no loads beyond
 // the run's metadata, read at wave-uniform addresses, and the LDS tables):
-// the lane's term, or flags bit 3 when the lane has no slot or no partner.
+// the lane's term, or flags bit 3 when the lane has no slot or no partner;
+// slot = the lane's global slot, ~0 when it has none.
 __device__ __forceinline__ Term cooling_draw(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
-                                             const uint64_t* __restrict__ xi, uint64_t m, uint32_t& q) {
+                                             const uint64_t* __restrict__ xi, uint64_t m, uint32_t& q,
+                                             uint64_t& slot) {
   const LayoutLaunch& L = P.L;
   const uint32_t lane = threadIdx.x & 63u;
   while (q + 1 < nq && uniform_u64(uload(xi + q + 1)) <= m) q = uniform_u32(q + 1);
@@ -191,11 +193,13 @@ __device__ __forceinline__ Term cooling_draw(const LocalLaunch& P, const LdsView
   const Rand4 r = philox10((uint32_t)s, (uint32_t)(s >> 32), L.iter, slot_c3, L.k0, L.k1);
   Term T;
   T.j = 0;
+  slot = ~0ull;
   if (k >= nw) {
     T.i = 0;
     T.flags = 8u;
     return T;
   }
+  slot = s;
   const uint64_t wstart = (uint64_t)w << P.win_shift;
   const uint64_t wlen = min((uint64_t)1 << P.win_shift, L.S - wstart);
   T.i = wstart + mulhi64((uint64_t)r.r0 | ((uint64_t)r.r1 << 32), wlen);
@@ -211,9 +215,11 @@ __device__ __forceinline__ Term cooling_draw(const LocalLaunch& P, const LdsView
 // A run of an all-cooling iteration, two items deep: the step records of
 // item m are requested, then item m + 1 is drawn (Philox, path, power-law
 // partner: arithmetic and LDS only) while they arrive, then item m is updated.
-// Only the read-only records and draws run ahead; the coordinates of item m
-// are read and written as in local_item, so no more updates are in flight.
-// The slots and their terms are those of local_item.
+// Only the draw runs ahead; the coordinates of item m are read and written as
+// in local_item, so no more updates are in flight.  The slots and their terms
+// are those of local_item; with the recording hook set (trace_f) the terms of
+// the slots [t_begin, t_end) are recorded instead of applied, as local_item
+// records them.
 __device__ __forceinline__ void local_run_cooling(const LocalLaunch& P, const LdsView& V, uint32_t wb, uint32_t nq,
                                                   const uint64_t* __restrict__ xi_in, uint64_t n_items,
                                                   unsigned long long* ctr) {
@@ -233,7 +239,25 @@ __device__ __forceinline__ void local_run_cooling(const LocalLaunch& P, const Ld
   uint32_t q = 0;
   uint64_t m = 0, m_end = 0;
   if (!grab(m, m_end)) return;
-  Term cur = cooling_draw(P, V, wb, nq, xi, m, q);
+  uint64_t slot;
+  if (L.trace_f) {  // parity hook: the drawn terms of the slots [t_begin, t_end), nothing applied
+    for (;;) {
+      Term T = cooling_draw(P, V, wb, nq, xi, m, q, slot);
+      if (slot >= L.t_begin && slot < L.t_end) {
+        if (!(T.flags & 8u)) {
+          uint64_t a, b;
+          float d;
+          if (!resolve_term(L.rec, T, a, b, d)) T.flags |= 8u;
+        }
+        const uint64_t o = slot - L.t_begin;
+        L.trace_i[o] = T.i;
+        L.trace_j[o] = T.j;
+        L.trace_f[o] = (uint8_t)T.flags;
+      }
+      if (++m >= m_end && !grab(m, m_end)) return;
+    }
+  }
+  Term cur = cooling_draw(P, V, wb, nq, xi, m, q, slot);
   for (;;) {
     // the next item's index first: a grab waits for its atomic before this item's loads are issued
     uint64_t mn = m + 1, mn_end = m_end;
@@ -246,7 +270,7 @@ __device__ __forceinline__ void local_run_cooling(const LocalLaunch& P, const Ld
     }
     Term nxt;
     nxt.flags = 8u;
-    if (more) nxt = cooling_draw(P, V, wb, nq, xi, mn, q);
+    if (more) nxt = cooling_draw(P, V, wb, nq, xi, mn, q, slot);
     if (live) {
       const uint32_t ei = cur.flags & 1u, ej = (cur.flags >> 1) & 1u;
       const uint64_t a = 2ull * (si.node_rev & kNodeMask) + ei;
@@ -395,7 +419,7 @@ __global__ __launch_bounds__(256) void k_layout_local(LocalLaunch P) {
     const uint64_t* __restrict__ xi = P.xitem + (size_t)run * P.xstride;
     const uint64_t n_items = uniform_u64(uload(xi + nq));
     unsigned long long* ctr = reinterpret_cast<unsigned long long*>(P.queue + (size_t)run * 16);
-    if (L.cool_all && L.drf <= 1 && !L.trace_f && !L.apply_mask) {
+    if (L.cool_all && L.drf <= 1 && !L.apply_mask) {
       local_run_cooling(P, V, wb, nq, xi, n_items, ctr);
       continue;
     }
