@@ -704,6 +704,10 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--paired-m", type=int, default=1000,
                     help="pairs per step of the paired quality comparison against the plain-order layout")
+    ap.add_argument("--oracle-layout", default=None, metavar="PATH",
+                    help="the oracle's final coordinates of this workload and seed (raw float32, as "
+                         "tests/golden/make_golden.py --save-layout writes them): adds the paired ratio against "
+                         "them at --paired-m pairs per step")
     ap.add_argument("--summarize", nargs="+", metavar="PATH",
                     help="TRACE_DIR FETCH_CSV WRITE_CSV TCC_CSV [RDREQ_CSV]: write the committed counter summaries "
                          "from rocprofv3 outputs (no GPU)")
@@ -803,8 +807,13 @@ def main():
     # the same pairs of Eq. 2 on this layout and on one made in the paper's processing order (plain schedule, same
     # seed and initial layout): the heavy tail is shared by both, so the ratio of the two means resolves a few
     # percent where two independent estimates cannot
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    note(f"timed {a.steps} steps: {wall / a.steps * 1e3:.1f} ms per step")
     paired = None
     if params.schedule != SCHEDULES["plain"]:
+        note("paired quality against a plain-order layout")
         ref = g.new_coords()
         P.init_coords(g, ref)
         ts = time.perf_counter()
@@ -823,6 +832,27 @@ def main():
                   "mean_this": cmp["mean_a"], "mean_plain": cmp["mean_b"],
                   "plain_layout_seconds": plain_s, "seconds": time.perf_counter() - ts}
         del ref
+    paired_oracle = None
+    if a.oracle_layout:
+        import numpy as np
+        with open(a.oracle_layout + ".json") as f:
+            meta = json.load(f)
+        if meta.get("config") != a.workload or meta.get("layout_seed") != params.seed:
+            raise SystemExit(f"{a.oracle_layout}: a layout of {meta.get('config')} with seed {meta.get('layout_seed')}, "
+                             f"not of {a.workload} with seed {params.seed}")
+        ora = np.fromfile(a.oracle_layout, dtype=np.float32)
+        if ora.size != 4 * g.n_nodes:
+            raise SystemExit(f"{a.oracle_layout}: {ora.size} floats, the graph needs {4 * g.n_nodes}")
+        co = torch.from_numpy(ora).to(dev)
+        note("paired quality against the oracle's layout")
+        ts = time.perf_counter()
+        cmp = P.path_stress_compare(g, coords, co, a.paired_m, 7, pairs="uniform_windowed")
+        paired_oracle = {"against": f"the oracle's layout ({meta.get('oracle_threads')} threads, "
+                                    f"{meta.get('applied_updates')} applied updates)", "pairs_per_step": a.paired_m,
+                         "pair_order": "window-major", "ratio": cmp["ratio"],
+                         "ci95": [cmp["ratio_ci_lo"], cmp["ratio_ci_hi"]], "mean_this": cmp["mean_a"],
+                         "mean_oracle": cmp["mean_b"], "seconds": time.perf_counter() - ts}
+        del co
     # a stored oracle layout of this workload and seed (sequential run preferred, else the Hogwild mode)
     oracle_sps = None
     import glob
@@ -870,9 +900,10 @@ def main():
                 "oracle_mode": oracle_sps.get("mode") if oracle_sps else None,
                 "ratio_to_oracle_resolution": "unpaired: the two m = 10 estimates carry independent heavy tails "
                                               "(CI half-widths of 15-20% each), so this ratio cannot resolve 3%; "
-                                              "a paired ratio needs the oracle's coordinates, which are not "
-                                              "shipped with the benchmark",
-                "paired": paired},
+                                              "a paired ratio needs the oracle's coordinates (159 MB, not shipped "
+                                              "with the benchmark; pass them with --oracle-layout)",
+                "paired": paired,
+                "paired_vs_oracle": paired_oracle},
     }
     if traffic is not None:
         rec["roofline"]["traffic_frac"] = traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
